@@ -1,0 +1,79 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers: it holds none of the method's
+arithmetic (no kernels, no tree, no expansion), so that the CPU oracle and
+the HIP path can both consume the same inputs without sharing code.
+
+Every generator uses ``numpy.random.default_rng(seed)`` and returns float64
+arrays in row-major layout (points: n x d, right-hand sides: n x nrhs).
+
+The workloads stand in for the paper's synthetic runs (points uniform in a
+box, Section 5.1) and for its real-data experiments, whose datasets are not
+used here.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_cube(n: int, d: int, seed: int) -> np.ndarray:
+    """n points i.i.d. uniform in [0, 1]^d."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, size=(n, d))
+
+
+def gaussian_mixture(n: int, d: int, ncomp: int, std: float, seed: int) -> np.ndarray:
+    """n points from an equal-weight isotropic Gaussian mixture.
+
+    Component means are uniform in [0, 1]^d; each point picks a component
+    uniformly at random and adds N(0, std^2 I) noise.
+    """
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(0.0, 1.0, size=(ncomp, d))
+    comp = rng.integers(0, ncomp, size=n)
+    return means[comp] + std * rng.standard_normal(size=(n, d))
+
+
+def normal_rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
+    """Right-hand sides x ~ N(0, 1), shape (n, nrhs)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=(n, nrhs))
+
+
+def subsample(n: int, k: int, seed: int) -> np.ndarray:
+    """k distinct indices out of range(n), sorted (without replacement)."""
+    rng = np.random.default_rng(seed)
+    k = min(k, n)
+    return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int64)
+
+
+def clustered_duplicates(n: int, d: int, ndistinct: int, seed: int) -> np.ndarray:
+    """n points drawn (with repetition) from ndistinct uniform sites.
+
+    Exercises coincident points: many exact duplicates of each site.
+    """
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(0.0, 1.0, size=(ndistinct, d))
+    return sites[rng.integers(0, ndistinct, size=n)]
+
+
+# Named workloads: (points recipe, rhs recipe). Sizes follow the problem
+# statements; seeds are fixed so every consumer sees identical inputs.
+WORKLOADS = {
+    # small correctness case: Gaussian kernel, length scale 0.1, leaf 128, p=4
+    "cube3_n2k_gauss": dict(n=2000, d=3, pts_seed=1001, rhs_seed=2001, nrhs=1,
+                            kernel="gaussian", lengthscale=0.1, leaf=128, order=4),
+    # headline case: one million uniform points in the unit cube, leaf 256, p=6
+    "cube3_n1m_matern32": dict(n=1_000_000, d=3, pts_seed=1002, rhs_seed=2002, nrhs=1,
+                               kernel="matern32", lengthscale=0.05, leaf=256, order=6),
+    "cube3_n1m_laplace": dict(n=1_000_000, d=3, pts_seed=1002, rhs_seed=2002, nrhs=1,
+                              kernel="laplace", lengthscale=1.0, leaf=256, order=6),
+}
+
+
+def make_points(spec: dict) -> np.ndarray:
+    return uniform_cube(spec["n"], spec["d"], spec["pts_seed"])
+
+
+def make_rhs(spec: dict) -> np.ndarray:
+    return normal_rhs(spec["n"], spec["nrhs"], spec["rhs_seed"])
