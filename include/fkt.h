@@ -1,0 +1,191 @@
+/*
+ * fkt.h -- C ABI of the MI355X Fast Kernel Transform library (libfkt.so).
+ *
+ * The library multiplies an isotropic kernel matrix by vectors,
+ *     z_i = sum_j K(|r_i - r_j|) x_j                       (paper eq. nbody),
+ * in O(N log N) work with the Fast Kernel Transform (Ryan, Ament, Gomes,
+ * Damle, arXiv 2106.04487): a binary space-partition tree (Sec. 3.1), far
+ * sets by the distance criterion (eq. accparam), dense near-field blocks
+ * and a far field compressed through the truncated expansion of Theorem 3.1
+ * (eq. finaltrunc) as source-to-multipole moments followed by
+ * multipole-to-target evaluation (Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *   - Nothing throws across this boundary; every call returns a status code
+ *     and fkt_last_error() gives a message for the calling thread.
+ *   - Arrays are row-major. "host" pointers are read on the CPU during the
+ *     call; "device" pointers are HIP device memory on the plan's device.
+ *   - Device work is enqueued on the plan's stream and is asynchronous: the
+ *     caller synchronises the stream before reading results.
+ *   - The caller owns every array it passes; the plan copies what it keeps.
+ *   - A plan is immutable after fkt_plan. Calls on one plan from several
+ *     host threads must use the same stream or be serialised by the caller
+ *     (the plan owns one set of work buffers).
+ */
+#ifndef FKT_H
+#define FKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fkt_plan_s *fkt_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+    FKT_OK = 0,
+    FKT_EINVAL = 1,        /* invalid argument (message says which)            */
+    FKT_ENOMEM = 2,        /* host or device allocation failed                 */
+    FKT_EDEVICE = 3,       /* HIP runtime error, or no device for this plan    */
+    FKT_EUNSUPPORTED = 4,  /* valid but not built: dimension/order/kind combo  */
+    FKT_ENOTCONV = 5       /* iterative solve hit maxit before rtol            */
+} fkt_status;
+
+/* Isotropic kernels K(r), r = |r_i - r_j|; l = lengthscale, s2 = variance. */
+typedef enum {
+    FKT_GAUSSIAN = 0,    /* s2 exp(-r^2 / (2 l^2))                            */
+    FKT_EXPONENTIAL = 1, /* s2 exp(-r / l)              (Matern nu = 1/2)      */
+    FKT_MATERN32 = 2,    /* s2 (1 + a r) exp(-a r),      a = sqrt(3) / l       */
+    FKT_MATERN52 = 3,    /* s2 (1 + a r + a^2 r^2 / 3) exp(-a r), a = sqrt(5)/l */
+    FKT_RATQUAD = 4,     /* s2 (1 + r^2 / (2 alpha l^2))^(-alpha)             */
+    FKT_CAUCHY = 5,      /* s2 / (1 + r^2 / l^2)                              */
+    FKT_LAPLACE = 6      /* s2 / r, with K(0) taken as 0 (no self term)       */
+} fkt_kernel_kind;
+
+typedef struct {
+    fkt_kernel_kind kind;
+    double lengthscale; /* l > 0 (ignored by FKT_LAPLACE)                     */
+    double alpha;       /* rational-quadratic shape, > 0 (FKT_RATQUAD only)   */
+    double variance;    /* s2 > 0                                             */
+} fkt_kernel;
+
+typedef enum {
+    FKT_F64 = 0, /* x, y are double; all device arithmetic in FP64            */
+    FKT_F32 = 1  /* x, y are float; near and far field in FP32, tree geometry,
+                    node centres and expansion coefficients kept in FP64      */
+} fkt_precision;
+
+typedef struct {
+    double theta;       /* distance criterion of eq. (accparam), 0 < theta < 1 */
+    fkt_precision prec;
+    int max_depth;      /* tree depth cap (guards duplicate points), 1..60    */
+    int device;         /* HIP device ordinal; -1 builds a host-only plan
+                           (tree, lists, tables; fkt_mvm then returns
+                           FKT_EDEVICE)                                        */
+    void *stream;       /* hipStream_t for all device work; NULL = null stream */
+    int profile;        /* nonzero: fkt_mvm records HIP events between its
+                           stages (see fkt_plan_stage_times)                   */
+} fkt_options;
+
+/* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0. */
+void fkt_default_options(fkt_options *opt);
+
+/*
+ * fkt_plan -- build the tree, the near/far partition and the coefficient
+ * tables, and upload them to the device (paper Sec. 3.1-3.2, Algorithm 1
+ * first line; coefficient tables of Appendix A.2).
+ *   points    host, n x d FP64, row-major. Copied; not retained.
+ *   n         number of points, >= 1 (sources and targets are the same set).
+ *   d         dimension, 3 <= d <= 5 (d = 2 needs the alpha = 0 Gegenbauer
+ *             limit and is FKT_EUNSUPPORTED).
+ *   k         kernel and its parameters.
+ *   leaf_size maximum points per leaf, >= 1 (a node with more is split).
+ *   order     truncation order p of eq. (finaltrunc): radial powers j <= p,
+ *             harmonic degrees k <= p; expansion rank C(p+d, d).
+ *             Built: 0 <= p <= 10 for d = 3, 0 <= p <= 8 for d = 4, 5.
+ *   opt       NULL for defaults.
+ *   out       receives the plan on FKT_OK, NULL otherwise.
+ * Errors: FKT_EINVAL (bad n, d, leaf_size, order, theta, kernel parameters,
+ * non-finite coordinates), FKT_EUNSUPPORTED, FKT_ENOMEM, FKT_EDEVICE.
+ */
+fkt_status fkt_plan(const double *points, int64_t n, int d, fkt_kernel k, int leaf_size, int order,
+                    const fkt_options *opt, fkt_plan_t *out);
+
+/*
+ * fkt_mvm -- y = K~ x with K~ the FKT approximation of the kernel matrix
+ * (Algorithm 1): near field exact, far field through the truncated
+ * expansion about each far node's centre.
+ *   x, y      device, n x nrhs row-major, element type double (FKT_F64) or
+ *             float (FKT_F32). Must not overlap. y is fully overwritten.
+ *   nrhs      number of right-hand sides, 1 <= nrhs <= 64.
+ * Enqueued on the plan's stream; returns before the result is ready.
+ * Errors: FKT_EINVAL (NULL/overlapping pointers, nrhs), FKT_EDEVICE (host-only
+ * plan, HIP failure), FKT_ENOMEM (work buffers grow on first use of a larger
+ * nrhs). On error y is unspecified.
+ */
+fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
+
+/*
+ * fkt_cg_solve -- solve (K~ + sigma2 I) x = b by conjugate gradients, each
+ * iteration one fkt_mvm. Used for the Gaussian-process posterior mean
+ * (paper eq. gp_posterior), whose inference runs through MVMs only.
+ *   sigma2    noise variance, >= 0.
+ *   b         device, n x nrhs (plan precision element type).
+ *   x         device, n x nrhs; on entry the initial guess, on exit the
+ *             solution (the last iterate if not converged).
+ *   rtol      stop when ||b - A x||_2 <= rtol ||b||_2 for every column.
+ *   maxit     iteration cap, >= 1.
+ *   precond   0 none, 1 block-Jacobi (per-leaf dense Cholesky of
+ *             K_ll + sigma2 I).
+ *   iters     host, receives the iteration count (may be NULL).
+ *   relres    host, receives max over columns of the final relative
+ *             residual (may be NULL).
+ * Synchronises the plan's stream (it reads residual norms on the host).
+ * Errors: as fkt_mvm, FKT_EUNSUPPORTED for an unknown precond, FKT_ENOTCONV
+ * when maxit is reached (x holds the last iterate).
+ */
+fkt_status fkt_cg_solve(fkt_plan_t p, double sigma2, const void *b, void *x, int nrhs, double rtol, int maxit,
+                        int precond, int *iters, double *relres);
+
+/* Release the plan and its device memory (NULL is a no-op). Waits for the
+ * plan's stream first. */
+void fkt_destroy(fkt_plan_t p);
+
+/* Message for the last failing call on this thread ("" if none). The
+ * pointer stays valid until the next call on the same thread. */
+const char *fkt_last_error(void);
+
+/* Plan statistics (host-side, available for host-only plans too). */
+typedef struct {
+    int64_t n, nnodes, nleaves, depth;
+    int64_t rank;             /* expansion terms per node, C(p+d, d)           */
+    int64_t nblocks;          /* 64-target blocks                              */
+    int64_t far_nodes;        /* nodes with a non-empty far set                */
+    int64_t near_entries;     /* (target block, source leaf) list entries      */
+    int64_t far_entries;      /* (target block, far node) list entries         */
+    int64_t near_pairs;       /* sum_l |N_l| |l|: kernel evaluations           */
+    int64_t near_lane_pairs;  /* evaluations incl. masked-off lanes            */
+    int64_t far_pairs;        /* sum_b |F_b|: (target, node) expansions        */
+    int64_t far_lane_pairs;   /* expansions incl. masked-off lanes             */
+    int64_t s2m_terms;        /* sum_b |b| over nodes with far sets            */
+    double plan_seconds;      /* host wall time of fkt_plan                    */
+} fkt_plan_stats;
+
+fkt_status fkt_plan_info(fkt_plan_t p, fkt_plan_stats *s);
+
+/* perm[i] = original index of the point at tree position i (host, n int64). */
+fkt_status fkt_plan_perm(fkt_plan_t p, int64_t *perm);
+
+/* Per target (original order, host arrays of n int64, any may be NULL):
+ * far nodes, far source points, near leaves, near source points. */
+fkt_status fkt_plan_target_counts(fkt_plan_t p, int64_t *far_nodes, int64_t *far_points, int64_t *near_leaves,
+                                  int64_t *near_points);
+
+/*
+ * Device time of fkt_mvm's stages, summed over the calls made since the plan
+ * was built with opt.profile != 0 (or since the last reset): ms[0] gather into
+ * tree order, ms[1] source-to-multipole moments (incl. partial sums), ms[2]
+ * multipole-to-target far field, ms[3] near field (incl. the scatter to the
+ * caller's order). Times come from HIP events recorded on the plan's stream
+ * around each stage. Synchronises those events. calls (may be NULL)
+ * receives the number of column passes timed. reset != 0 clears the record.
+ * Errors: FKT_EINVAL (NULL, plan built without profile), FKT_EDEVICE.
+ */
+fkt_status fkt_plan_stage_times(fkt_plan_t p, double *ms, int64_t *calls, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKT_H */

@@ -1,0 +1,231 @@
+"""Python binding of libfkt.so, the MI355X Fast Kernel Transform library.
+
+Argument marshalling only: every step of the MVM runs in the library's HIP
+kernels. PyTorch supplies device memory and streams. There is no CPU
+fallback: if ``libfkt.so`` is missing the import of this module fails.
+
+Entry points mirror the C ABI (include/fkt.h):
+    fkt_plan(points, kernel, leaf_size, order, ...) -> Plan
+    fkt_mvm(plan, x, y=None) -> y
+    fkt_cg_solve(plan, sigma2, b, x0=None, ...) -> (x, iters, relres)
+    fkt_destroy(plan)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfkt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2106_04487_amd/build.py` "
+                      "(there is no fallback implementation)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+KERNELS = {"gaussian": 0, "exponential": 1, "matern32": 2, "matern52": 3,
+           "ratquad": 4, "cauchy": 5, "laplace": 6}
+PRECISIONS = {"f64": 0, "f32": 1}
+STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "FKT_EUNSUPPORTED",
+          5: "FKT_ENOTCONV"}
+
+EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_destroy", "fkt_last_error",
+            "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times"]
+
+
+class FktError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("lengthscale", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("variance", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int)]
+
+
+_STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
+                "near_pairs", "near_lane_pairs", "far_pairs", "far_lane_pairs", "s2m_terms"]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in _STAT_FIELDS] + [("plan_seconds", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_lib.fkt_default_options.argtypes = [ctypes.POINTER(_Options)]
+_lib.fkt_plan.restype = ctypes.c_int
+_lib.fkt_plan.argtypes = [_P, ctypes.c_int64, ctypes.c_int, _Kernel, ctypes.c_int, ctypes.c_int,
+                          ctypes.POINTER(_Options), ctypes.POINTER(_P)]
+_lib.fkt_mvm.restype = ctypes.c_int
+_lib.fkt_mvm.argtypes = [_P, _P, _P, ctypes.c_int]
+_lib.fkt_cg_solve.restype = ctypes.c_int
+_lib.fkt_cg_solve.argtypes = [_P, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+_lib.fkt_destroy.argtypes = [_P]
+_lib.fkt_last_error.restype = ctypes.c_char_p
+_lib.fkt_plan_info.restype = ctypes.c_int
+_lib.fkt_plan_info.argtypes = [_P, ctypes.POINTER(_Stats)]
+_lib.fkt_plan_perm.restype = ctypes.c_int
+_lib.fkt_plan_perm.argtypes = [_P, _P]
+_lib.fkt_plan_target_counts.restype = ctypes.c_int
+_lib.fkt_plan_target_counts.argtypes = [_P, _P, _P, _P, _P]
+_lib.fkt_plan_stage_times.restype = ctypes.c_int
+_lib.fkt_plan_stage_times.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+
+
+def _check(status: int):
+    if status != 0:
+        raise FktError(status, _lib.fkt_last_error().decode())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream or None
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return getattr(stream, "cuda_stream", None) or None
+
+
+class Plan:
+    """An FKT plan: tree, near/far lists and tables, resident on one device."""
+
+    def __init__(self, handle, n, d, prec, device, stream):
+        self._h = handle
+        self.n, self.d, self.prec, self.device, self.stream = n, d, prec, device, stream
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    @property
+    def np_dtype(self):
+        return np.float32 if self.prec == "f32" else np.float64
+
+    def info(self) -> dict:
+        s = _Stats()
+        _check(_lib.fkt_plan_info(self.handle, ctypes.byref(s)))
+        out = {f: int(getattr(s, f)) for f in _STAT_FIELDS}
+        out["plan_seconds"] = float(s.plan_seconds)
+        return out
+
+    def perm(self) -> np.ndarray:
+        p = np.zeros(self.n, dtype=np.int64)
+        _check(_lib.fkt_plan_perm(self.handle, p.ctypes.data))
+        return p
+
+    def target_counts(self):
+        outs = [np.zeros(self.n, dtype=np.int64) for _ in range(4)]
+        _check(_lib.fkt_plan_target_counts(self.handle, *[o.ctypes.data for o in outs]))
+        return tuple(outs)
+
+    def stage_times(self, reset: bool = False):
+        """(ms per stage summed over profiled passes, passes): stages are
+        gather, s2m, m2t, near. Needs a plan built with profile=True."""
+        ms = np.zeros(4)
+        calls = ctypes.c_int64(0)
+        _check(_lib.fkt_plan_stage_times(self.handle, ms.ctypes.data, ctypes.byref(calls), int(reset)))
+        return dict(zip(("gather", "s2m", "m2t", "near"), ms.tolist())), calls.value
+
+    def close(self):
+        if self._h:
+            _lib.fkt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
+             variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
+             device: int | None = 0, stream=None, profile: bool = False) -> Plan:
+    """Build a plan. points: (n, d) array-like (host or device; copied to host
+    FP64 for the tree build). device=None builds a host-only plan."""
+    if hasattr(points, "detach"):
+        points = points.detach().to("cpu").double().numpy()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    if pts.ndim != 2:
+        raise ValueError("points must be (n, d)")
+    n, d = pts.shape
+    if kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}; one of {sorted(KERNELS)}")
+    if prec not in PRECISIONS:
+        raise ValueError(f"prec must be one of {sorted(PRECISIONS)}")
+    k = _Kernel(KERNELS[kernel], float(lengthscale), float(alpha), float(variance))
+    opt = _Options()
+    _lib.fkt_default_options(ctypes.byref(opt))
+    opt.theta = float(theta)
+    opt.prec = PRECISIONS[prec]
+    opt.max_depth = int(max_depth)
+    opt.device = -1 if device is None else int(device)
+    sh = None if device is None else _stream_handle(stream)
+    opt.stream = sh
+    opt.profile = int(bool(profile))
+    h = _P()
+    _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
+    return Plan(h, n, d, prec, device, sh)
+
+
+def _device_matrix(plan: Plan, t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    want = torch.float32 if plan.prec == "f32" else torch.float64
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want} for a {plan.prec} plan")
+    if t.shape[0] != plan.n or t.dim() not in (1, 2):
+        raise ValueError(f"{name} must be (n,) or (n, nrhs) with n = {plan.n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def fkt_mvm(plan: Plan, x, y=None):
+    """y = K~ x on the plan's stream (asynchronous). x: (n,) or (n, nrhs)."""
+    import torch
+    x = _device_matrix(plan, x, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    y = _device_matrix(plan, y, "y")
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    _check(_lib.fkt_mvm(plan.handle, x.data_ptr(), y.data_ptr(), nrhs))
+    return y
+
+
+def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,
+                 precond: int = 0):
+    """Solve (K~ + sigma2 I) x = b by CG. Returns (x, iters, relres); raises
+    FktError(FKT_ENOTCONV) if maxit is reached."""
+    import torch
+    b = _device_matrix(plan, b, "b")
+    x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0").clone()
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    _check(_lib.fkt_cg_solve(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol), int(maxit),
+                             int(precond), ctypes.byref(it), ctypes.byref(rr)))
+    return x, it.value, rr.value
+
+
+def fkt_destroy(plan: Plan):
+    plan.close()
+
+
+def last_error() -> str:
+    return _lib.fkt_last_error().decode()

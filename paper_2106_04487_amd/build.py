@@ -1,0 +1,69 @@
+"""Build libfkt.so in-tree for gfx950 (hipcc for device code, g++ for the
+pure host plan builder).
+
+Usage: python paper_2106_04487_amd/build.py [--jobs N]   (run as a script: importing
+the package would first load the library being rebuilt)
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libfkt.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+# Packed FP32 instructions are kept out of the device code on purpose.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include")]
+
+
+def _jobs():
+    return [
+        # the FP64 far-test predicate must not be contracted into FMAs
+        (["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-c",
+          os.path.join(CSRC, "plan_host.cpp"), "-o", os.path.join(BUILD, "plan_host.o")]),
+        ([HIPCC, *COMMON, "-c", os.path.join(CSRC, "fkt_api.cpp"), "-o", os.path.join(BUILD, "fkt_api.o")]),
+        ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"),
+          "-o", os.path.join(BUILD, "kernels.o")]),
+        ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "cg.hip"),
+          "-o", os.path.join(BUILD, "cg.o")]),
+    ]
+
+
+def build(jobs: int = 4, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+
+    def run(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+        return r
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(run, _jobs()))
+    tmp = LIB + ".tmp"
+    run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}",
+         os.path.join(BUILD, "plan_host.o"), os.path.join(BUILD, "fkt_api.o"),
+         os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "cg.o"),
+         "-o", tmp, "-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("-v", action="store_true")
+    a = ap.parse_args()
+    print(build(a.jobs, a.v))
+    sys.exit(0)

@@ -1,0 +1,217 @@
+// Conjugate gradients on (K~ + sigma2 I) x = b with the FKT MVM as operator.
+//
+// The paper computes Gaussian-process posterior means through kernel MVMs
+// only (Sec. 5.3 and eq. gp_posterior); this is the solve that needs. The CG
+// vectors and scalars are FP64 whatever the plan's precision; the operator
+// runs in the plan's precision (inputs and outputs converted on the fly).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/fkt.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kDotBlocks = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_to_f64(int64_t m, const T* __restrict__ a, double* __restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < m) b[i] = (double)a[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_from_f64(int64_t m, const double* __restrict__ a, T* __restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < m) b[i] = (T)a[i];
+}
+
+// q = Kp_op (plan precision) + sigma2 p ; then per-block partial dots of p.q
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_add_shift(int64_t m, const T* __restrict__ kp, const double* __restrict__ p,
+                                                        double sigma2, double* __restrict__ q)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < m) q[i] = (double)kp[i] + sigma2 * p[i];
+}
+
+// partial[blk][c] = sum over rows i in block-stride of a[i][c] * b[i][c]
+__global__ __launch_bounds__(kThreads) void k_dot_partial(int64_t n, int nrhs, const double* __restrict__ a,
+                                                          const double* __restrict__ b, double* __restrict__ partial)
+{
+    __shared__ double sh[kThreads];
+    for (int c = 0; c < nrhs; ++c) {
+        double s = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+            s += a[i * nrhs + c] * b[i * nrhs + c];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = kThreads / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * nrhs + c] = sh[0];
+        __syncthreads();
+    }
+}
+
+// y[i][c] += alpha[c] * x[i][c]
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, int nrhs, const double* __restrict__ alpha,
+                                                   const double* __restrict__ x, double* __restrict__ y)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g < n * nrhs) y[g] += alpha[g % nrhs] * x[g];
+}
+
+// p[i][c] = r[i][c] + beta[c] * p[i][c]
+__global__ __launch_bounds__(kThreads) void k_xpby(int64_t n, int nrhs, const double* __restrict__ r,
+                                                   const double* __restrict__ beta, double* __restrict__ p)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g < n * nrhs) p[g] = r[g] + beta[g % nrhs] * p[g];
+}
+
+// r = b - q
+__global__ __launch_bounds__(kThreads) void k_sub(int64_t m, const double* __restrict__ b, const double* __restrict__ q,
+                                                  double* __restrict__ r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < m) r[i] = b[i] - q[i];
+}
+
+unsigned grid_of(int64_t m) { return (unsigned)((m + kThreads - 1) / kThreads); }
+
+struct Buf {
+    std::vector<void*> ptrs;
+    ~Buf()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    hipError_t get(size_t count, T** out)
+    {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(T) * (count ? count : 1));
+        if (e == hipSuccess) ptrs.push_back(p);
+        *out = (T*)p;
+        return e;
+    }
+};
+
+}  // namespace
+
+namespace fkt {
+// set by the C-ABI layer: plan precision, size, stream and device
+struct CgPlanView {
+    int64_t n;
+    int prec;
+    int device;
+    hipStream_t stream;
+};
+fkt_status cg_set_error(fkt_status st, const std::string& msg);
+}  // namespace fkt
+
+namespace fkt {
+
+template <typename T>
+static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const T* b_in, T* x_io, int nrhs, double rtol,
+                           int maxit, int* iters, double* relres)
+{
+    const int64_t n = v.n, m = n * nrhs;
+    hipStream_t s = v.stream;
+    Buf buf;
+    double *b, *x, *r, *p, *q, *part, *coef;
+    T *op_in, *op_out;
+    hipError_t e;
+    if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &p)) ||
+        (e = buf.get(m, &q)) || (e = buf.get((size_t)kDotBlocks * nrhs, &part)) || (e = buf.get(3 * nrhs, &coef)) ||
+        (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)))
+        return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "cg work buffers");
+
+    std::vector<double> hpart((size_t)kDotBlocks * nrhs), hcoef(3 * nrhs);
+    auto dots = [&](const double* a, const double* c, std::vector<double>& out) -> bool {
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, s, n, nrhs, a, c, part);
+        if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        out.assign(nrhs, 0.0);
+        for (int k = 0; k < kDotBlocks; ++k)
+            for (int c = 0; c < nrhs; ++c) out[c] += hpart[(size_t)k * nrhs + c];
+        return true;
+    };
+    auto apply = [&](const double* in, double* out) -> fkt_status {
+        hipLaunchKernelGGL((k_from_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, in, op_in);
+        fkt_status st = fkt_mvm(P, op_in, op_out, nrhs);
+        if (st != FKT_OK) return st;
+        hipLaunchKernelGGL((k_add_shift<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, op_out, in, sigma2, out);
+        return FKT_OK;
+    };
+
+    hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, b_in, b);
+    hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const T*)x_io, x);
+    fkt_status st = apply(x, q);
+    if (st != FKT_OK) return st;
+    hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
+    // p = r
+    if (hipMemcpyAsync(p, r, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return cg_set_error(FKT_EDEVICE, "cg copy");
+
+    std::vector<double> bb, rr, pq, rr_new;
+    if (!dots(b, b, bb) || !dots(r, r, rr)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+    auto worst = [&](const std::vector<double>& rv) {
+        double w = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double den = bb[c] > 0.0 ? std::sqrt(bb[c]) : 1.0;
+            w = std::max(w, std::sqrt(std::max(rv[c], 0.0)) / den);
+        }
+        return w;
+    };
+    int it = 0;
+    double res = worst(rr);
+    while (res > rtol && it < maxit) {
+        st = apply(p, q);
+        if (st != FKT_OK) return st;
+        if (!dots(p, q, pq)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        // coef = [alpha | -alpha | beta]; host slots are rewritten only after
+        // a stream synchronisation (inside dots) has retired the copy.
+        for (int c = 0; c < nrhs; ++c) {
+            hcoef[c] = (pq[c] != 0.0) ? rr[c] / pq[c] : 0.0;
+            hcoef[nrhs + c] = -hcoef[c];
+        }
+        if (hipMemcpyAsync(coef, hcoef.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s) != hipSuccess)
+            return cg_set_error(FKT_EDEVICE, "cg copy");
+        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef, p, x);
+        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef + nrhs, q, r);
+        if (!dots(r, r, rr_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        for (int c = 0; c < nrhs; ++c) hcoef[2 * nrhs + c] = rr[c] > 0.0 ? rr_new[c] / rr[c] : 0.0;
+        if (hipMemcpyAsync(coef + 2 * nrhs, hcoef.data() + 2 * nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return cg_set_error(FKT_EDEVICE, "cg copy");
+        hipLaunchKernelGGL(k_xpby, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, r, coef + 2 * nrhs, p);
+        rr = rr_new;
+        ++it;
+        res = worst(rr);
+    }
+    hipLaunchKernelGGL((k_from_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, x, x_io);
+    if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
+    if (iters) *iters = it;
+    if (relres) *relres = res;
+    if (res > rtol) return cg_set_error(FKT_ENOTCONV, "cg reached maxit before rtol");
+    return FKT_OK;
+}
+
+fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
+                         double rtol, int maxit, int precond, int* iters, double* relres)
+{
+    if (precond != 0) return cg_set_error(FKT_EUNSUPPORTED, "only precond = 0 (none) is built");
+    if (v.prec == 1)
+        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, iters, relres);
+    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, iters, relres);
+}
+
+}  // namespace fkt

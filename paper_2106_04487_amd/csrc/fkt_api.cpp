@@ -1,0 +1,390 @@
+// C-ABI entry points of libfkt.so (declared in include/fkt.h).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fkt.h"
+#include "fkt_device.h"
+#include "fkt_host.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fkt_status fail(fkt_status st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+fkt_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Makes `dev` current for the scope and restores the caller's device.
+struct DeviceScope {
+    int old = -1;
+    bool ok = false;
+    explicit DeviceScope(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) return;
+        ok = (old == dev) || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceScope()
+    {
+        if (ok && old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+}  // namespace
+
+namespace fkt {
+struct CgPlanView {
+    int64_t n;
+    int prec;
+    int device;
+    hipStream_t stream;
+};
+fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
+fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
+                         double rtol, int maxit, int precond, int* iters, double* relres);
+}  // namespace fkt
+
+struct fkt_plan_s {
+    int64_t n = 0;
+    int d = 0, p = 0, leaf = 0;
+    fkt_kernel kern{};
+    fkt_options opt{};
+    fkt::Tree T;
+    fkt::Lists L;
+    fkt::Tables tab;
+    fkt_plan_stats st{};
+    bool on_device = false;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    fkt::DevPlan dp{};
+    fkt::DevWork wk{};
+    struct Ev5 { hipEvent_t e[5]; };
+    std::vector<Ev5> prof;   // events of profiled column passes not yet summed
+    double prof_ms[4] = {0, 0, 0, 0};
+    int64_t prof_calls = 0;
+
+    void drop_events()
+    {
+        for (auto& q : prof)
+            for (hipEvent_t ev : q.e) (void)hipEventDestroy(ev);
+        prof.clear();
+    }
+
+    ~fkt_plan_s()
+    {
+        if (on_device) {
+            DeviceScope ds(opt.device);
+            (void)hipStreamSynchronize(stream);
+            drop_events();
+            for (void* q : allocs) (void)hipFree(q);
+        }
+    }
+
+    hipError_t alloc(size_t bytes, void** out)
+    {
+        *out = nullptr;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(out, bytes);
+        if (e == hipSuccess) allocs.push_back(*out);
+        return e;
+    }
+
+    template <class V>
+    hipError_t upload(const std::vector<V>& v, const V** out)
+    {
+        void* q = nullptr;
+        hipError_t e = alloc(sizeof(V) * v.size(), &q);
+        if (e != hipSuccess) return e;
+        if (!v.empty()) e = hipMemcpy(q, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice);
+        *out = (const V*)q;
+        return e;
+    }
+};
+
+extern "C" {
+
+void fkt_default_options(fkt_options* opt)
+{
+    if (!opt) return;
+    opt->theta = 0.5;
+    opt->prec = FKT_F64;
+    opt->max_depth = 48;
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->profile = 0;
+}
+
+const char* fkt_last_error(void) { return g_err.c_str(); }
+
+static fkt_status check_kernel(const fkt_kernel& k)
+{
+    if ((int)k.kind < (int)FKT_GAUSSIAN || (int)k.kind > (int)FKT_LAPLACE)
+        return fail(FKT_EINVAL, "unknown kernel kind");
+    if (!(k.variance > 0.0) || !std::isfinite(k.variance)) return fail(FKT_EINVAL, "kernel variance must be > 0");
+    if (k.kind != FKT_LAPLACE && (!(k.lengthscale > 0.0) || !std::isfinite(k.lengthscale)))
+        return fail(FKT_EINVAL, "kernel lengthscale must be > 0");
+    if (k.kind == FKT_RATQUAD && (!(k.alpha > 0.0) || !std::isfinite(k.alpha)))
+        return fail(FKT_EINVAL, "rational-quadratic alpha must be > 0");
+    return FKT_OK;
+}
+
+static fkt_status upload_plan(fkt_plan_t P)
+{
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device " + std::to_string(P->opt.device));
+    P->on_device = true;
+    P->stream = (hipStream_t)P->opt.stream;
+    fkt::DevPlan& a = P->dp;
+    const fkt::Tree& T = P->T;
+    const fkt::Lists& L = P->L;
+    hipError_t e = hipSuccess;
+#define FKT_UP(vec, dst) \
+    if ((e = P->upload(vec, &dst)) != hipSuccess) return hip_fail(e, "plan upload")
+    a.n = (int)P->n;
+    a.d = P->d;
+    a.p = P->p;
+    a.rank = (int)P->tab.rank;
+    a.nblocks = (int)L.blk_begin.size();
+    a.nslots = (int)L.slot_node.size();
+    a.nunits = (int)L.unit_slot.size();
+    a.nred = (int)L.red_slot.size();
+    a.kind = (int)P->kern.kind;
+    a.ell = P->kern.lengthscale;
+    a.alpha = P->kern.alpha;
+    a.var = P->kern.variance;
+    FKT_UP(T.pts, a.pts64);
+    if (P->opt.prec == FKT_F32) {
+        std::vector<float> p32(T.pts.begin(), T.pts.end());
+        FKT_UP(p32, a.pts32);
+    }
+    FKT_UP(T.perm, a.perm);
+    FKT_UP(L.blk_begin, a.blk_begin);
+    FKT_UP(L.blk_count, a.blk_count);
+    FKT_UP(L.near_off, a.near_off);
+    FKT_UP(L.near_beg, a.near_beg);
+    FKT_UP(L.near_end, a.near_end);
+    FKT_UP(L.near_mask, a.near_mask);
+    FKT_UP(L.far_off, a.far_off);
+    FKT_UP(L.far_slot, a.far_slot);
+    FKT_UP(L.far_mask, a.far_mask);
+    FKT_UP(L.slot_ctr, a.slot_ctr);
+    FKT_UP(L.slot_scale, a.slot_scale);
+    FKT_UP(L.unit_slot, a.unit_slot);
+    FKT_UP(L.unit_begin, a.unit_begin);
+    FKT_UP(L.unit_end, a.unit_end);
+    FKT_UP(L.unit_dst, a.unit_dst);
+    FKT_UP(L.red_slot, a.red_slot);
+    FKT_UP(L.red_off, a.red_off);
+    FKT_UP(P->tab.tbar, a.tbar);
+    FKT_UP(P->tab.hnorm, a.hn64);
+    {
+        std::vector<float> h32(P->tab.hnorm.begin(), P->tab.hnorm.end());
+        FKT_UP(h32, a.hn32);
+    }
+#undef FKT_UP
+    const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
+    if ((e = P->alloc(es * P->n, &P->wk.w)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * P->n, &P->wk.zfar)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * L.slot_node.size() * P->tab.rank, &P->wk.mom)) != hipSuccess)
+        return hip_fail(e, "moment buffer");
+    if ((e = P->alloc(es * L.npartials * P->tab.rank, &P->wk.part)) != hipSuccess)
+        return hip_fail(e, "partial-moment buffer");
+    return FKT_OK;
+}
+
+fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int leaf_size, int order,
+                    const fkt_options* opt_in, fkt_plan_t* out)
+{
+    if (!out) return fail(FKT_EINVAL, "out is NULL");
+    *out = nullptr;
+    fkt_options opt;
+    fkt_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!points) return fail(FKT_EINVAL, "points is NULL");
+    if (n < 1) return fail(FKT_EINVAL, "n must be >= 1");
+    if (n > 0x7fffffffLL) return fail(FKT_EINVAL, "n must be < 2^31");
+    if (d < 1) return fail(FKT_EINVAL, "d must be >= 1");
+    if (d < 3 || d > 5) return fail(FKT_EUNSUPPORTED, "d must be 3, 4 or 5");
+    if (leaf_size < 1) return fail(FKT_EINVAL, "leaf_size must be >= 1");
+    if (order < 0) return fail(FKT_EINVAL, "order must be >= 0");
+    if (!fkt::far_supported(d, order))
+        return fail(FKT_EUNSUPPORTED, "order " + std::to_string(order) + " not built for d = " + std::to_string(d));
+    if (!(opt.theta > 0.0 && opt.theta < 1.0)) return fail(FKT_EINVAL, "theta must be in (0, 1)");
+    if (opt.prec != FKT_F64 && opt.prec != FKT_F32) return fail(FKT_EINVAL, "unknown precision");
+    if (opt.max_depth < 1 || opt.max_depth > 60) return fail(FKT_EINVAL, "max_depth must be in [1, 60]");
+    if (opt.device < -1) return fail(FKT_EINVAL, "device must be >= -1");
+    fkt_status s = check_kernel(k);
+    if (s != FKT_OK) return s;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!std::isfinite(points[i])) return fail(FKT_EINVAL, "non-finite coordinate at index " + std::to_string(i));
+
+    const auto t0 = std::chrono::steady_clock::now();
+    fkt_plan_t P = new (std::nothrow) fkt_plan_s();
+    if (!P) return fail(FKT_ENOMEM, "plan allocation");
+    try {
+        P->n = n;
+        P->d = d;
+        P->p = order;
+        P->leaf = leaf_size;
+        P->kern = k;
+        P->opt = opt;
+        fkt::build_tree(points, n, d, leaf_size, opt.max_depth, P->T);
+        fkt::build_lists(P->T, opt.theta, P->L, P->st);
+        fkt::build_tables(d, order, P->tab);
+    } catch (const std::bad_alloc&) {
+        delete P;
+        return fail(FKT_ENOMEM, "host allocation while building the plan");
+    }
+    fkt_plan_stats& st = P->st;
+    st.n = n;
+    st.nnodes = P->T.nnodes();
+    st.nleaves = 0;
+    st.depth = 0;
+    for (int64_t b = 0; b < st.nnodes; ++b) {
+        st.nleaves += P->T.leaf(b);
+        st.depth = std::max<int64_t>(st.depth, P->T.level[b]);
+    }
+    st.rank = P->tab.rank;
+    if (opt.device >= 0) {
+        s = upload_plan(P);
+        if (s != FKT_OK) {
+            delete P;
+            return s;
+        }
+    }
+    st.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P;
+    return FKT_OK;
+}
+
+fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_mvm");
+    if (!x || !y) return fail(FKT_EINVAL, "x or y is NULL");
+    if (nrhs < 1 || nrhs > 64) return fail(FKT_EINVAL, "nrhs must be in [1, 64]");
+    const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
+    const size_t bytes = es * (size_t)P->n * nrhs;
+    const char *xb = (const char*)x, *yb = (const char*)y;
+    if (xb < yb + bytes && yb < xb + bytes) return fail(FKT_EINVAL, "x and y overlap");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    for (int c = 0; c < nrhs; ++c) {
+        hipEvent_t* ev = nullptr;
+        if (P->opt.profile) {
+            fkt_plan_s::Ev5 q{};
+            for (auto& e : q.e)
+                if (hipEventCreate(&e) != hipSuccess) return fail(FKT_EDEVICE, "hipEventCreate");
+            P->prof.push_back(q);
+            ev = P->prof.back().e;
+        }
+        hipError_t e = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, P->stream, ev);
+        if (e != hipSuccess) return hip_fail(e, "fkt_mvm launch");
+    }
+    return FKT_OK;
+}
+
+fkt_status fkt_plan_stage_times(fkt_plan_t P, double* ms, int64_t* calls, int reset)
+{
+    if (!P || !ms) return fail(FKT_EINVAL, "NULL argument");
+    if (!P->opt.profile) return fail(FKT_EINVAL, "plan was built without opt.profile");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    for (auto& q : P->prof) {
+        if (hipEventSynchronize(q.e[4]) != hipSuccess) return fail(FKT_EDEVICE, "hipEventSynchronize");
+        for (int i = 0; i < 4; ++i) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, q.e[i], q.e[i + 1]) != hipSuccess) return fail(FKT_EDEVICE, "hipEventElapsedTime");
+            P->prof_ms[i] += t;
+        }
+        P->prof_calls += 1;
+    }
+    P->drop_events();
+    for (int i = 0; i < 4; ++i) ms[i] = P->prof_ms[i];
+    if (calls) *calls = P->prof_calls;
+    if (reset) {
+        for (double& v : P->prof_ms) v = 0.0;
+        P->prof_calls = 0;
+    }
+    return FKT_OK;
+}
+
+void fkt_destroy(fkt_plan_t P) { delete P; }
+
+fkt_status fkt_plan_info(fkt_plan_t P, fkt_plan_stats* s)
+{
+    if (!P || !s) return fail(FKT_EINVAL, "NULL argument");
+    *s = P->st;
+    return FKT_OK;
+}
+
+fkt_status fkt_plan_perm(fkt_plan_t P, int64_t* perm)
+{
+    if (!P || !perm) return fail(FKT_EINVAL, "NULL argument");
+    std::memcpy(perm, P->T.perm.data(), sizeof(int64_t) * P->n);
+    return FKT_OK;
+}
+
+fkt_status fkt_plan_target_counts(fkt_plan_t P, int64_t* far_nodes, int64_t* far_points, int64_t* near_leaves,
+                                  int64_t* near_points)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    const fkt::Lists& L = P->L;
+    const fkt::Tree& T = P->T;
+    int64_t* outs[4] = {far_nodes, far_points, near_leaves, near_points};
+    for (int64_t* o : outs)
+        if (o) std::memset(o, 0, sizeof(int64_t) * P->n);
+    const int64_t nb = (int64_t)L.blk_begin.size();
+    for (int64_t q = 0; q < nb; ++q) {
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) {
+            const int32_t b = L.slot_node[L.far_slot[e]];
+            for (int lane = 0; lane < L.blk_count[q]; ++lane) {
+                if (!((L.far_mask[e] >> lane) & 1)) continue;
+                const int64_t t = T.perm[L.blk_begin[q] + lane];
+                if (far_nodes) far_nodes[t] += 1;
+                if (far_points) far_points[t] += T.end[b] - T.begin[b];
+            }
+        }
+        for (int e = L.near_off[q]; e < L.near_off[q + 1]; ++e) {
+            for (int lane = 0; lane < L.blk_count[q]; ++lane) {
+                if (!((L.near_mask[e] >> lane) & 1)) continue;
+                const int64_t t = T.perm[L.blk_begin[q] + lane];
+                if (near_leaves) near_leaves[t] += 1;
+                if (near_points) near_points[t] += L.near_end[e] - L.near_beg[e];
+            }
+        }
+    }
+    return FKT_OK;
+}
+
+fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
+                        int precond, int* iters, double* relres)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_cg_solve");
+    if (!b || !x) return fail(FKT_EINVAL, "b or x is NULL");
+    if (nrhs < 1 || nrhs > 64) return fail(FKT_EINVAL, "nrhs must be in [1, 64]");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be >= 0");
+    if (!(rtol > 0.0)) return fail(FKT_EINVAL, "rtol must be > 0");
+    if (maxit < 1) return fail(FKT_EINVAL, "maxit must be >= 1");
+    if (precond < 0 || precond > 1) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt::CgPlanView v{P->n, (int)P->opt.prec, P->opt.device, P->stream};
+    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres);
+}
+
+}  // extern "C"

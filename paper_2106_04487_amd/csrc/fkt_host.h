@@ -1,0 +1,70 @@
+// Host-side plan data of the FKT library: tree, interaction lists, tables.
+//
+// Everything here is built once per plan on the CPU and uploaded to the
+// device; the device kernels only read it.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/fkt.h"
+
+namespace fkt {
+
+// Targets are processed in blocks of up to 64 consecutive tree positions
+// inside one leaf: one block is one wavefront, one lane per target.
+constexpr int kBlock = 64;
+// s2m work units: at most this many consecutive points of one node.
+constexpr int kUnitPoints = 1024;
+
+// Binary space-partition tree (paper Sec. 3.1), nodes in preorder.
+struct Tree {
+    int d = 0;
+    int64_t n = 0;
+    std::vector<int64_t> perm;   // tree position -> original index
+    std::vector<double> pts;     // [n][d] coordinates in tree order
+    std::vector<double> lo, side, ctr;  // [nnodes][d] box corner, side lengths, centre
+    std::vector<double> rho2;    // squared radius: max over the node's points of |x - ctr|^2
+    std::vector<int64_t> begin, end;    // point range [begin, end) in tree order
+    std::vector<int32_t> kid0, kid1, parent, level;
+    int64_t nnodes() const { return (int64_t)rho2.size(); }
+    bool leaf(int64_t b) const { return kid0[b] < 0 && kid1[b] < 0; }
+};
+
+// Near/far interaction lists per 64-target block, with lane masks: bit i of
+// a mask is set when target (block begin + i) has that entry in its own
+// near or far set (paper eq. accparam, per target).
+struct Lists {
+    std::vector<int32_t> blk_begin, blk_count;
+    std::vector<int32_t> near_off, near_beg, near_end;  // near_off: [nblocks + 1]
+    std::vector<uint64_t> near_mask;
+    std::vector<int32_t> far_off, far_slot;             // far_off: [nblocks + 1]
+    std::vector<uint64_t> far_mask;
+    std::vector<int32_t> slot_node;                     // far-node slot -> node id
+    std::vector<double> slot_ctr, slot_scale;           // [nslots][d], [nslots]
+    // s2m work units (node slot, point range) and the moment/partial they fill
+    std::vector<int32_t> unit_slot, unit_begin, unit_end, unit_dst;
+    // slots whose moments are the sum of several partials: slot, partial range
+    std::vector<int32_t> red_slot, red_off;
+    int64_t npartials = 0;
+};
+
+// Dimension/order-only constants (paper Appendix A.2; harmonics normalisation).
+struct Tables {
+    int d = 0, p = 0;
+    int64_t rank = 0;
+    std::vector<double> tbar;   // [(k*(p+1) + j)*(p+1) + m]
+    std::vector<double> hnorm;  // [((e-3)*(p+1) + mu)*(p+1) + n], e = 3..d
+};
+
+void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T);
+void build_lists(const Tree& T, double theta, Lists& L, fkt_plan_stats& st);
+void build_tables(int d, int p, Tables& tab);
+int64_t binom(int64_t a, int64_t b);
+
+// Simple parallel-for over [0, n) on host threads.
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn);
+
+}  // namespace fkt

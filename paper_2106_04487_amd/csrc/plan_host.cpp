@@ -1,0 +1,389 @@
+// Host plan builder: space-partition tree, per-target near/far partition
+// gathered into 64-target blocks, and the expansion's constant tables.
+//
+// Built with -ffp-contract=off: the far test of eq. (accparam) must give the
+// same answer as any other FP64 evaluation of the same predicate (summed in
+// axis order, multiply then add, no fused multiply-add).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "fkt_host.h"
+
+namespace fkt {
+
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn)
+{
+    if (n <= 0) return;
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nthreads = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 16));
+    if (n <= grain || nthreads == 1) { fn(0, n); return; }
+    std::atomic<int64_t> next(0);
+    auto worker = [&]() {
+        for (;;) {
+            int64_t b = next.fetch_add(grain);
+            if (b >= n) break;
+            fn(b, std::min(n, b + grain));
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int64_t t = 1; t < nthreads; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+}
+
+int64_t binom(int64_t a, int64_t b)
+{
+    if (b < 0 || a < 0 || b > a) return 0;
+    int64_t r = 1;
+    for (int64_t i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return r;
+}
+
+// ---------------------------------------------------------------- tree
+
+namespace {
+struct Pending {
+    int64_t begin, end;
+    int32_t parent, level, which;
+    double lo[8], side[8];
+};
+}  // namespace
+
+// Orders a leaf's points by continued midplane halving of the longest side
+// (down to groups of kLeafGroup points) so that every 64-target block is a
+// compact piece of space. Only the order inside the leaf changes: leaf
+// membership, and so the partition, is untouched.
+constexpr int64_t kLeafGroup = 16;
+static void order_leaf(const double* X, int d, const double* lo_in, const double* side_in, int64_t* idx,
+                       int64_t cnt, int64_t* scratch, int depth = 0)
+{
+    if (cnt <= kLeafGroup || depth >= 64) return;
+    double lo[8] = {0}, side[8] = {0};
+    for (int a = 0; a < d; ++a) { lo[a] = lo_in[a]; side[a] = side_in[a]; }
+    int axis = 0;
+    for (int a = 1; a < d; ++a) if (side[a] > side[axis]) axis = a;
+    if (!(side[axis] > 0.0)) return;
+    const double mid = lo[axis] + 0.5 * side[axis];
+    int64_t w = 0, r = 0;
+    for (int64_t i = 0; i < cnt; ++i) {
+        if (X[idx[i] * d + axis] < mid) idx[w++] = idx[i]; else scratch[r++] = idx[i];
+    }
+    std::memcpy(idx + w, scratch, sizeof(int64_t) * r);
+    side[axis] *= 0.5;
+    order_leaf(X, d, lo, side, idx, w, scratch, depth + 1);
+    lo[axis] = mid;
+    order_leaf(X, d, lo, side, idx + w, cnt - w, scratch, depth + 1);
+}
+
+// Sec. 3.1: hypercube root; each split halves one of the longest sides of the
+// node (so the aspect ratio stays <= 2), choosing among those the axis that
+// splits the points most evenly (lowest axis on ties); a node with at most
+// leaf_size points (or at the depth cap) is a leaf. Children keep the stable
+// order of their points; empty children are not created; ids are preorder.
+void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T)
+{
+    T = Tree();
+    T.d = d;
+    T.n = n;
+    T.perm.resize(n);
+    std::iota(T.perm.begin(), T.perm.end(), int64_t(0));
+    std::vector<int64_t> scratch(n);
+
+    Pending root{};
+    root.begin = 0; root.end = n; root.parent = -1; root.level = 0; root.which = -1;
+    double extent = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double mn = X[a], mx = X[a];
+        for (int64_t i = 1; i < n; ++i) {
+            double v = X[i * d + a];
+            mn = v < mn ? v : mn;
+            mx = v > mx ? v : mx;
+        }
+        root.lo[a] = mn;
+        extent = std::max(extent, mx - mn);
+    }
+    for (int a = 0; a < d; ++a) root.side[a] = extent;
+
+    std::vector<Pending> stack{root};
+    while (!stack.empty()) {
+        Pending P = stack.back();
+        stack.pop_back();
+        const int32_t id = (int32_t)T.rho2.size();
+        for (int a = 0; a < d; ++a) {
+            T.lo.push_back(P.lo[a]);
+            T.side.push_back(P.side[a]);
+            T.ctr.push_back(P.lo[a] + 0.5 * P.side[a]);
+        }
+        T.rho2.push_back(0.0);
+        T.begin.push_back(P.begin);
+        T.end.push_back(P.end);
+        T.kid0.push_back(-1);
+        T.kid1.push_back(-1);
+        T.parent.push_back(P.parent);
+        T.level.push_back(P.level);
+        if (P.parent >= 0) (P.which == 0 ? T.kid0 : T.kid1)[P.parent] = id;
+
+        const int64_t cnt = P.end - P.begin;
+        if (cnt <= leaf_size || P.level >= max_depth) {
+            order_leaf(X, d, P.lo, P.side, T.perm.data() + P.begin, cnt, scratch.data());
+            continue;
+        }
+
+        double smax = 0.0;
+        for (int a = 0; a < d; ++a) smax = std::max(smax, P.side[a]);
+        int axis = -1;
+        int64_t best = 0, nl_best = 0;
+        double mid_best = 0.0;
+        for (int a = 0; a < d; ++a) {
+            if (P.side[a] != smax) continue;
+            const double mid = P.lo[a] + 0.5 * P.side[a];
+            int64_t nl = 0;
+            for (int64_t i = P.begin; i < P.end; ++i) nl += X[T.perm[i] * d + a] < mid;
+            const int64_t score = std::llabs(2 * nl - cnt);
+            if (axis < 0 || score < best) { axis = a; best = score; nl_best = nl; mid_best = mid; }
+        }
+        // stable partition of perm[begin, end) into {< mid} then {>= mid}
+        int64_t w = P.begin, r = 0;
+        for (int64_t i = P.begin; i < P.end; ++i) {
+            const int64_t q = T.perm[i];
+            if (X[q * d + axis] < mid_best) T.perm[w++] = q; else scratch[r++] = q;
+        }
+        std::memcpy(T.perm.data() + w, scratch.data(), sizeof(int64_t) * r);
+
+        Pending L = P, R = P;
+        L.parent = R.parent = id;
+        L.level = R.level = P.level + 1;
+        L.which = 0; R.which = 1;
+        L.side[axis] = R.side[axis] = 0.5 * P.side[axis];
+        R.lo[axis] = mid_best;
+        L.end = P.begin + nl_best;
+        R.begin = P.begin + nl_best;
+        // LIFO: the left child is taken (and numbered) first
+        if (R.end > R.begin) stack.push_back(R);
+        if (L.end > L.begin) stack.push_back(L);
+    }
+
+    T.pts.resize((size_t)n * d);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a) T.pts[i * d + a] = X[T.perm[i] * d + a];
+
+    const int64_t nn = T.nnodes();
+    parallel_for(nn, 64, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            double m = 0.0;
+            for (int64_t i = T.begin[b]; i < T.end[b]; ++i) {
+                double s = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    const double u = T.pts[i * d + a] - T.ctr[b * d + a];
+                    s = s + u * u;
+                }
+                m = s > m ? s : m;
+            }
+            T.rho2[b] = m;
+        }
+    });
+}
+
+// ------------------------------------------------------------- partition
+
+namespace {
+struct BlockLists {
+    std::vector<int32_t> near_node, far_node;
+    std::vector<uint64_t> near_mask, far_mask;
+};
+}  // namespace
+
+// For every target t, walking from the root: t is in F_b when b is the first
+// node on the path with rho_b^2 < theta^2 |t - c_b|^2 (eq. accparam), and in
+// N_l for each leaf l reached without such a node (Sec. 3.2). Done for 64
+// targets at once with a mask of the targets still walking.
+void build_lists(const Tree& T, double theta, Lists& L, fkt_plan_stats& st)
+{
+    const int d = T.d;
+    const int64_t nn = T.nnodes();
+    const double theta2 = theta * theta;
+    L = Lists();
+
+    // 64 consecutive tree positions per block (blocks may span leaves: tree
+    // order keeps them spatially compact, and full blocks keep lanes busy)
+    for (int64_t o = 0; o < T.n; o += kBlock) {
+        L.blk_begin.push_back((int32_t)o);
+        L.blk_count.push_back((int32_t)std::min<int64_t>(kBlock, T.n - o));
+    }
+    const int64_t nb = (int64_t)L.blk_begin.size();
+    std::vector<BlockLists> per(nb);
+
+    parallel_for(nb, 16, [&](int64_t q0, int64_t q1) {
+        std::vector<std::pair<int32_t, uint64_t>> stack;
+        for (int64_t q = q0; q < q1; ++q) {
+            const int64_t tb = L.blk_begin[q];
+            const int cnt = L.blk_count[q];
+            BlockLists& out = per[q];
+            stack.clear();
+            stack.emplace_back(0, cnt == 64 ? ~uint64_t(0) : ((uint64_t(1) << cnt) - 1));
+            while (!stack.empty()) {
+                auto [b, active] = stack.back();
+                stack.pop_back();
+                uint64_t far = 0;
+                for (int lane = 0; lane < cnt; ++lane) {
+                    if (!((active >> lane) & 1)) continue;
+                    const double* t = &T.pts[(tb + lane) * d];
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        const double u = t[a] - T.ctr[b * d + a];
+                        s = s + u * u;
+                    }
+                    if (T.rho2[b] < theta2 * s) far |= uint64_t(1) << lane;
+                }
+                if (far) { out.far_node.push_back(b); out.far_mask.push_back(far); }
+                active &= ~far;
+                if (!active) continue;
+                if (T.leaf(b)) { out.near_node.push_back(b); out.near_mask.push_back(active); continue; }
+                if (T.kid1[b] >= 0) stack.emplace_back(T.kid1[b], active);
+                if (T.kid0[b] >= 0) stack.emplace_back(T.kid0[b], active);
+            }
+        }
+    });
+
+    // far-node slots, in node order
+    std::vector<int32_t> slot_of(nn, -1);
+    for (const auto& bl : per)
+        for (int32_t b : bl.far_node) slot_of[b] = 1;
+    for (int64_t b = 0; b < nn; ++b)
+        if (slot_of[b] >= 0) { slot_of[b] = (int32_t)L.slot_node.size(); L.slot_node.push_back((int32_t)b); }
+
+    L.near_off.assign(nb + 1, 0);
+    L.far_off.assign(nb + 1, 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        L.near_off[q + 1] = L.near_off[q] + (int32_t)per[q].near_node.size();
+        L.far_off[q + 1] = L.far_off[q] + (int32_t)per[q].far_node.size();
+    }
+    int64_t near_pairs = 0, near_lane = 0, far_pairs = 0, far_lane = 0;
+    for (int64_t q = 0; q < nb; ++q) {
+        for (size_t e = 0; e < per[q].near_node.size(); ++e) {
+            const int32_t b = per[q].near_node[e];
+            L.near_beg.push_back((int32_t)T.begin[b]);
+            L.near_end.push_back((int32_t)T.end[b]);
+            L.near_mask.push_back(per[q].near_mask[e]);
+            near_pairs += (int64_t)__builtin_popcountll(per[q].near_mask[e]) * (T.end[b] - T.begin[b]);
+            near_lane += (int64_t)kBlock * (T.end[b] - T.begin[b]);
+        }
+        for (size_t e = 0; e < per[q].far_node.size(); ++e) {
+            L.far_slot.push_back(slot_of[per[q].far_node[e]]);
+            L.far_mask.push_back(per[q].far_mask[e]);
+            far_pairs += __builtin_popcountll(per[q].far_mask[e]);
+            far_lane += kBlock;
+        }
+    }
+
+    const int64_t ns = (int64_t)L.slot_node.size();
+    L.slot_ctr.resize(ns * d);
+    L.slot_scale.resize(ns);
+    int64_t s2m_terms = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t b = L.slot_node[s];
+        for (int a = 0; a < d; ++a) L.slot_ctr[s * d + a] = T.ctr[b * d + a];
+        L.slot_scale[s] = T.rho2[b] > 0.0 ? std::sqrt(T.rho2[b]) : 1.0;
+        const int64_t beg = T.begin[b], end = T.end[b];
+        s2m_terms += end - beg;
+        const int64_t nunits = (end - beg + kUnitPoints - 1) / kUnitPoints;
+        if (nunits > 1) {
+            L.red_slot.push_back((int32_t)s);
+            L.red_off.push_back((int32_t)L.npartials);
+        }
+        for (int64_t u = 0; u < nunits; ++u) {
+            L.unit_slot.push_back((int32_t)s);
+            L.unit_begin.push_back((int32_t)(beg + u * kUnitPoints));
+            L.unit_end.push_back((int32_t)std::min(end, beg + (u + 1) * kUnitPoints));
+            L.unit_dst.push_back(nunits == 1 ? (int32_t)s : (int32_t)(-1 - L.npartials++));
+        }
+    }
+    L.red_off.push_back((int32_t)L.npartials);
+
+    st.nblocks = nb;
+    st.far_nodes = ns;
+    st.near_entries = (int64_t)L.near_beg.size();
+    st.far_entries = (int64_t)L.far_slot.size();
+    st.near_pairs = near_pairs;
+    st.near_lane_pairs = near_lane;
+    st.far_pairs = far_pairs;
+    st.far_lane_pairs = far_lane;
+    st.s2m_terms = s2m_terms;
+}
+
+// ----------------------------------------------------------------- tables
+
+namespace {
+using ld = long double;
+
+ld fact(int n) { ld r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
+ld dfact(int n) { ld r = 1; for (int i = n; i > 1; i -= 2) r *= i; return r; }  // (-1)!! = 0!! = 1
+ld rising(ld a, int n) { ld r = 1; for (int i = 0; i < n; ++i) r *= a + i; return r; }
+
+// cos^i = sum_k A(k,i) C_k^alpha(cos), Appendix A.2 eq. (coschange), with the
+// half-integer (i-k)/2 in the denominator read as a factorial.
+ld coef_A(int k, int i, ld alpha)
+{
+    if (k > i || ((i - k) & 1)) return 0;
+    return fact(i) * (alpha + k) / (std::pow((ld)2, (ld)i) * fact((i - k) / 2) * rising(alpha, (i + k) / 2 + 1));
+}
+
+// d^n/de^n K(r sqrt(1+e)) at e = 0 = sum_m B(n,m) K^(m)(r) r^m (Lemma A.2).
+ld coef_B(int n, int m)
+{
+    if (m < 1 || m > n) return 0;
+    const ld sgn = ((n + m) & 1) ? -1 : 1;
+    return sgn * dfact(2 * n - 2 * m - 1) * (ld)binom(2 * n - m - 1, m - 1) / std::pow((ld)2, (ld)n);
+}
+}  // namespace
+
+void build_tables(int d, int p, Tables& tab)
+{
+    tab.d = d;
+    tab.p = p;
+    const ld alpha = (ld)d / 2 - 1;
+    const int P1 = p + 1;
+    tab.tbar.assign((size_t)P1 * P1 * P1, 0.0);
+    // Tbar_{k,j,m} = sum_n A_{k,2n-j} (-2)^{2n-j} C(n, 2n-j) B_{n,m} / n!  (the
+    // binomial of the binomial expansion of eps^n is kept).
+    for (int k = 0; k <= p; ++k)
+        for (int j = k; j <= p; j += 2)
+            for (int m = 1; m <= j; ++m) {
+                ld s = 0;
+                for (int n = std::max((j + k) / 2, m); n <= j; ++n) {
+                    const int i = 2 * n - j;
+                    s += coef_A(k, i, alpha) * std::pow((ld)-2, (ld)i) * (ld)binom(n, i) * coef_B(n, m) / fact(n);
+                }
+                tab.tbar[((size_t)k * P1 + j) * P1 + m] = (double)s;
+            }
+
+    // Orthonormal solid harmonics built one dimension at a time: a degree-k
+    // harmonic in e dimensions is |x|^(k-mu) C_{k-mu}^{mu+(e-2)/2}(x_e/|x|)
+    // times a degree-mu harmonic of the first e-1 coordinates. hnorm holds
+    // the factor that makes each level orthonormal on its sphere, and at the
+    // top level also sqrt(Z_k) of the addition theorem, so that
+    //   sum_h Yhat_kh(u) Yhat_kh(v) = C_k^alpha(u . v)   (|u| = |v| = 1).
+    tab.hnorm.assign((size_t)std::max(1, d - 2) * P1 * P1, 0.0);
+    const ld pi = 3.14159265358979323846264338327950288L;
+    const ld area = 2 * std::pow(pi, (ld)d / 2) / std::tgamma((ld)d / 2);
+    for (int e = 3; e <= d; ++e)
+        for (int mu = 0; mu <= p; ++mu)
+            for (int n = 0; mu + n <= p; ++n) {
+                const ld lam = mu + (ld)(e - 2) / 2;
+                const ld logh = std::log(pi) + (1 - 2 * lam) * std::log((ld)2) + std::lgamma(n + 2 * lam) -
+                                std::lgamma((ld)n + 1) - std::log(n + lam) - 2 * std::lgamma(lam);
+                ld v = std::exp(-0.5L * logh);
+                if (e == d) {
+                    const int k = mu + n;
+                    v *= std::sqrt(alpha * area / (k + alpha));
+                }
+                tab.hnorm[((size_t)(e - 3) * P1 + mu) * P1 + n] = (double)v;
+            }
+    tab.rank = binom(p + d, d);
+}
+
+}  // namespace fkt
