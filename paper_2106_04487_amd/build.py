@@ -26,19 +26,28 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include")]
 
 
 def _jobs():
-    return [
+    dev = [HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS]
+    jobs = [
         # the FP64 far-test predicate must not be contracted into FMAs
         (["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-c",
           os.path.join(CSRC, "plan_host.cpp"), "-o", os.path.join(BUILD, "plan_host.o")]),
         ([HIPCC, *COMMON, "-c", os.path.join(CSRC, "fkt_api.cpp"), "-o", os.path.join(BUILD, "fkt_api.o")]),
-        ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"),
-          "-o", os.path.join(BUILD, "kernels.o")]),
-        ([HIPCC, *COMMON, f"--offload-arch={ARCH}", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "cg.hip"),
-          "-o", os.path.join(BUILD, "cg.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "mvm.hip"), "-o", os.path.join(BUILD, "mvm.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "stage_s2m.hip"), "-o", os.path.join(BUILD, "stage_s2m.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "cg.hip"), "-o", os.path.join(BUILD, "cg.o")]),
     ]
+    # one multipole-to-target object per kernel kind (fkt_kernel_kind 0..6)
+    for kind in range(7):
+        jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "stage_m2t.hip"),
+                     "-o", os.path.join(BUILD, f"stage_m2t_{kind}.o")])
+    return jobs
 
 
-def build(jobs: int = 4, verbose: bool = False) -> str:
+def _objects():
+    return [j[j.index("-o") + 1] for j in _jobs()]
+
+
+def build(jobs: int = 8, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
 
     def run(cmd):
@@ -52,17 +61,14 @@ def build(jobs: int = 4, verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(run, _jobs()))
     tmp = LIB + ".tmp"
-    run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}",
-         os.path.join(BUILD, "plan_host.o"), os.path.join(BUILD, "fkt_api.o"),
-         os.path.join(BUILD, "kernels.o"), os.path.join(BUILD, "cg.o"),
-         "-o", tmp, "-lpthread"])
+    run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *_objects(), "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", action="store_true")
     a = ap.parse_args()
     print(build(a.jobs, a.v))

@@ -189,14 +189,16 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.red_slot, a.red_slot);
     FKT_UP(L.red_off, a.red_off);
     FKT_UP(P->tab.tbar, a.tbar);
-    FKT_UP(P->tab.hnorm, a.hn64);
     {
-        std::vector<float> h32(P->tab.hnorm.begin(), P->tab.hnorm.end());
+        std::vector<double> h2(P->tab.hnorm.size());
+        for (size_t i = 0; i < h2.size(); ++i) h2[i] = P->tab.hnorm[i] * P->tab.hnorm[i];
+        FKT_UP(h2, a.hn64);
+        std::vector<float> h32(h2.begin(), h2.end());
         FKT_UP(h32, a.hn32);
     }
 #undef FKT_UP
     const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
-    if ((e = P->alloc(es * P->n, &P->wk.w)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * P->n * (P->d == 3 ? 4 : 6), &P->wk.src)) != hipSuccess) return hip_fail(e, "work buffer");
     if ((e = P->alloc(es * P->n, &P->wk.zfar)) != hipSuccess) return hip_fail(e, "work buffer");
     if ((e = P->alloc(es * L.slot_node.size() * P->tab.rank, &P->wk.mom)) != hipSuccess)
         return hip_fail(e, "moment buffer");

@@ -33,13 +33,13 @@ struct DevPlan {
     const int* red_slot;          // slots summed from partials
     const int* red_off;           // [nred + 1] partial ranges
     const double* tbar;           // [(k*(p+1)+j)*(p+1)+m]
-    const double* hn64;           // harmonic normalisation, FP64
+    const double* hn64;           // squared harmonic normalisation (x Z_k), FP64
     const float* hn32;            //   and FP32 copy
 };
 
 // Per-call work buffers (device) for one right-hand-side column.
 struct DevWork {
-    void* w;      // [n] tree-ordered weights
+    void* src;    // [n][4 or 6] tree-ordered packed (coordinates, weight) records
     void* zfar;   // [n] far-field result, tree order
     void* mom;    // [nslots][rank]
     void* part;   // [npartials][rank]

@@ -1,0 +1,720 @@
+// Device templates of the FKT matrix-vector product for CDNA4 (gfx950),
+// included by the .hip translation units that instantiate them.
+//
+// One 64-lane wavefront owns a block of up to 64 consecutive targets inside
+// one leaf (one lane per target). Source data that every lane needs at the
+// same time -- source points of a near leaf, a far node's centre and
+// moments, the constant tables -- is indexed uniformly across the wave, so it
+// is fetched with scalar loads and used as scalar operands; per-target data
+// lives in vector registers. Lane masks from the plan select, per target,
+// exactly the near leaves and far nodes of that target's own walk.
+//
+// Expansion (paper Theorem 3.1, eq. finaltrunc), per far node b with centre
+// c and scale s = node radius, for a source at r' = x_s - c and a target at
+// r = t - c:
+//   K~(r', r) = sum_{k<=p} sum_h Yhat_kh(r^) Yhat_kh(r'^)
+//               sum_{j=k,k+2..<=p} r'^j F_kj(|r|),
+//   F_kj(r)  = [j=0] K(r) + sum_{m=1}^{j} K^(m)(r) r^(m-j) Tbar_kjm,
+// where the harmonics are normalised so that sum_h Yhat(u) Yhat(v) =
+// C_k^alpha(u.v) (addition theorem, Appendix A.1; this absorbs Z_k).
+// s2m stores, in units of s,
+//   M_b[kh, j] = sum_s Yhat_kh(r'^) (|r'|/s)^j x_s
+//              = sum_s Rhat_kh(r'/s) (|r'|/s)^(j-k) x_s   (solid harmonics),
+// and m2t evaluates sum_kh Yhat_kh(r^) sum_j (s/|r|)^j (F_kj |r|^j) M_b[kh, j].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "../../include/fkt.h"
+#include "fkt_device.h"
+
+namespace fkt {
+namespace {
+
+constexpr int kWave = 64;
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+constexpr int cbinom(int a, int b)
+{
+    if (b < 0 || b > a) return 0;
+    long long r = 1;
+    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return (int)r;
+}
+
+// number of radial powers j = k, k+2, ..., <= p for harmonic degree k
+constexpr int nj_of(int p, int k) { return (p - k) / 2 + 1; }
+// offset of degree k's F_kj entries in a flat per-pair array
+constexpr int f_off(int p, int k)
+{
+    int o = 0;
+    for (int q = 0; q < k; ++q) o += nj_of(p, q);
+    return o;
+}
+
+// Hides a table pointer's value from the optimiser so that loads from fixed
+// offsets are issued where they are used (cheap scalar-cache hits) instead of
+// being hoisted out of a loop into dozens of long-lived registers.
+template <typename P>
+__device__ __forceinline__ P* opaque(P* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// ------------------------------------------------- expansion coefficients
+//
+// Tbar_{k,j,m} depends only on the dimension and the indices (Appendix
+// A.2), so it is evaluated at compile time:
+//   Tbar_kjm = sum_{n = max((j+k)/2, m)}^{j} A_{k,2n-j} (-2)^{2n-j} C(n, 2n-j) B_{n,m} / n!
+//   A_{k,i}  = i! (alpha + k) / (2^i ((i-k)/2)! (alpha)_{(i+k)/2+1})  (k = i mod 2)
+//   B_{n,m}  = (-1)^{n+m} (2n-2m-1)!! C(2n-m-1, m-1) / 2^n,
+// with alpha = d/2 - 1 and the binomial of the binomial expansion of eps^n
+// kept in Tbar.
+constexpr double cx_fact(int n)
+{
+    double r = 1.0;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+constexpr double cx_dfact(int n)
+{
+    double r = 1.0;
+    for (int i = n; i > 1; i -= 2) r *= i;
+    return r;
+}
+constexpr double cx_rising(double a, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= a + i;
+    return r;
+}
+constexpr double cx_binom(int a, int b)
+{
+    if (b < 0 || b > a) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return r;
+}
+constexpr double cx_pow(double x, int n)
+{
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+constexpr double cx_A(int k, int i, double alpha)
+{
+    if (k > i || ((i - k) & 1)) return 0.0;
+    return cx_fact(i) * (alpha + k) / (cx_pow(2.0, i) * cx_fact((i - k) / 2) * cx_rising(alpha, (i + k) / 2 + 1));
+}
+constexpr double cx_B(int n, int m)
+{
+    if (m < 1 || m > n) return 0.0;
+    return (((n + m) & 1) ? -1.0 : 1.0) * cx_dfact(2 * n - 2 * m - 1) * cx_binom(2 * n - m - 1, m - 1) / cx_pow(2.0, n);
+}
+constexpr double cx_tbar(int d, int k, int j, int m)
+{
+    const double alpha = 0.5 * d - 1.0;
+    double s = 0.0;
+    const int n0 = (j + k) / 2 > m ? (j + k) / 2 : m;
+    for (int n = n0; n <= j; ++n) {
+        const int i = 2 * n - j;
+        s += cx_A(k, i, alpha) * cx_pow(-2.0, i) * cx_binom(n, i) * cx_B(n, m) / cx_fact(n);
+    }
+    return s;
+}
+
+// ------------------------------------------------------------ harmonics
+//
+// All solid harmonics of degree <= P of x (D coordinates), each handed to
+// emit(integral_constant<degree>, value). A degree-k harmonic in e dims is
+//   G_{k-mu}^{lam}(x_{e-1}; rho_e^2) * H_mu(x_0..x_{e-2}),  lam = mu + (e-2)/2,
+// with G_n^lam(z; rho^2) = rho^n C_n^lam(z / rho) from the Gegenbauer
+// three-term recurrence (Appendix A.1) multiplied through by rho^n, and H_mu
+// a degree-mu harmonic of one dimension less; in two dimensions the
+// harmonics are Re and Im of (x_0 + i x_1)^m.
+//
+// With NORM the values are multiplied by the square of the orthonormal
+// normalisation times Z_k (table hn2, and 1/(2 pi), 1/pi at the base), so
+// that the product of a NORM harmonic and a plain one of the same (k, h)
+// summed over h is C_k^alpha of the cosine between the two unit vectors.
+// s2m folds that factor into the moments; m2t then needs none.
+template <int E, int P, bool NORM, typename T, class Emit>
+__device__ __forceinline__ void harmonics(const T* x, const T* rho2, const T* __restrict__ hn2, Emit& emit)
+{
+    if constexpr (E == 2) {
+        T cr = T(1), ci = T(0);
+        auto base = [&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            if constexpr (m == 0) {
+                emit(mc, NORM ? T(0.159154943091895335768884) : T(1));  // 1 / (2 pi)
+            } else {
+                const T nr = cr * x[0] - ci * x[1];
+                const T ni = cr * x[1] + ci * x[0];
+                cr = nr;
+                ci = ni;
+                if constexpr (NORM) {
+                    emit(mc, cr * T(0.318309886183790671537768));  // 1 / pi
+                    emit(mc, ci * T(0.318309886183790671537768));
+                } else {
+                    emit(mc, cr);
+                    emit(mc, ci);
+                }
+            }
+        };
+        static_for<0, P + 1>(base);
+    } else {
+        const T z = x[E - 1];
+        const T r2 = rho2[E];
+        auto level = [&](auto muc, T H) {
+            constexpr int mu = decltype(muc)::value;
+            constexpr double lam = mu + 0.5 * (E - 2);
+            T g1 = T(1), g2 = T(0);
+            auto step = [&](auto nc) {
+                constexpr int n = decltype(nc)::value;
+                T g;
+                if constexpr (n == 0) {
+                    g = T(1);
+                } else if constexpr (n == 1) {
+                    g = T(2.0 * lam) * z;
+                } else {
+                    g = T(2.0 * (n + lam - 1.0) / n) * z * g1 - T((n + 2.0 * lam - 2.0) / n) * r2 * g2;
+                }
+                if constexpr (n >= 1) {
+                    g2 = g1;
+                    g1 = g;
+                }
+                if constexpr (NORM)
+                    emit(std::integral_constant<int, mu + n>{}, H * (g * hn2[((E - 3) * (P + 1) + mu) * (P + 1) + n]));
+                else
+                    emit(std::integral_constant<int, mu + n>{}, H * g);
+            };
+            static_for<0, P - mu + 1>(step);
+        };
+        harmonics<E - 1, P, NORM, T>(x, rho2, hn2, level);
+    }
+}
+
+// ------------------------------------------------------------ FP64 helpers
+//
+// 1/sqrt(d2) for d2 > 0: hardware estimate, then one third-order correction
+// y (1 + e/2 + 3e^2/8) with e = 1 - d2 y^2.
+__device__ __forceinline__ double rsqrt_pos(double d2)
+{
+    const double y = __builtin_amdgcn_rsq(d2);
+    const double e = fma(-d2 * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+// exp(x) for finite x <= 0: x = k ln2 + f with |f| <= ln2/2 (ln2 split in a
+// high part exact in k * hi and a low part, as in fdlibm's exp), e^f by its
+// Taylor polynomial to degree 12 (truncation < 2e-16 relative), times 2^k.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    const double k = __builtin_rint(x * 1.44269504088896340736);
+    double f = fma(k, -6.93147180369123816490e-01, x);
+    f = fma(k, -1.90821492927058770002e-10, f);
+    double p = 2.08767569878680989792e-09;      // 1/12!
+    p = fma(p, f, 2.50521083854417187751e-08);  // 1/11!
+    p = fma(p, f, 2.75573192239858906526e-07);  // 1/10!
+    p = fma(p, f, 2.75573192239858906526e-06);  // 1/9!
+    p = fma(p, f, 2.48015873015873015873e-05);  // 1/8!
+    p = fma(p, f, 1.98412698412698412698e-04);  // 1/7!
+    p = fma(p, f, 1.38888888888888888889e-03);  // 1/6!
+    p = fma(p, f, 8.33333333333333333333e-03);  // 1/5!
+    p = fma(p, f, 4.16666666666666666667e-02);  // 1/4!
+    p = fma(p, f, 1.66666666666666666667e-01);  // 1/3!
+    p = fma(p, f, 0.5);
+    p = fma(p, f, 1.0);
+    p = fma(p, f, 1.0);
+    return __builtin_ldexp(p, (int)k);
+}
+
+// ------------------------------------------------------- radial derivatives
+//
+// K^(m)(r), m = 0..P, in FP64 (closed forms / recurrences per kernel).
+template <int KIND, int P>
+__device__ __forceinline__ void radial_derivs(const DevPlan& a, double r, double (&D)[P + 1])
+{
+    const double var = a.var;
+    if constexpr (KIND == FKT_GAUSSIAN) {  // exp(-u^2), u = r s: d^m/dr^m = (-s)^m H_m(u) exp(-u^2)
+        const double s = 0.70710678118654752440 / a.ell, u = r * s, e = var * exp_nonpos(-u * u);
+        double h1 = 1.0, h2 = 0.0, sc = 1.0;
+#pragma unroll
+        for (int m = 0; m <= P; ++m) {
+            double h = (m == 0) ? 1.0 : 2.0 * u * h1 - 2.0 * (m - 1) * h2;
+            if (m >= 1) { h2 = h1; h1 = h; }
+            D[m] = sc * h * e;
+            sc *= -s;
+        }
+    } else if constexpr (KIND == FKT_EXPONENTIAL) {
+        const double c = 1.0 / a.ell, e = var * exp_nonpos(-c * r);
+        double sc = 1.0;
+#pragma unroll
+        for (int m = 0; m <= P; ++m) { D[m] = sc * e; sc *= -c; }
+    } else if constexpr (KIND == FKT_MATERN32) {  // (1 + cr) e^{-cr}: (-c)^m (1 - m + cr) e^{-cr}
+        const double c = 1.7320508075688772935 / a.ell, cr = c * r, e = var * exp_nonpos(-cr);
+        double sc = 1.0;
+#pragma unroll
+        for (int m = 0; m <= P; ++m) { D[m] = sc * (1.0 - m + cr) * e; sc *= -c; }
+    } else if constexpr (KIND == FKT_MATERN52) {  // Q e^{-cr}, Q = 1 + cr + (cr)^2/3 (Leibniz rule)
+        const double c = 2.2360679774997896964 / a.ell, cr = c * r, e = var * exp_nonpos(-cr);
+        const double q0 = 1.0 + cr + cr * cr / 3.0, q1 = c + 2.0 * c * cr / 3.0, q2 = 2.0 * c * c / 3.0;
+        double s0 = 1.0, s1 = 0.0, s2 = 0.0;  // (-c)^m, (-c)^(m-1), (-c)^(m-2)
+#pragma unroll
+        for (int m = 0; m <= P; ++m) {
+            D[m] = e * (s0 * q0 + m * s1 * q1 + 0.5 * m * (m - 1) * s2 * q2);
+            s2 = s1;
+            s1 = (m == 0) ? 1.0 : s1 * -c;
+            s0 *= -c;
+        }
+    } else if constexpr (KIND == FKT_RATQUAD || KIND == FKT_CAUCHY) {
+        // w(r+h)^beta, w quadratic in h: J.C.P. Miller's power-series recurrence
+        double g0, g1, g2, beta;
+        if constexpr (KIND == FKT_RATQUAD) {
+            const double c = 0.5 / (a.alpha * a.ell * a.ell);
+            g0 = 1.0 + c * r * r; g1 = 2.0 * c * r; g2 = c; beta = -a.alpha;
+        } else {
+            const double c = 1.0 / (a.ell * a.ell);
+            g0 = 1.0 + c * r * r; g1 = 2.0 * c * r; g2 = c; beta = -1.0;
+        }
+        const double ig0 = 1.0 / g0;
+        double f[P + 1];
+        if constexpr (KIND == FKT_CAUCHY) f[0] = ig0; else f[0] = pow(g0, beta);
+        double fact = 1.0;
+        D[0] = var * f[0];
+#pragma unroll
+        for (int m = 1; m <= P; ++m) {
+            double acc = ((beta + 1.0) - m) * g1 * f[m - 1];
+            if (m >= 2) acc += (2.0 * (beta + 1.0) - m) * g2 * f[m - 2];
+            f[m] = acc * ig0 / m;
+            fact *= m;
+            D[m] = var * fact * f[m];
+        }
+    } else if constexpr (KIND == FKT_LAPLACE) {  // 1/r: (-1)^m m! / r^(m+1)
+        const double ir = 1.0 / r;
+        D[0] = var * ir;
+#pragma unroll
+        for (int m = 1; m <= P; ++m) D[m] = D[m - 1] * (-(double)m) * ir;
+    } else {
+        static_assert(KIND == FKT_GAUSSIAN, "unknown kernel kind");
+    }
+}
+
+template <typename T> __device__ __forceinline__ const T* hn_ptr(const DevPlan& a);
+template <> __device__ __forceinline__ const double* hn_ptr<double>(const DevPlan& a) { return a.hn64; }
+template <> __device__ __forceinline__ const float* hn_ptr<float>(const DevPlan& a) { return a.hn32; }
+
+// ------------------------------------------------------------------ gather
+//
+// Packed source records in tree order: D coordinates then the weight of the
+// current right-hand-side column, stride src_stride(D) elements.
+constexpr int src_stride(int d) { return d == 3 ? 4 : 6; }
+
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict__ perm, const T* __restrict__ pts,
+                                                const T* __restrict__ x, int nrhs, int col, T* __restrict__ src)
+{
+    constexpr int S = src_stride(D);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int a = 0; a < D; ++a) src[(size_t)i * S + a] = pts[(size_t)i * D + a];
+    src[(size_t)i * S + D] = x[perm[i] * nrhs + col];
+#pragma unroll
+    for (int a = D + 1; a < S; ++a) src[(size_t)i * S + a] = T(0);
+}
+
+// --------------------------------------------------------------------- s2m
+//
+// Moments of every far node straight from its own points (Algorithm 1,
+// source2mult; no translation between levels). One wave per work unit of at
+// most kUnitPoints points of one node; each lane accumulates its points'
+// contributions to moment entries [C0, C1) in registers, then the wave sums.
+// Moments carry the harmonics' normalisation (see harmonics<NORM>).
+template <int D, int P, typename T, int C0, int C1>
+__global__ __launch_bounds__(kWave) void k_s2m(const DevPlan a, const T* __restrict__ src, T* __restrict__ mom,
+                                               T* __restrict__ part)
+{
+    constexpr int R = cbinom(P + D, D);
+    constexpr int NC = C1 - C0;
+    constexpr int S = src_stride(D);
+    const int u = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int slot = a.unit_slot[u];
+    const int beg = a.unit_begin[u], end = a.unit_end[u];
+    double c[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) c[i] = a.slot_ctr[slot * D + i];
+    const double is = 1.0 / a.slot_scale[slot];
+    const T* __restrict__ hn2 = hn_ptr<T>(a);
+
+    T acc[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) acc[i] = T(0);
+
+    for (int s = beg + lane; s < end; s += kWave) {
+        const T* __restrict__ hnl = opaque(hn2);
+        T x[D], rho2[D + 1];
+        rho2[0] = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            x[i] = T((a.pts64[(size_t)s * D + i] - c[i]) * is);
+            rho2[i + 1] = rho2[i] + x[i] * x[i];
+        }
+        T q[P / 2 + 1];
+        q[0] = src[(size_t)s * S + D];
+#pragma unroll
+        for (int i = 1; i <= P / 2; ++i) q[i] = q[i - 1] * rho2[D];
+        int off = 0;
+        auto emit = [&](auto kc, T v) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int nj = nj_of(P, k);
+            auto put = [&](auto jc) {
+                constexpr int jj = decltype(jc)::value;
+                const int idx = off + jj;
+                if (idx >= C0 && idx < C1) acc[idx - C0] += v * q[jj];
+            };
+            static_for<0, nj>(put);
+            off += nj;
+        };
+        harmonics<D, P, true, T>(x, rho2, hnl, emit);
+    }
+
+    const int dst = a.unit_dst[u];
+    T* out = dst >= 0 ? mom + (size_t)dst * R : part + (size_t)(-1 - dst) * R;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const T v = wave_sum(acc[i]);
+        if (lane == 0) out[C0 + i] = v;
+    }
+}
+
+// Nodes split over several units: moments = ordered sum of the partials.
+template <typename T>
+__global__ __launch_bounds__(256) void k_s2m_reduce(int nred, int R, const int* __restrict__ red_slot,
+                                                    const int* __restrict__ red_off, const T* __restrict__ part,
+                                                    T* __restrict__ mom)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)nred * R) return;
+    const int r = (int)(g / R), i = (int)(g % R);
+    T s = T(0);
+    for (int q = red_off[r]; q < red_off[r + 1]; ++q) s += part[(size_t)q * R + i];
+    mom[(size_t)red_slot[r] * R + i] = s;
+}
+
+// --------------------------------------------------------------------- m2t
+//
+// Far field of every target: for each far node of its own walk, the plain
+// harmonics of the unit vector towards the target contracted with the
+// node's moments, S_kj = sum_h Y_kh(r^) M_b[kh, j], then the radial
+// functions (FP64): z += sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj.
+//
+// The wave walks its block's far list; each entry's moments are staged in
+// LDS (two buffers: the next entry's moments are fetched into registers
+// while the current entry computes) and read back as broadcasts. The Tbar
+// table sits in LDS for the whole kernel.
+template <int D, int P>
+constexpr int m2t_pf()  // moments per lane per prefetch
+{
+    return (cbinom(P + D, D) + kWave - 1) / kWave;
+}
+
+template <int D, int P, int KIND, typename T>
+__global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zfar)
+{
+    constexpr int R = cbinom(P + D, D);
+    constexpr int NF = f_off(P, P + 1);
+    constexpr int PF = m2t_pf<D, P>();
+    __shared__ T smom[2][PF * kWave];
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
+    const bool valid = lane < cnt;
+    const int t = tb + (valid ? lane : 0);
+    double tx[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)t * D + i];
+
+    const int e0 = a.far_off[blk], e1 = a.far_off[blk + 1];
+    T pre[PF];
+    auto fetch = [&](int e) {
+        const T* __restrict__ src = mom + (size_t)a.far_slot[e] * R;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int i = q * kWave + lane;
+            pre[q] = (i < R) ? src[i] : T(0);
+        }
+    };
+    if (e0 < e1) fetch(e0);
+
+    double acc = 0.0;
+    int buf = 0;
+    for (int e = e0; e < e1; ++e) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) smom[buf][q * kWave + lane] = pre[q];
+        __syncthreads();
+        const uint64_t msk = a.far_mask[e];
+        const int slot = a.far_slot[e];
+        if (e + 1 < e1) fetch(e + 1);
+        if ((msk >> lane) & 1) {
+            double r[D], r2 = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                r[i] = tx[i] - a.slot_ctr[slot * D + i];
+                r2 = fma(r[i], r[i], r2);
+            }
+            const double ir = rsqrt_pos(r2);  // r2 > 0: a far target is never at the centre
+            const double rr = r2 * ir;
+
+            // angular part: S_kj over harmonics of r^ (|r^| = 1 at the top level)
+            T x[D], rho2[D + 1];
+            rho2[0] = T(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                x[i] = T(r[i] * ir);
+                rho2[i + 1] = rho2[i] + x[i] * x[i];
+            }
+            rho2[D] = T(1);
+            T Skj[NF];
+#pragma unroll
+            for (int i = 0; i < NF; ++i) Skj[i] = T(0);
+            const T* M = smom[buf];
+            int off = 0;
+            auto emit = [&](auto kc, T yv) {
+                constexpr int k = decltype(kc)::value;
+                constexpr int nj = nj_of(P, k);
+                auto dot = [&](auto jc) {
+                    constexpr int jj = decltype(jc)::value;
+                    Skj[f_off(P, k) + jj] += yv * M[off + jj];
+                };
+                static_for<0, nj>(dot);
+                off += nj;
+                // keep each harmonic's LDS reads next to their use
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            harmonics<D, P, false, T>(x, rho2, (const T*)nullptr, emit);
+
+            // radial part (FP64): F_kj(r) r^j = [j=0] K + sum_m K^(m) r^m Tbar_kjm
+            double Dm[P + 1];
+            radial_derivs<KIND, P>(a, rr, Dm);
+            double um[P + 1];
+            um[0] = Dm[0];
+            double rp = 1.0;
+#pragma unroll
+            for (int m = 1; m <= P; ++m) { rp *= rr; um[m] = Dm[m] * rp; }
+            const double v = a.slot_scale[slot] * ir;  // s / |r| < theta
+            double vp[P + 1];
+            vp[0] = 1.0;
+#pragma unroll
+            for (int j = 1; j <= P; ++j) vp[j] = vp[j - 1] * v;
+            auto radial_k = [&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                auto radial_j = [&](auto jc) {
+                    constexpr int jj = decltype(jc)::value;
+                    constexpr int j = k + 2 * jj;
+                    double f = (j == 0) ? um[0] : 0.0;
+                    auto term = [&](auto mc) {
+                        constexpr int m = decltype(mc)::value + 1;
+                        constexpr double c = cx_tbar(D, k, j, m);
+                        f = fma(um[m], c, f);
+                    };
+                    static_for<0, j>(term);
+                    acc = fma(vp[j] * f, (double)Skj[f_off(P, k) + jj], acc);
+                };
+                static_for<0, nj_of(P, k)>(radial_j);
+            };
+            static_for<0, P + 1>(radial_k);
+        }
+        buf ^= 1;
+    }
+    if (valid) zfar[t] = T(acc);
+}
+
+// -------------------------------------------------------------- near field
+//
+// Dense near blocks (Algorithm 1, near_mat): for each near leaf of the
+// block's list, the lanes whose target has that leaf in its own near set
+// sum K(|t - x_s|) x_s over the leaf's points; the points stream through
+// scalar registers. The far-field result is added and the sum scattered to
+// the caller's order.
+template <int KIND, typename T>
+struct NearKernel;
+
+template <> struct NearKernel<FKT_GAUSSIAN, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double) { return exp_nonpos(c0 * d2); }
+};
+template <> struct NearKernel<FKT_EXPONENTIAL, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    {
+        const double r = d2 > 0.0 ? d2 * rsqrt_pos(d2) : 0.0;
+        return exp_nonpos(c0 * r);
+    }
+};
+template <> struct NearKernel<FKT_MATERN32, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    {
+        const double ar = d2 > 0.0 ? c0 * (d2 * rsqrt_pos(d2)) : 0.0;
+        return (1.0 + ar) * exp_nonpos(-ar);
+    }
+};
+template <> struct NearKernel<FKT_MATERN52, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    {
+        const double ar = d2 > 0.0 ? c0 * (d2 * rsqrt_pos(d2)) : 0.0;
+        return (1.0 + ar + ar * ar * (1.0 / 3.0)) * exp_nonpos(-ar);
+    }
+};
+template <> struct NearKernel<FKT_RATQUAD, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double c1) { return pow(1.0 + c0 * d2, c1); }
+};
+template <> struct NearKernel<FKT_CAUCHY, double> {
+    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    {
+        const double b = 1.0 + c0 * d2;  // >= 1
+        double y = __builtin_amdgcn_rcp(b);
+        y = fma(fma(-b, y, 1.0), y, y);
+        return fma(fma(-b, y, 1.0), y, y);
+    }
+};
+template <> struct NearKernel<FKT_LAPLACE, double> {
+    static __device__ __forceinline__ double eval(double d2, double, double)
+    {
+        const double y = rsqrt_pos(d2);
+        return d2 > 0.0 ? y : 0.0;
+    }
+};
+
+// FP32: hardware transcendental approximations (v_exp_f32 / v_log_f32 are
+// base 2; c0 is pre-scaled by log2(e) where an exponential follows).
+template <> struct NearKernel<FKT_GAUSSIAN, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float) { return __builtin_amdgcn_exp2f(c0 * d2); }
+};
+template <> struct NearKernel<FKT_EXPONENTIAL, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float)
+    {
+        return __builtin_amdgcn_exp2f(c0 * __builtin_amdgcn_sqrtf(d2));
+    }
+};
+template <> struct NearKernel<FKT_MATERN32, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    {
+        const float r = __builtin_amdgcn_sqrtf(d2);
+        return (1.0f + c1 * r) * __builtin_amdgcn_exp2f(c0 * r);
+    }
+};
+template <> struct NearKernel<FKT_MATERN52, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    {
+        const float ar = c1 * __builtin_amdgcn_sqrtf(d2);
+        return (1.0f + ar + ar * ar * (1.0f / 3.0f)) * __builtin_amdgcn_exp2f(c0 * ar);
+    }
+};
+template <> struct NearKernel<FKT_RATQUAD, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    {
+        return __builtin_amdgcn_exp2f(c1 * __builtin_amdgcn_logf(1.0f + c0 * d2));
+    }
+};
+template <> struct NearKernel<FKT_CAUCHY, float> {
+    static __device__ __forceinline__ float eval(float d2, float c0, float)
+    {
+        return __builtin_amdgcn_rcpf(1.0f + c0 * d2);
+    }
+};
+template <> struct NearKernel<FKT_LAPLACE, float> {
+    static __device__ __forceinline__ float eval(float d2, float, float)
+    {
+        return d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
+    }
+};
+
+template <int D, int KIND, typename T>
+__global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, const T* __restrict__ zfar,
+                                                T* __restrict__ y, int nrhs, int col, T c0, T c1, T scale)
+{
+    constexpr int S = src_stride(D);
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
+    const bool valid = lane < cnt;
+    const int t = tb + (valid ? lane : 0);
+    T tx[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) tx[i] = src[(size_t)t * S + i];
+    T acc0 = T(0), acc1 = T(0);
+    auto pair = [&](const T* __restrict__ q) {
+        T d2 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const T u = tx[i] - q[i];
+            d2 = fma(u, u, d2);
+        }
+        return NearKernel<KIND, T>::eval(d2, c0, c1) * q[D];
+    };
+    const int e0 = a.near_off[blk], e1 = a.near_off[blk + 1];
+    for (int e = e0; e < e1; ++e) {
+        const uint64_t msk = a.near_mask[e];
+        if (!((msk >> lane) & 1)) continue;
+        const T* __restrict__ q = src + (size_t)a.near_beg[e] * S;
+        const int m = a.near_end[e] - a.near_beg[e];
+        int s = 0;
+        for (; s + 4 <= m; s += 4) {
+            acc0 += pair(q + (s + 0) * S);
+            acc1 += pair(q + (s + 1) * S);
+            acc0 += pair(q + (s + 2) * S);
+            acc1 += pair(q + (s + 3) * S);
+        }
+        for (; s < m; ++s) acc0 += pair(q + s * S);
+    }
+    if (valid) {
+        T out = scale * (acc0 + acc1);
+        if (zfar) out += zfar[t];
+        y[a.perm[t] * nrhs + col] = out;
+    }
+}
+
+// ------------------------------------------------- built orders per dimension
+
+template <int D> struct PMax;
+template <> struct PMax<3> { static constexpr int value = 8; };
+template <> struct PMax<4> { static constexpr int value = 6; };
+template <> struct PMax<5> { static constexpr int value = 6; };
+
+constexpr int kChunk = 128;  // s2m moment entries accumulated per lane and launch
+
+}  // namespace
+
+// Launchers implemented in the per-stage translation units.
+bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
+bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
+#define FKT_DECLARE_M2T(K) bool launch_m2t_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
+FKT_DECLARE_M2T(0)
+FKT_DECLARE_M2T(1)
+FKT_DECLARE_M2T(2)
+FKT_DECLARE_M2T(3)
+FKT_DECLARE_M2T(4)
+FKT_DECLARE_M2T(5)
+FKT_DECLARE_M2T(6)
+#undef FKT_DECLARE_M2T
+
+}  // namespace fkt

@@ -1,0 +1,127 @@
+// Orchestration of one MVM column (gather, s2m, m2t, near field) and the
+// near-field launches.
+#include "fkt_kernels.h"
+
+namespace fkt {
+
+bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+{
+    switch (kind) {
+    case 0: return launch_m2t_kind0(a, wk, prec, s);
+    case 1: return launch_m2t_kind1(a, wk, prec, s);
+    case 2: return launch_m2t_kind2(a, wk, prec, s);
+    case 3: return launch_m2t_kind3(a, wk, prec, s);
+    case 4: return launch_m2t_kind4(a, wk, prec, s);
+    case 5: return launch_m2t_kind5(a, wk, prec, s);
+    case 6: return launch_m2t_kind6(a, wk, prec, s);
+    default: return false;
+    }
+}
+
+namespace {
+
+// near-field kernel constants (FP32 variants fold log2(e) into c0)
+template <typename T>
+void near_consts(const DevPlan& a, T& c0, T& c1)
+{
+    const bool f32 = std::is_same<T, float>::value;
+    const double log2e = 1.4426950408889634074;
+    double k0 = 0.0, k1 = 0.0;
+    switch (a.kind) {
+    case FKT_GAUSSIAN: k0 = -0.5 / (a.ell * a.ell) * (f32 ? log2e : 1.0); break;
+    case FKT_EXPONENTIAL: k0 = -1.0 / a.ell * (f32 ? log2e : 1.0); break;
+    case FKT_MATERN32:
+    case FKT_MATERN52: {
+        const double c = (a.kind == FKT_MATERN32 ? 1.7320508075688772935 : 2.2360679774997896964) / a.ell;
+        if (f32) { k0 = -c * log2e; k1 = c; if (a.kind == FKT_MATERN52) k0 = -log2e; }
+        else k0 = c;
+        break;
+    }
+    case FKT_RATQUAD: k0 = 0.5 / (a.alpha * a.ell * a.ell); k1 = -a.alpha; break;
+    case FKT_CAUCHY: k0 = 1.0 / (a.ell * a.ell); break;
+    default: break;
+    }
+    c0 = (T)k0;
+    c1 = (T)k1;
+}
+
+template <int D, typename T>
+bool run_near_d(const DevPlan& a, const T* src, const T* zfar, T* y, int nrhs, int col, hipStream_t s)
+{
+    T c0, c1;
+    near_consts<T>(a, c0, c1);
+    const T scale = (T)a.var;
+    dim3 g(a.nblocks), b(kWave);
+    switch (a.kind) {
+#define FKT_NEAR_CASE(K) \
+    case K: hipLaunchKernelGGL((k_near<D, K, T>), g, b, 0, s, a, src, zfar, y, nrhs, col, c0, c1, scale); return true;
+        FKT_NEAR_CASE(FKT_GAUSSIAN)
+        FKT_NEAR_CASE(FKT_EXPONENTIAL)
+        FKT_NEAR_CASE(FKT_MATERN32)
+        FKT_NEAR_CASE(FKT_MATERN52)
+        FKT_NEAR_CASE(FKT_RATQUAD)
+        FKT_NEAR_CASE(FKT_CAUCHY)
+        FKT_NEAR_CASE(FKT_LAPLACE)
+#undef FKT_NEAR_CASE
+    default: return false;
+    }
+}
+
+template <typename T>
+hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int nrhs, int col, hipStream_t s,
+                      hipEvent_t* ev)
+{
+    const T* pts = std::is_same<T, float>::value ? (const T*)a.pts32 : (const T*)a.pts64;
+    T* src = (T*)wk.src;
+    const dim3 gg((a.n + 255) / 256), gb(256);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    switch (a.d) {
+    case 3: hipLaunchKernelGGL((k_gather<3, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (ev) (void)hipEventRecord(ev[1], s);
+    const T* zfar = nullptr;
+    const int prec = std::is_same<T, float>::value ? 1 : 0;
+    if (a.nslots > 0) {
+        if (!launch_s2m(a, wk, prec, s)) return hipErrorInvalidValue;
+        if (ev) (void)hipEventRecord(ev[2], s);
+        if (!launch_m2t(a.kind, a, wk, prec, s)) return hipErrorInvalidValue;
+        zfar = (const T*)wk.zfar;
+    } else if (ev) {
+        (void)hipEventRecord(ev[2], s);
+    }
+    if (ev) (void)hipEventRecord(ev[3], s);
+    bool ok = false;
+    switch (a.d) {
+    case 3: ok = run_near_d<3, T>(a, src, zfar, y, nrhs, col, s); break;
+    case 4: ok = run_near_d<4, T>(a, src, zfar, y, nrhs, col, s); break;
+    case 5: ok = run_near_d<5, T>(a, src, zfar, y, nrhs, col, s); break;
+    default: break;
+    }
+    if (!ok) return hipErrorInvalidValue;
+    if (ev) (void)hipEventRecord(ev[4], s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool far_supported(int d, int p)
+{
+    switch (d) {
+    case 3: return p >= 0 && p <= PMax<3>::value;
+    case 4: return p >= 0 && p <= PMax<4>::value;
+    case 5: return p >= 0 && p <= PMax<5>::value;
+    default: return false;
+    }
+}
+
+hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col, int prec,
+                             hipStream_t s, hipEvent_t* ev)
+{
+    if (prec == 1) return mvm_column<float>(a, wk, (const float*)x, (float*)y, nrhs, col, s, ev);
+    return mvm_column<double>(a, wk, (const double*)x, (double*)y, nrhs, col, s, ev);
+}
+
+}  // namespace fkt

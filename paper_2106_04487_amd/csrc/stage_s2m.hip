@@ -1,0 +1,61 @@
+// s2m launches (source-to-multipole moments and partial-sum reduction).
+#include "fkt_kernels.h"
+
+namespace fkt {
+namespace {
+
+template <int D, int P, typename T, int C0>
+void launch_s2m_chunks(const DevPlan& a, const T* src, T* mom, T* part, hipStream_t s)
+{
+    constexpr int R = cbinom(P + D, D);
+    if constexpr (C0 < R) {
+        constexpr int C1 = (C0 + kChunk < R) ? C0 + kChunk : R;
+        hipLaunchKernelGGL((k_s2m<D, P, T, C0, C1>), dim3(a.nunits), dim3(kWave), 0, s, a, src, mom, part);
+        launch_s2m_chunks<D, P, T, C1>(a, src, mom, part, s);
+    }
+}
+
+template <int D, int P, typename T>
+void s2m_dp(const DevPlan& a, const DevWork& wk, hipStream_t s)
+{
+    constexpr int R = cbinom(P + D, D);
+    T* mom = (T*)wk.mom;
+    T* part = (T*)wk.part;
+    launch_s2m_chunks<D, P, T, 0>(a, (const T*)wk.src, mom, part, s);
+    if (a.nred > 0) {
+        const int64_t tot = (int64_t)a.nred * R;
+        hipLaunchKernelGGL((k_s2m_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a.nred, R,
+                           a.red_slot, a.red_off, part, mom);
+    }
+}
+
+template <int D, typename T, int P = 0>
+bool s2m_d(const DevPlan& a, const DevWork& wk, hipStream_t s)
+{
+    if constexpr (P > PMax<D>::value) {
+        return false;
+    } else {
+        if (a.p == P) { s2m_dp<D, P, T>(a, wk, s); return true; }
+        return s2m_d<D, T, P + 1>(a, wk, s);
+    }
+}
+
+template <typename T>
+bool s2m_t(const DevPlan& a, const DevWork& wk, hipStream_t s)
+{
+    switch (a.d) {
+    case 3: return s2m_d<3, T>(a, wk, s);
+    case 4: return s2m_d<4, T>(a, wk, s);
+    case 5: return s2m_d<5, T>(a, wk, s);
+    default: return false;
+    }
+}
+
+}  // namespace
+
+bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+{
+    return prec == 1 ? s2m_t<float>(a, wk, s) : s2m_t<double>(a, wk, s);
+}
+
+}  // namespace fkt
