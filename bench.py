@@ -28,8 +28,8 @@ import fkt_workloads as W  # noqa: E402
 
 # largest theta on a 0.05 grid with rel err <= 1e-5 vs dense FP64 at the
 # default workload (measured by the error sweep)
-DEFAULT_THETA = {("laplace", "f64"): 0.35, ("laplace", "f32"): 0.35,
-                 ("matern32", "f64"): 0.25, ("matern32", "f32"): 0.25}
+DEFAULT_THETA = {("laplace", "f64"): 0.32, ("laplace", "f32"): 0.32,
+                 ("matern32", "f64"): 0.26, ("matern32", "f32"): 0.26}
 KERNEL_KW = {"laplace": {}, "matern32": {"lengthscale": 0.05}}
 ORACLE_KIND = {"laplace": ("power", {"shape": 1.0}), "matern32": ("matern32", {"lengthscale": 0.05})}
 

@@ -24,6 +24,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_2106_04487_amd/build.py` "
                       "(there is no fallback implementation)")
 
+# PyTorch brings its own HIP runtime; load it first so that libfkt.so binds to
+# the same runtime instance as the tensors and streams it is handed.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 KERNELS = {"gaussian": 0, "exponential": 1, "matern32": 2, "matern52": 3,

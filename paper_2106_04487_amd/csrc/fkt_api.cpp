@@ -161,6 +161,7 @@ static fkt_status upload_plan(fkt_plan_t P)
     a.nslots = (int)L.slot_node.size();
     a.nunits = (int)L.unit_slot.size();
     a.nred = (int)L.red_slot.size();
+    a.nnear_units = (int)L.nu_beg.size();
     a.kind = (int)P->kern.kind;
     a.ell = P->kern.lengthscale;
     a.alpha = P->kern.alpha;
@@ -173,13 +174,15 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(T.perm, a.perm);
     FKT_UP(L.blk_begin, a.blk_begin);
     FKT_UP(L.blk_count, a.blk_count);
-    FKT_UP(L.near_off, a.near_off);
-    FKT_UP(L.near_beg, a.near_beg);
-    FKT_UP(L.near_end, a.near_end);
-    FKT_UP(L.near_mask, a.near_mask);
-    FKT_UP(L.far_off, a.far_off);
-    FKT_UP(L.far_slot, a.far_slot);
-    FKT_UP(L.far_mask, a.far_mask);
+    FKT_UP(L.near_tgt, a.near_tgt);
+    FKT_UP(L.nu_beg, a.nu_beg);
+    FKT_UP(L.nu_end, a.nu_end);
+    FKT_UP(L.nu_toff, a.nu_toff);
+    FKT_UP(L.nu_tcnt, a.nu_tcnt);
+    FKT_UP(L.job_off, a.job_off);
+    FKT_UP(L.job_noff, a.job_noff);
+    FKT_UP(L.job_nodes, a.job_nodes);
+    FKT_UP(L.job_pairs, a.job_pairs);
     FKT_UP(L.slot_ctr, a.slot_ctr);
     FKT_UP(L.slot_scale, a.slot_scale);
     FKT_UP(L.unit_slot, a.unit_slot);
@@ -199,7 +202,7 @@ static fkt_status upload_plan(fkt_plan_t P)
 #undef FKT_UP
     const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
     if ((e = P->alloc(es * P->n * (P->d == 3 ? 4 : 6), &P->wk.src)) != hipSuccess) return hip_fail(e, "work buffer");
-    if ((e = P->alloc(es * P->n, &P->wk.zfar)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * P->n, &P->wk.zacc)) != hipSuccess) return hip_fail(e, "work buffer");
     if ((e = P->alloc(es * L.slot_node.size() * P->tab.rank, &P->wk.mom)) != hipSuccess)
         return hip_fail(e, "moment buffer");
     if ((e = P->alloc(es * L.npartials * P->tab.rank, &P->wk.part)) != hipSuccess)
@@ -244,7 +247,13 @@ fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int le
         P->kern = k;
         P->opt = opt;
         fkt::build_tree(points, n, d, leaf_size, opt.max_depth, P->T);
-        fkt::build_lists(P->T, opt.theta, P->L, P->st);
+        fkt::build_lists(P->T, opt.theta,
+                         fkt::m2t_max_job_nodes(d, order, opt.prec == FKT_F32 ? (int)sizeof(float) : (int)sizeof(double)),
+                         P->L, P->st);
+        if (P->L.near_tgt.size() > (size_t)0x7fffffff) {
+            delete P;
+            return fail(FKT_EUNSUPPORTED, "near sets exceed 2^31 (target, leaf) pairs; use fewer points or a smaller theta");
+        }
         fkt::build_tables(d, order, P->tab);
     } catch (const std::bad_alloc&) {
         delete P;

@@ -9,7 +9,7 @@ namespace fkt {
 
 // Read-only plan data on the device (all pointers are device memory).
 struct DevPlan {
-    int n, d, p, rank, nblocks, nslots, nunits, nred;
+    int n, d, p, rank, nblocks, nslots, nunits, nred, nnear_units;
     int kind;
     double ell, alpha, var;       // kernel parameters
     const double* pts64;          // [n][d] tree-ordered coordinates
@@ -17,13 +17,15 @@ struct DevPlan {
     const int64_t* perm;          // tree position -> original index
     const int* blk_begin;         // per 64-target block: first tree position
     const int* blk_count;         //   and number of targets (<= 64)
-    const int* near_off;          // [nblocks + 1] into near_*
-    const int* near_beg;          // source leaf point range
-    const int* near_end;
-    const uint64_t* near_mask;    // lanes whose target has this leaf in N_l
-    const int* far_off;           // [nblocks + 1] into far_*
-    const int* far_slot;          // far node (compact slot id)
-    const uint64_t* far_mask;     // lanes whose target is in F_b
+    const int* near_tgt;          // near sets N_l: target positions grouped by leaf
+    const int* nu_beg;            // near units: source leaf point range
+    const int* nu_end;
+    const int* nu_toff;           //   and their targets near_tgt[toff, toff + tcnt)
+    const int* nu_tcnt;
+    const int* job_off;           // [nblocks + 1] far-field jobs of each block
+    const int* job_noff;          // [njobs + 1] into job_nodes
+    const int* job_nodes;         // far-node slots of each job
+    const uint16_t* job_pairs;    // [njobs][64] target lane | job node index << 6
     const double* slot_ctr;       // [nslots][d] expansion centres
     const double* slot_scale;     // [nslots] node radius (1 when zero)
     const int* unit_slot;         // s2m units: node slot
@@ -40,10 +42,20 @@ struct DevPlan {
 // Per-call work buffers (device) for one right-hand-side column.
 struct DevWork {
     void* src;    // [n][4 or 6] tree-ordered packed (coordinates, weight) records
-    void* zfar;   // [n] far-field result, tree order
+    void* zacc;   // [n] per-target sum (far field stored, near field added), tree order
     void* mom;    // [nslots][rank]
     void* part;   // [npartials][rank]
 };
+
+// Far nodes per 64-lane far-field job: as many node moment sets as fit in
+// 8 KB of LDS (two such buffers per wave), between 1 and 8.
+constexpr int m2t_max_job_nodes(int d, int p, int elem_bytes)
+{
+    long long r = 1;
+    for (int i = 1; i <= d; ++i) r = r * (p + i) / i;  // C(p+d, d)
+    const long long n = 8192 / (r * elem_bytes);
+    return n < 1 ? 1 : (n > 8 ? 8 : (int)n);
+}
 
 // Whether kernels for (d, p) are compiled into the library.
 bool far_supported(int d, int p);

@@ -18,6 +18,8 @@ namespace fkt {
 constexpr int kBlock = 64;
 // s2m work units: at most this many consecutive points of one node.
 constexpr int kUnitPoints = 1024;
+// near-field work units: one source leaf and at most this many of its targets.
+constexpr int kNearUnitTargets = 256;
 
 // Binary space-partition tree (paper Sec. 3.1), nodes in preorder.
 struct Tree {
@@ -35,13 +37,24 @@ struct Tree {
 
 // Near/far interaction lists per 64-target block, with lane masks: bit i of
 // a mask is set when target (block begin + i) has that entry in its own
-// near or far set (paper eq. accparam, per target).
+// near or far set (paper eq. accparam, per target). The far lists drive the
+// multipole-to-target kernel; the near lists are transposed into the
+// source-major near sets N_l (Sec. 3.2) that drive the near-field kernel.
 struct Lists {
     std::vector<int32_t> blk_begin, blk_count;
-    std::vector<int32_t> near_off, near_beg, near_end;  // near_off: [nblocks + 1]
-    std::vector<uint64_t> near_mask;
-    std::vector<int32_t> far_off, far_slot;             // far_off: [nblocks + 1]
-    std::vector<uint64_t> far_mask;
+    std::vector<int32_t> near_off, near_beg, near_end;  // near_off: [nblocks + 1] (host only)
+    std::vector<uint64_t> near_mask;                    // (host only)
+    std::vector<int32_t> near_tgt;                      // N_l: target positions, by leaf
+    std::vector<int32_t> nu_beg, nu_end;                // near units: source leaf range
+    std::vector<int32_t> nu_toff, nu_tcnt;              //   and their slice of near_tgt
+    std::vector<int32_t> far_off, far_slot;             // far_off: [nblocks + 1] (host only)
+    std::vector<uint64_t> far_mask;                     // (host only)
+    // far field packed into 64-lane jobs: every (target, far node) pair of a
+    // block gets its own lane; a job holds pairs of at most max_job_nodes nodes
+    std::vector<int32_t> job_off;                       // [nblocks + 1] jobs of each block
+    std::vector<int32_t> job_noff, job_nodes;           // [njobs + 1] node slots of each job
+    std::vector<uint16_t> job_pairs;                    // [njobs][64]: lane | node index << 6
+    int max_job_nodes = 0;
     std::vector<int32_t> slot_node;                     // far-node slot -> node id
     std::vector<double> slot_ctr, slot_scale;           // [nslots][d], [nslots]
     // s2m work units (node slot, point range) and the moment/partial they fill
@@ -60,7 +73,7 @@ struct Tables {
 };
 
 void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T);
-void build_lists(const Tree& T, double theta, Lists& L, fkt_plan_stats& st);
+void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 void build_tables(int d, int p, Tables& tab);
 int64_t binom(int64_t a, int64_t b);
 

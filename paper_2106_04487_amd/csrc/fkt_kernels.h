@@ -429,58 +429,71 @@ __global__ __launch_bounds__(256) void k_s2m_reduce(int nred, int R, const int* 
 // node's moments, S_kj = sum_h Y_kh(r^) M_b[kh, j], then the radial
 // functions (FP64): z += sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj.
 //
-// The wave walks its block's far list; each entry's moments are staged in
-// LDS (two buffers: the next entry's moments are fetched into registers
-// while the current entry computes) and read back as broadcasts. The Tbar
-// table sits in LDS for the whole kernel.
-template <int D, int P>
-constexpr int m2t_pf()  // moments per lane per prefetch
-{
-    return (cbinom(P + D, D) + kWave - 1) / kWave;
-}
-
+// One wave per 64-target block. The block's (target, far node) pairs come
+// packed in jobs of 64 lanes, one pair per lane, with at most MAXN nodes per
+// job; a job's node moments and centres are staged in LDS (two buffers: the
+// next job is fetched into registers while the current one computes), and
+// each lane adds its pair's value to its target's LDS accumulator. The block
+// then stores its 64 sums, which initialises zacc for the near field.
 template <int D, int P, int KIND, typename T>
-__global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zfar)
+__global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zacc)
 {
     constexpr int R = cbinom(P + D, D);
     constexpr int NF = f_off(P, P + 1);
-    constexpr int PF = m2t_pf<D, P>();
-    __shared__ T smom[2][PF * kWave];
+    constexpr int MAXN = m2t_max_job_nodes(D, P, (int)sizeof(T));
+    constexpr int PF = (MAXN * R + kWave - 1) / kWave;
+    constexpr int G = D + 1;  // centre and scale per node
+    static_assert(MAXN * G <= kWave, "node geometry is fetched one value per lane");
+    __shared__ T smom[2][PF * kWave];  // whole 64-lane rows: the fill below writes PF * 64 entries
+    __shared__ double sgeo[2][MAXN * G];
+    __shared__ double zblk[kWave];
     const int blk = blockIdx.x;
     const int lane = threadIdx.x;
     const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
-    const bool valid = lane < cnt;
-    const int t = tb + (valid ? lane : 0);
+    zblk[lane] = 0.0;
+    // each lane holds its own target; pairs fetch it by cross-lane shuffle
     double tx[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)t * D + i];
+    for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
 
-    const int e0 = a.far_off[blk], e1 = a.far_off[blk + 1];
+    const int j0 = a.job_off[blk], j1 = a.job_off[blk + 1];
     T pre[PF];
-    auto fetch = [&](int e) {
-        const T* __restrict__ src = mom + (size_t)a.far_slot[e] * R;
+    double pgeo = 0.0;
+    auto fetch = [&](int j) {
+        const int n0 = a.job_noff[j], nn = a.job_noff[j + 1] - n0;
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int i = q * kWave + lane;
-            pre[q] = (i < R) ? src[i] : T(0);
+            const int node = i / R;
+            pre[q] = (node < nn) ? mom[(size_t)a.job_nodes[n0 + node] * R + (i - node * R)] : T(0);
+        }
+        const int node = lane / G, c = lane - node * G;
+        if (node < nn) {
+            const int slot = a.job_nodes[n0 + node];
+            pgeo = (c < D) ? a.slot_ctr[slot * D + c] : a.slot_scale[slot];
         }
     };
-    if (e0 < e1) fetch(e0);
+    if (j0 < j1) fetch(j0);
 
-    double acc = 0.0;
     int buf = 0;
-    for (int e = e0; e < e1; ++e) {
+    for (int j = j0; j < j1; ++j) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) smom[buf][q * kWave + lane] = pre[q];
+        if (lane < MAXN * G) sgeo[buf][lane] = pgeo;
         __syncthreads();
-        const uint64_t msk = a.far_mask[e];
-        const int slot = a.far_slot[e];
-        if (e + 1 < e1) fetch(e + 1);
-        if ((msk >> lane) & 1) {
+        const unsigned pw = a.job_pairs[(size_t)j * kWave + lane];
+        if (j + 1 < j1) fetch(j + 1);
+        const int lt = pw & 63;
+        double txl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) txl[i] = __shfl(tx[i], lt, kWave);
+        if (pw != 0xffffu) {
+            const int ni = pw >> 6;
+            const double* __restrict__ geo = sgeo[buf] + ni * G;
             double r[D], r2 = 0.0;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                r[i] = tx[i] - a.slot_ctr[slot * D + i];
+                r[i] = txl[i] - geo[i];
                 r2 = fma(r[i], r[i], r2);
             }
             const double ir = rsqrt_pos(r2);  // r2 > 0: a far target is never at the centre
@@ -498,7 +511,7 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
             T Skj[NF];
 #pragma unroll
             for (int i = 0; i < NF; ++i) Skj[i] = T(0);
-            const T* M = smom[buf];
+            const T* M = smom[buf] + ni * R;
             int off = 0;
             auto emit = [&](auto kc, T yv) {
                 constexpr int k = decltype(kc)::value;
@@ -509,8 +522,6 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
                 };
                 static_for<0, nj>(dot);
                 off += nj;
-                // keep each harmonic's LDS reads next to their use
-                __builtin_amdgcn_sched_barrier(0);
             };
             harmonics<D, P, false, T>(x, rho2, (const T*)nullptr, emit);
 
@@ -522,32 +533,35 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
             double rp = 1.0;
 #pragma unroll
             for (int m = 1; m <= P; ++m) { rp *= rr; um[m] = Dm[m] * rp; }
-            const double v = a.slot_scale[slot] * ir;  // s / |r| < theta
+            const double v = geo[D] * ir;  // s / |r| < theta
             double vp[P + 1];
             vp[0] = 1.0;
 #pragma unroll
-            for (int j = 1; j <= P; ++j) vp[j] = vp[j - 1] * v;
+            for (int jp = 1; jp <= P; ++jp) vp[jp] = vp[jp - 1] * v;
+            double acc = 0.0;
             auto radial_k = [&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 auto radial_j = [&](auto jc) {
                     constexpr int jj = decltype(jc)::value;
-                    constexpr int j = k + 2 * jj;
-                    double f = (j == 0) ? um[0] : 0.0;
+                    constexpr int jv = k + 2 * jj;
+                    double f = (jv == 0) ? um[0] : 0.0;
                     auto term = [&](auto mc) {
                         constexpr int m = decltype(mc)::value + 1;
-                        constexpr double c = cx_tbar(D, k, j, m);
+                        constexpr double c = cx_tbar(D, k, jv, m);
                         f = fma(um[m], c, f);
                     };
-                    static_for<0, j>(term);
-                    acc = fma(vp[j] * f, (double)Skj[f_off(P, k) + jj], acc);
+                    static_for<0, jv>(term);
+                    acc = fma(vp[jv] * f, (double)Skj[f_off(P, k) + jj], acc);
                 };
                 static_for<0, nj_of(P, k)>(radial_j);
             };
             static_for<0, P + 1>(radial_k);
+            atomicAdd(&zblk[lt], acc);
         }
         buf ^= 1;
     }
-    if (valid) zfar[t] = T(acc);
+    __syncthreads();
+    if (lane < cnt) zacc[tb + lane] = T(zblk[lane]);
 }
 
 // -------------------------------------------------------------- near field
@@ -648,35 +662,39 @@ template <> struct NearKernel<FKT_LAPLACE, float> {
     }
 };
 
+// Source-major near field: one wave per work unit (a source leaf l and up to
+// kNearUnitTargets targets of N_l, 64 at a time, one per lane). The leaf's
+// points stream through scalar registers; each target's sum is added to its
+// accumulator (which the far-field stage initialised) with one FP64/FP32
+// atomic per (target, leaf), so no lane ever idles on a target whose own walk
+// does not reach l.
 template <int D, int KIND, typename T>
-__global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, const T* __restrict__ zfar,
-                                                T* __restrict__ y, int nrhs, int col, T c0, T c1, T scale)
+__global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, T* __restrict__ zacc,
+                                                T c0, T c1, T scale)
 {
     constexpr int S = src_stride(D);
-    const int blk = blockIdx.x;
+    const int u = blockIdx.x;
     const int lane = threadIdx.x;
-    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
-    const bool valid = lane < cnt;
-    const int t = tb + (valid ? lane : 0);
-    T tx[D];
+    const int s0 = a.nu_beg[u], m = a.nu_end[u] - s0;
+    const int toff = a.nu_toff[u], tcnt = a.nu_tcnt[u];
+    const T* __restrict__ q = src + (size_t)s0 * S;
+    for (int c = 0; c < tcnt; c += kWave) {
+        const int i = c + lane;
+        const bool valid = i < tcnt;
+        const int t = a.near_tgt[toff + (valid ? i : 0)];
+        T tx[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) tx[i] = src[(size_t)t * S + i];
-    T acc0 = T(0), acc1 = T(0);
-    auto pair = [&](const T* __restrict__ q) {
-        T d2 = T(0);
+        for (int k = 0; k < D; ++k) tx[k] = src[(size_t)t * S + k];
+        auto pair = [&](const T* __restrict__ p) {
+            T d2 = T(0);
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const T u = tx[i] - q[i];
-            d2 = fma(u, u, d2);
-        }
-        return NearKernel<KIND, T>::eval(d2, c0, c1) * q[D];
-    };
-    const int e0 = a.near_off[blk], e1 = a.near_off[blk + 1];
-    for (int e = e0; e < e1; ++e) {
-        const uint64_t msk = a.near_mask[e];
-        if (!((msk >> lane) & 1)) continue;
-        const T* __restrict__ q = src + (size_t)a.near_beg[e] * S;
-        const int m = a.near_end[e] - a.near_beg[e];
+            for (int k = 0; k < D; ++k) {
+                const T w = tx[k] - p[k];
+                d2 = fma(w, w, d2);
+            }
+            return NearKernel<KIND, T>::eval(d2, c0, c1) * p[D];
+        };
+        T acc0 = T(0), acc1 = T(0);
         int s = 0;
         for (; s + 4 <= m; s += 4) {
             acc0 += pair(q + (s + 0) * S);
@@ -685,12 +703,24 @@ __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __rest
             acc1 += pair(q + (s + 3) * S);
         }
         for (; s < m; ++s) acc0 += pair(q + s * S);
+        if (valid) unsafeAtomicAdd(zacc + t, scale * (acc0 + acc1));
     }
-    if (valid) {
-        T out = scale * (acc0 + acc1);
-        if (zfar) out += zfar[t];
-        y[a.perm[t] * nrhs + col] = out;
-    }
+}
+
+// y (caller order, column col) <- zacc (tree order)
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restrict__ perm, const T* __restrict__ zacc,
+                                                 T* __restrict__ y, int nrhs, int col)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[perm[i] * nrhs + col] = zacc[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(int n, T* __restrict__ z)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) z[i] = T(0);
 }
 
 // ------------------------------------------------- built orders per dimension

@@ -46,15 +46,16 @@ void near_consts(const DevPlan& a, T& c0, T& c1)
 }
 
 template <int D, typename T>
-bool run_near_d(const DevPlan& a, const T* src, const T* zfar, T* y, int nrhs, int col, hipStream_t s)
+bool run_near_d(const DevPlan& a, const T* src, T* zacc, hipStream_t s)
 {
+    if (a.nnear_units == 0) return true;
     T c0, c1;
     near_consts<T>(a, c0, c1);
     const T scale = (T)a.var;
-    dim3 g(a.nblocks), b(kWave);
+    dim3 g(a.nnear_units), b(kWave);
     switch (a.kind) {
 #define FKT_NEAR_CASE(K) \
-    case K: hipLaunchKernelGGL((k_near<D, K, T>), g, b, 0, s, a, src, zfar, y, nrhs, col, c0, c1, scale); return true;
+    case K: hipLaunchKernelGGL((k_near<D, K, T>), g, b, 0, s, a, src, zacc, c0, c1, scale); return true;
         FKT_NEAR_CASE(FKT_GAUSSIAN)
         FKT_NEAR_CASE(FKT_EXPONENTIAL)
         FKT_NEAR_CASE(FKT_MATERN32)
@@ -73,6 +74,7 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
 {
     const T* pts = std::is_same<T, float>::value ? (const T*)a.pts32 : (const T*)a.pts64;
     T* src = (T*)wk.src;
+    T* zacc = (T*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
     if (ev) (void)hipEventRecord(ev[0], s);
     switch (a.d) {
@@ -82,25 +84,26 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
     default: return hipErrorInvalidValue;
     }
     if (ev) (void)hipEventRecord(ev[1], s);
-    const T* zfar = nullptr;
     const int prec = std::is_same<T, float>::value ? 1 : 0;
     if (a.nslots > 0) {
         if (!launch_s2m(a, wk, prec, s)) return hipErrorInvalidValue;
         if (ev) (void)hipEventRecord(ev[2], s);
+        // stores the far field of every target: initialises zacc
         if (!launch_m2t(a.kind, a, wk, prec, s)) return hipErrorInvalidValue;
-        zfar = (const T*)wk.zfar;
-    } else if (ev) {
-        (void)hipEventRecord(ev[2], s);
+    } else {
+        if (ev) (void)hipEventRecord(ev[2], s);
+        hipLaunchKernelGGL((k_zero<T>), gg, gb, 0, s, a.n, zacc);
     }
     if (ev) (void)hipEventRecord(ev[3], s);
     bool ok = false;
     switch (a.d) {
-    case 3: ok = run_near_d<3, T>(a, src, zfar, y, nrhs, col, s); break;
-    case 4: ok = run_near_d<4, T>(a, src, zfar, y, nrhs, col, s); break;
-    case 5: ok = run_near_d<5, T>(a, src, zfar, y, nrhs, col, s); break;
+    case 3: ok = run_near_d<3, T>(a, src, zacc, s); break;
+    case 4: ok = run_near_d<4, T>(a, src, zacc, s); break;
+    case 5: ok = run_near_d<5, T>(a, src, zacc, s); break;
     default: break;
     }
     if (!ok) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_scatter<T>), gg, gb, 0, s, a.n, a.perm, (const T*)zacc, y, nrhs, col);
     if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }

@@ -201,7 +201,7 @@ struct BlockLists {
 // node on the path with rho_b^2 < theta^2 |t - c_b|^2 (eq. accparam), and in
 // N_l for each leaf l reached without such a node (Sec. 3.2). Done for 64
 // targets at once with a mask of the targets still walking.
-void build_lists(const Tree& T, double theta, Lists& L, fkt_plan_stats& st)
+void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st)
 {
     const int d = T.d;
     const int64_t nn = T.nnodes();
@@ -263,20 +263,85 @@ void build_lists(const Tree& T, double theta, Lists& L, fkt_plan_stats& st)
         L.far_off[q + 1] = L.far_off[q] + (int32_t)per[q].far_node.size();
     }
     int64_t near_pairs = 0, near_lane = 0, far_pairs = 0, far_lane = 0;
+    std::vector<int64_t> ncount(nn + 1, 0);  // |N_l| per leaf
     for (int64_t q = 0; q < nb; ++q) {
         for (size_t e = 0; e < per[q].near_node.size(); ++e) {
             const int32_t b = per[q].near_node[e];
             L.near_beg.push_back((int32_t)T.begin[b]);
             L.near_end.push_back((int32_t)T.end[b]);
             L.near_mask.push_back(per[q].near_mask[e]);
-            near_pairs += (int64_t)__builtin_popcountll(per[q].near_mask[e]) * (T.end[b] - T.begin[b]);
-            near_lane += (int64_t)kBlock * (T.end[b] - T.begin[b]);
+            const int c = __builtin_popcountll(per[q].near_mask[e]);
+            near_pairs += (int64_t)c * (T.end[b] - T.begin[b]);
+            ncount[b + 1] += c;
         }
         for (size_t e = 0; e < per[q].far_node.size(); ++e) {
             L.far_slot.push_back(slot_of[per[q].far_node[e]]);
             L.far_mask.push_back(per[q].far_mask[e]);
             far_pairs += __builtin_popcountll(per[q].far_mask[e]);
-            far_lane += kBlock;
+        }
+    }
+
+    // Pack each block's far pairs into jobs of 64 lanes, in list order (so a
+    // node's lanes are adjacent), starting a new job when 64 pairs or
+    // max_job_nodes distinct nodes are reached.
+    L.max_job_nodes = max_job_nodes;
+    L.job_off.assign(nb + 1, 0);
+    L.job_noff.assign(1, 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        int in_job = kBlock, nodes_in_job = max_job_nodes;  // forces a new job
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) {
+            uint64_t m = L.far_mask[e];
+            bool node_open = false;
+            while (m) {
+                if (in_job == kBlock || (!node_open && nodes_in_job == max_job_nodes)) {
+                    L.job_pairs.resize(L.job_pairs.size() + kBlock, (uint16_t)0xffff);
+                    L.job_noff.push_back(L.job_noff.back());
+                    in_job = 0;
+                    nodes_in_job = 0;
+                    node_open = false;
+                }
+                if (!node_open) {
+                    L.job_nodes.push_back(L.far_slot[e]);
+                    L.job_noff.back() += 1;
+                    ++nodes_in_job;
+                    node_open = true;
+                }
+                const int lane = __builtin_ctzll(m);
+                m &= m - 1;
+                L.job_pairs[L.job_pairs.size() - kBlock + in_job] = (uint16_t)(lane | ((nodes_in_job - 1) << 6));
+                ++in_job;
+            }
+        }
+        L.job_off[q + 1] = (int32_t)(L.job_noff.size() - 1);
+    }
+    far_lane = (int64_t)(L.job_noff.size() - 1) * kBlock;
+
+    // N_l for every leaf l: the targets whose walk ends in l, in target order
+    // (blocks and lanes are visited in tree order)
+    for (int64_t b = 0; b < nn; ++b) ncount[b + 1] += ncount[b];
+    L.near_tgt.resize(ncount[nn]);
+    {
+        std::vector<int64_t> fill(ncount.begin(), ncount.end() - 1);
+        for (int64_t q = 0; q < nb; ++q)
+            for (size_t e = 0; e < per[q].near_node.size(); ++e) {
+                uint64_t m = per[q].near_mask[e];
+                const int32_t b = per[q].near_node[e];
+                while (m) {
+                    const int lane = __builtin_ctzll(m);
+                    m &= m - 1;
+                    L.near_tgt[fill[b]++] = L.blk_begin[q] + lane;
+                }
+            }
+    }
+    for (int64_t b = 0; b < nn; ++b) {
+        if (!T.leaf(b)) continue;
+        for (int64_t o = ncount[b]; o < ncount[b + 1]; o += kNearUnitTargets) {
+            const int64_t c = std::min<int64_t>(kNearUnitTargets, ncount[b + 1] - o);
+            L.nu_beg.push_back((int32_t)T.begin[b]);
+            L.nu_end.push_back((int32_t)T.end[b]);
+            L.nu_toff.push_back((int32_t)o);
+            L.nu_tcnt.push_back((int32_t)c);
+            near_lane += ((c + kBlock - 1) / kBlock) * kBlock * (T.end[b] - T.begin[b]);
         }
     }
 

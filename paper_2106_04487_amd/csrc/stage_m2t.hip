@@ -20,7 +20,7 @@ bool m2t_d(const DevPlan& a, const DevWork& wk, hipStream_t s)
     } else {
         if (a.p == P) {
             hipLaunchKernelGGL((k_m2t<D, P, FKT_M2T_KIND, T>), dim3(a.nblocks), dim3(kWave), 0, s, a,
-                               (const T*)wk.mom, (T*)wk.zfar);
+                               (const T*)wk.mom, (T*)wk.zacc);
             return true;
         }
         return m2t_d<D, T, P + 1>(a, wk, s);
