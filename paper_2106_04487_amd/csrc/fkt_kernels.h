@@ -459,19 +459,25 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
     const int j0 = a.job_off[blk], j1 = a.job_off[blk + 1];
     T pre[PF];
     double pgeo = 0.0;
+    // Fetch job j's node moments and centres into registers: lane i of row q
+    // holds entry q*64 + i of the job's concatenated moments. Entries past
+    // the job's last node are clamped to it (valid addresses; never read).
     auto fetch = [&](int j) {
         const int n0 = a.job_noff[j], nn = a.job_noff[j + 1] - n0;
+        const int myslot = a.job_nodes[n0 + (lane < nn ? lane : nn - 1)];
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int i = q * kWave + lane;
-            const int node = i / R;
-            pre[q] = (node < nn) ? mom[(size_t)a.job_nodes[n0 + node] * R + (i - node * R)] : T(0);
+            int node = i / R;
+            node = node < nn ? node : nn - 1;
+            const int slot = __shfl(myslot, node, kWave);
+            pre[q] = mom[(unsigned)(slot * R + (i - node * R))];
         }
-        const int node = lane / G, c = lane - node * G;
-        if (node < nn) {
-            const int slot = a.job_nodes[n0 + node];
-            pgeo = (c < D) ? a.slot_ctr[slot * D + c] : a.slot_scale[slot];
-        }
+        int node = lane / G;
+        node = node < nn ? node : nn - 1;
+        const int c = lane - (lane / G) * G;
+        const int slot = __shfl(myslot, node, kWave);
+        pgeo = (c < D) ? a.slot_ctr[(unsigned)(slot * D + c)] : a.slot_scale[slot];
     };
     if (j0 < j1) fetch(j0);
 

@@ -167,3 +167,38 @@ def test_cg_solve_plain(F):
     assert rr <= 1e-6 and it > 0
     res = F.fkt_mvm(plan, x) + 0.1 * x - b
     assert float(res.norm() / b.norm()) < 1e-5
+
+
+# FP32 bar: unit roundoff 6e-8 times sqrt of the ~1.2e4-2.2e4 terms summed
+# per target (~1e-5 worst case with cancellation in the 1/r sums)
+FULL = [("matern32", dict(lengthscale=0.05), 0.26, "f64", 1e-10),
+        ("laplace", dict(), 0.32, "f64", 1e-10),
+        ("matern32", dict(lengthscale=0.05), 0.26, "f32", 1e-5),
+        ("laplace", dict(), 0.32, "f32", 1e-5)]
+
+
+@pytest.fixture(scope="module")
+def full_points():
+    return W.uniform_cube(1_000_000, 3, 1002), W.normal_rhs(1_000_000, 1, 2002)[:, 0]
+
+
+@pytest.fixture(scope="module")
+def full_tree(full_points):
+    return oracle.Tree(full_points[0], 256)
+
+
+@pytest.mark.parametrize("kind,kw,theta,prec,tol", FULL, ids=[f"{c[0]}-{c[3]}" for c in FULL])
+def test_full_size_sampled_rows(F, full_points, full_tree, kind, kw, theta, prec, tol):
+    """The benchmark's launch configuration (10^6 uniform points, leaf 256,
+    p = 6, theta at the 1e-5 operating point): 48 sampled output rows
+    against the oracle's rows of Algorithm 1 at the same truncation.
+    FP64: the parity bar; FP32: FP32 rounding only."""
+    X, x = full_points
+    z, plan = _gpu_mvm(F, X, x, kind, 256, 6, theta, prec=prec, **kw)
+    tg = W.subsample(X.shape[0], 48, 4004)
+    okind, okw = _oracle_kind(kind, kw)
+    zr = oracle.fkt_rows(full_tree, x, okind, theta, 6, tg, **okw)[:, 0]
+    rel = np.linalg.norm(z[tg] - zr) / np.linalg.norm(zr)
+    relinf = np.abs(z[tg] - zr).max() / np.abs(zr).max()
+    print(f"full-size {kind} {prec}: rel {rel:.3e} max {relinf:.3e}")
+    assert rel <= tol and relinf <= tol
