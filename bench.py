@@ -86,6 +86,37 @@ def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmu
             "rel_err_vs_dense": rel_err, "stages_ms": stages, "plan": info}
 
 
+def gp_solve(F, torch, n, theta, order, rtol, maxit):
+    """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM,
+    without and with the block-Jacobi preconditioner; d = 4 mixture."""
+    spec = W.WORKLOADS["gmm4_n200k_gp"]
+    X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
+    y = W.gp_targets(X, spec["lengthscale"], spec["sigma2"], spec["nfeat"], spec["rhs_seed"])
+    t0 = time.perf_counter()
+    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, lengthscale=spec["lengthscale"])
+    plan_s = time.perf_counter() - t0
+    b = torch.as_tensor(y, device="cuda")
+    out = {"workload": f"gmm{spec['d']}_n{n}_matern52_gp", "n": n, "d": spec["d"], "theta": theta, "p": order,
+           "sigma2": spec["sigma2"], "rtol": rtol, "plan_seconds": plan_s}
+    for name, pc in (("none", 0), ("block_jacobi", 1)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            x, it, rr = F.fkt_cg_solve(plan, spec["sigma2"], b, rtol=rtol, maxit=maxit, precond=pc)
+            ok = True
+        except F.FktError as e:
+            if e.status != 5:
+                raise
+            x, it, rr, ok = e.x, e.iters, e.relres, False
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"iterations": it, "relres": rr, "converged": ok, "seconds": sec}
+        print(f"bench: gp solve n={n} precond={name}: {it} iterations, {sec:.2f} s, relres {rr:.2e}",
+              file=sys.stderr, flush=True)
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +133,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time budget of the CPU-oracle baseline sample; 0 skips")
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
+    ap.add_argument("--gp-n", type=int, default=50_000,
+                    help="points of the GP solve (the d = 4 mixture workload at 200k takes minutes); 0 skips it")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -139,6 +172,10 @@ def main():
             v.pop("plan")
             variants.append(v)
 
+    gp = None
+    if a.gp_n > 0 and not a.no_variants:
+        gp = gp_solve(F, torch, a.gp_n, 0.35, 6, 1e-6, 6000)
+
     cpu = None
     if a.cpu_seconds > 0:
         # the oracle as it stands: rows of its Algorithm 1 (pairwise far
@@ -172,6 +209,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "gp_solve": gp,
     }
     print(json.dumps(out))
 

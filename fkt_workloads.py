@@ -57,6 +57,25 @@ def clustered_duplicates(n: int, d: int, ndistinct: int, seed: int) -> np.ndarra
     return sites[rng.integers(0, ndistinct, size=n)]
 
 
+def gp_targets(X: np.ndarray, lengthscale: float, sigma2: float, nfeat: int, seed: int) -> np.ndarray:
+    """y = f(X) + noise, f a random-Fourier-feature draw of a Matern-5/2 GP.
+
+    Frequencies follow the Matern-5/2 spectral density, a multivariate
+    Student-t with 5 degrees of freedom scaled by 1/lengthscale; phases are
+    uniform; f = sqrt(2/D) sum_i w_i cos(omega_i . x + b_i), w_i ~ N(0, 1);
+    the noise is N(0, sigma2).
+    """
+    rng = np.random.default_rng(seed)
+    n, d = X.shape
+    g = rng.standard_normal(size=(nfeat, d))
+    u = rng.chisquare(5.0, size=(nfeat, 1))
+    omega = g / lengthscale * np.sqrt(5.0 / u)
+    b = rng.uniform(0.0, 2.0 * np.pi, size=nfeat)
+    w = rng.standard_normal(size=nfeat)
+    f = np.sqrt(2.0 / nfeat) * (np.cos(X @ omega.T + b) @ w)
+    return f + np.sqrt(sigma2) * rng.standard_normal(size=n)
+
+
 # Named workloads: (points recipe, rhs recipe). Sizes follow the problem
 # statements; seeds are fixed so every consumer sees identical inputs.
 WORKLOADS = {
@@ -68,6 +87,10 @@ WORKLOADS = {
                                kernel="matern32", lengthscale=0.05, leaf=256, order=6),
     "cube3_n1m_laplace": dict(n=1_000_000, d=3, pts_seed=1002, rhs_seed=2002, nrhs=1,
                               kernel="laplace", lengthscale=1.0, leaf=256, order=6),
+    # Gaussian-process solve: 200k points from an 8-component mixture in d=4
+    # (std 0.15), Matern-5/2 length scale 0.3, noise variance 1e-2
+    "gmm4_n200k_gp": dict(n=200_000, d=4, ncomp=8, std=0.15, pts_seed=1005, rhs_seed=2005,
+                          kernel="matern52", lengthscale=0.3, sigma2=1e-2, nfeat=2048, leaf=256),
 }
 
 

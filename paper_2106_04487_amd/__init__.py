@@ -214,16 +214,21 @@ def fkt_mvm(plan: Plan, x, y=None):
 
 def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,
                  precond: int = 0):
-    """Solve (K~ + sigma2 I) x = b by CG. Returns (x, iters, relres); raises
-    FktError(FKT_ENOTCONV) if maxit is reached."""
+    """Solve (K~ + sigma2 I) x = b by CG. Returns (x, iters, relres); if maxit
+    is reached raises FktError(FKT_ENOTCONV) carrying .x, .iters, .relres."""
     import torch
     b = _device_matrix(plan, b, "b")
     x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0").clone()
     nrhs = 1 if b.dim() == 1 else b.shape[1]
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
-    _check(_lib.fkt_cg_solve(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol), int(maxit),
-                             int(precond), ctypes.byref(it), ctypes.byref(rr)))
+    st = _lib.fkt_cg_solve(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol), int(maxit),
+                           int(precond), ctypes.byref(it), ctypes.byref(rr))
+    if st == 5:  # FKT_ENOTCONV: x holds the last iterate
+        err = FktError(st, _lib.fkt_last_error().decode())
+        err.x, err.iters, err.relres = x, it.value, rr.value
+        raise err
+    _check(st)
     return x, it.value, rr.value
 
 

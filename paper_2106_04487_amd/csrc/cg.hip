@@ -84,6 +84,27 @@ __global__ __launch_bounds__(kThreads) void k_sub(int64_t m, const double* __res
     if (i < m) r[i] = b[i] - q[i];
 }
 
+// z[:, c] = blockdiag((K_ll + sigma2 I)^-1) r[:, c]: one workgroup per leaf;
+// the leaf's residual entries are gathered through the tree permutation into
+// LDS, each thread forms rows of the (symmetric) inverse block times it.
+__global__ __launch_bounds__(kThreads) void k_bj_apply(const int* __restrict__ begin, const int* __restrict__ count,
+                                                       const int64_t* __restrict__ off, const double* __restrict__ inv,
+                                                       const int64_t* __restrict__ perm, int nrhs, int col,
+                                                       const double* __restrict__ r, double* __restrict__ z)
+{
+    extern __shared__ double rl[];
+    const int l = blockIdx.x;
+    const int b = begin[l], m = count[l];
+    const double* __restrict__ A = inv + off[l];
+    for (int j = threadIdx.x; j < m; j += kThreads) rl[j] = r[perm[b + j] * nrhs + col];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kThreads) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += A[(size_t)j * m + i] * rl[j];
+        z[perm[b + i] * nrhs + col] = s;
+    }
+}
+
 unsigned grid_of(int64_t m) { return (unsigned)((m + kThreads - 1) / kThreads); }
 
 struct Buf {
@@ -112,6 +133,12 @@ struct CgPlanView {
     int prec;
     int device;
     hipStream_t stream;
+    const int64_t* perm;     // device: tree position -> original index
+    int nleaf, maxleaf;      // block-Jacobi blocks (precond = 1)
+    const int* bj_begin;
+    const int* bj_count;
+    const int64_t* bj_off;
+    const double* bj_inv;
 };
 fkt_status cg_set_error(fkt_status st, const std::string& msg);
 }  // namespace fkt
@@ -120,28 +147,28 @@ namespace fkt {
 
 template <typename T>
 static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const T* b_in, T* x_io, int nrhs, double rtol,
-                           int maxit, int* iters, double* relres)
+                           int maxit, int precond, int* iters, double* relres)
 {
     const int64_t n = v.n, m = n * nrhs;
     hipStream_t s = v.stream;
     Buf buf;
-    double *b, *x, *r, *p, *q, *part, *coef;
+    double *b, *x, *r, *z, *p, *q, *part, *coef;
     T *op_in, *op_out;
     hipError_t e;
-    if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &p)) ||
-        (e = buf.get(m, &q)) || (e = buf.get((size_t)kDotBlocks * nrhs, &part)) || (e = buf.get(3 * nrhs, &coef)) ||
-        (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)))
+    if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &z)) ||
+        (e = buf.get(m, &p)) || (e = buf.get(m, &q)) || (e = buf.get((size_t)kDotBlocks * nrhs, &part)) ||
+        (e = buf.get(3 * nrhs, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)))
         return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "cg work buffers");
 
     std::vector<double> hpart((size_t)kDotBlocks * nrhs), hcoef(3 * nrhs);
-    auto dots = [&](const double* a, const double* c, std::vector<double>& out) -> bool {
-        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, s, n, nrhs, a, c, part);
+    auto dots = [&](const double* a1, const double* a2, std::vector<double>& out) -> bool {
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, s, n, nrhs, a1, a2, part);
         if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
             return false;
         if (hipStreamSynchronize(s) != hipSuccess) return false;
         out.assign(nrhs, 0.0);
         for (int k = 0; k < kDotBlocks; ++k)
-            for (int c = 0; c < nrhs; ++c) out[c] += hpart[(size_t)k * nrhs + c];
+            for (int c2 = 0; c2 < nrhs; ++c2) out[c2] += hpart[(size_t)k * nrhs + c2];
         return true;
     };
     auto apply = [&](const double* in, double* out) -> fkt_status {
@@ -151,23 +178,32 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         hipLaunchKernelGGL((k_add_shift<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, op_out, in, sigma2, out);
         return FKT_OK;
     };
+    auto precondition = [&](const double* in, double* out) -> bool {
+        if (precond == 1) {
+            for (int c2 = 0; c2 < nrhs; ++c2)
+                hipLaunchKernelGGL(k_bj_apply, dim3(v.nleaf), dim3(kThreads), sizeof(double) * v.maxleaf, s, v.bj_begin,
+                                   v.bj_count, v.bj_off, v.bj_inv, v.perm, nrhs, c2, in, out);
+            return hipGetLastError() == hipSuccess;
+        }
+        return hipMemcpyAsync(out, in, sizeof(double) * m, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    };
 
     hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, b_in, b);
     hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const T*)x_io, x);
     fkt_status st = apply(x, q);
     if (st != FKT_OK) return st;
     hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
-    // p = r
-    if (hipMemcpyAsync(p, r, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
+    if (hipMemcpyAsync(p, z, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return cg_set_error(FKT_EDEVICE, "cg copy");
 
-    std::vector<double> bb, rr, pq, rr_new;
-    if (!dots(b, b, bb) || !dots(r, r, rr)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+    std::vector<double> bb, rr, rz, pq, rz_new;
+    if (!dots(b, b, bb) || !dots(r, r, rr) || !dots(r, z, rz)) return cg_set_error(FKT_EDEVICE, "cg reduction");
     auto worst = [&](const std::vector<double>& rv) {
         double w = 0.0;
-        for (int c = 0; c < nrhs; ++c) {
-            const double den = bb[c] > 0.0 ? std::sqrt(bb[c]) : 1.0;
-            w = std::max(w, std::sqrt(std::max(rv[c], 0.0)) / den);
+        for (int c2 = 0; c2 < nrhs; ++c2) {
+            const double den = bb[c2] > 0.0 ? std::sqrt(bb[c2]) : 1.0;
+            w = std::max(w, std::sqrt(std::max(rv[c2], 0.0)) / den);
         }
         return w;
     };
@@ -179,21 +215,22 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         if (!dots(p, q, pq)) return cg_set_error(FKT_EDEVICE, "cg reduction");
         // coef = [alpha | -alpha | beta]; host slots are rewritten only after
         // a stream synchronisation (inside dots) has retired the copy.
-        for (int c = 0; c < nrhs; ++c) {
-            hcoef[c] = (pq[c] != 0.0) ? rr[c] / pq[c] : 0.0;
-            hcoef[nrhs + c] = -hcoef[c];
+        for (int c2 = 0; c2 < nrhs; ++c2) {
+            hcoef[c2] = (pq[c2] != 0.0) ? rz[c2] / pq[c2] : 0.0;
+            hcoef[nrhs + c2] = -hcoef[c2];
         }
         if (hipMemcpyAsync(coef, hcoef.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s) != hipSuccess)
             return cg_set_error(FKT_EDEVICE, "cg copy");
         hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef, p, x);
         hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef + nrhs, q, r);
-        if (!dots(r, r, rr_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
-        for (int c = 0; c < nrhs; ++c) hcoef[2 * nrhs + c] = rr[c] > 0.0 ? rr_new[c] / rr[c] : 0.0;
+        if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
+        if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        for (int c2 = 0; c2 < nrhs; ++c2) hcoef[2 * nrhs + c2] = rz[c2] != 0.0 ? rz_new[c2] / rz[c2] : 0.0;
         if (hipMemcpyAsync(coef + 2 * nrhs, hcoef.data() + 2 * nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, s) !=
             hipSuccess)
             return cg_set_error(FKT_EDEVICE, "cg copy");
-        hipLaunchKernelGGL(k_xpby, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, r, coef + 2 * nrhs, p);
-        rr = rr_new;
+        hipLaunchKernelGGL(k_xpby, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, z, coef + 2 * nrhs, p);
+        rz = rz_new;
         ++it;
         res = worst(rr);
     }
@@ -208,10 +245,10 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres)
 {
-    if (precond != 0) return cg_set_error(FKT_EUNSUPPORTED, "only precond = 0 (none) is built");
+    if (precond != 0 && precond != 1) return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
     if (v.prec == 1)
-        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, iters, relres);
-    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, iters, relres);
+        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters, relres);
+    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters, relres);
 }
 
 }  // namespace fkt

@@ -51,6 +51,12 @@ struct CgPlanView {
     int prec;
     int device;
     hipStream_t stream;
+    const int64_t* perm;
+    int nleaf, maxleaf;
+    const int* bj_begin;
+    const int* bj_count;
+    const int64_t* bj_off;
+    const double* bj_inv;
 };
 fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
@@ -75,6 +81,14 @@ struct fkt_plan_s {
     std::vector<Ev5> prof;   // events of profiled column passes not yet summed
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_calls = 0;
+    // block-Jacobi factors, built on first use for a given sigma2
+    double bj_sigma2 = -1.0;
+    int bj_nleaf = 0, bj_maxleaf = 0;
+    const int* bj_begin = nullptr;
+    const int* bj_count = nullptr;
+    const int64_t* bj_off = nullptr;
+    const double* bj_inv = nullptr;
+    std::vector<void*> bj_allocs;
 
     void drop_events()
     {
@@ -90,6 +104,7 @@ struct fkt_plan_s {
             (void)hipStreamSynchronize(stream);
             drop_events();
             for (void* q : allocs) (void)hipFree(q);
+            for (void* q : bj_allocs) (void)hipFree(q);
         }
     }
 
@@ -394,7 +409,43 @@ fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int
     if (precond < 0 || precond > 1) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
-    fkt::CgPlanView v{P->n, (int)P->opt.prec, P->opt.device, P->stream};
+    if (precond == 1 && P->st.nleaves > 0) {
+        int64_t big = 0;
+        for (int64_t b = 0; b < P->T.nnodes(); ++b)
+            if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
+        if (big > 4096) return fail(FKT_EUNSUPPORTED, "block-Jacobi needs leaves of at most 4096 points");
+    }
+    if (precond == 1 && P->bj_sigma2 != sigma2) {
+        std::vector<int32_t> lb, lc;
+        std::vector<int64_t> off;
+        std::vector<double> inv;
+        if (!fkt::build_block_jacobi(P->T, P->kern, sigma2, lb, lc, off, inv))
+            return fail(FKT_EINVAL, "a leaf block K_ll + sigma2 I is not positive definite");
+        (void)hipStreamSynchronize(P->stream);
+        for (void* q : P->bj_allocs) (void)hipFree(q);
+        P->bj_allocs.clear();
+        P->bj_sigma2 = -1.0;
+        auto up = [&](const void* src, size_t bytes, const void** dst) -> hipError_t {
+            void* q = nullptr;
+            hipError_t e = hipMalloc(&q, bytes ? bytes : 256);
+            if (e != hipSuccess) return e;
+            P->bj_allocs.push_back(q);
+            *dst = q;
+            return bytes ? hipMemcpy(q, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+        };
+        hipError_t e;
+        if ((e = up(lb.data(), sizeof(int32_t) * lb.size(), (const void**)&P->bj_begin)) ||
+            (e = up(lc.data(), sizeof(int32_t) * lc.size(), (const void**)&P->bj_count)) ||
+            (e = up(off.data(), sizeof(int64_t) * off.size(), (const void**)&P->bj_off)) ||
+            (e = up(inv.data(), sizeof(double) * inv.size(), (const void**)&P->bj_inv)))
+            return hip_fail(e, "block-Jacobi upload");
+        P->bj_nleaf = (int)lb.size();
+        P->bj_maxleaf = 0;
+        for (int32_t c : lc) P->bj_maxleaf = std::max(P->bj_maxleaf, (int)c);
+        P->bj_sigma2 = sigma2;
+    }
+    fkt::CgPlanView v{P->n, (int)P->opt.prec, P->opt.device, P->stream, P->dp.perm, P->bj_nleaf, P->bj_maxleaf,
+                      P->bj_begin, P->bj_count, P->bj_off, P->bj_inv};
     return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres);
 }
 

@@ -75,6 +75,16 @@ struct Tables {
 void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T);
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 void build_tables(int d, int p, Tables& tab);
+
+// K(r) for a kernel (K(0) = 0 for the singular 1/r), FP64, host side.
+double kernel_value(const fkt_kernel& k, double r);
+
+// Block-Jacobi preconditioner: for every leaf l, (K_ll + sigma2 I)^-1 as a
+// dense symmetric matrix, from a Cholesky factorisation (FP64). inv holds
+// the blocks back to back; off[l] is block l's first entry. Returns false if
+// a block is not numerically positive definite.
+bool build_block_jacobi(const Tree& T, const fkt_kernel& k, double sigma2, std::vector<int32_t>& leaf_begin,
+                        std::vector<int32_t>& leaf_count, std::vector<int64_t>& off, std::vector<double>& inv);
 int64_t binom(int64_t a, int64_t b);
 
 // Simple parallel-for over [0, n) on host threads.

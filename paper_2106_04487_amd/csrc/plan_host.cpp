@@ -451,4 +451,91 @@ void build_tables(int d, int p, Tables& tab)
     tab.rank = binom(p + d, d);
 }
 
+// ------------------------------------------------------- block Jacobi
+
+double kernel_value(const fkt_kernel& k, double r)
+{
+    const double l = k.lengthscale, s2 = k.variance;
+    switch (k.kind) {
+    case FKT_GAUSSIAN: return s2 * std::exp(-r * r / (2.0 * l * l));
+    case FKT_EXPONENTIAL: return s2 * std::exp(-r / l);
+    case FKT_MATERN32: { const double a = std::sqrt(3.0) * r / l; return s2 * (1.0 + a) * std::exp(-a); }
+    case FKT_MATERN52: { const double a = std::sqrt(5.0) * r / l; return s2 * (1.0 + a + a * a / 3.0) * std::exp(-a); }
+    case FKT_RATQUAD: return s2 * std::pow(1.0 + r * r / (2.0 * k.alpha * l * l), -k.alpha);
+    case FKT_CAUCHY: return s2 / (1.0 + r * r / (l * l));
+    case FKT_LAPLACE: return r > 0.0 ? s2 / r : 0.0;
+    }
+    return 0.0;
+}
+
+bool build_block_jacobi(const Tree& T, const fkt_kernel& k, double sigma2, std::vector<int32_t>& leaf_begin,
+                        std::vector<int32_t>& leaf_count, std::vector<int64_t>& off, std::vector<double>& inv)
+{
+    const int d = T.d;
+    leaf_begin.clear();
+    leaf_count.clear();
+    off.assign(1, 0);
+    for (int64_t b = 0; b < T.nnodes(); ++b) {
+        if (!T.leaf(b)) continue;
+        const int64_t m = T.end[b] - T.begin[b];
+        leaf_begin.push_back((int32_t)T.begin[b]);
+        leaf_count.push_back((int32_t)m);
+        off.push_back(off.back() + m * m);
+    }
+    inv.assign(off.back(), 0.0);
+    std::atomic<bool> ok(true);
+    parallel_for((int64_t)leaf_begin.size(), 1, [&](int64_t l0, int64_t l1) {
+        std::vector<double> L, Wt;
+        for (int64_t l = l0; l < l1; ++l) {
+            const int m = leaf_count[l];
+            const int64_t b0 = leaf_begin[l];
+            L.assign((size_t)m * m, 0.0);
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        const double u = T.pts[(b0 + i) * d + a] - T.pts[(b0 + j) * d + a];
+                        s += u * u;
+                    }
+                    L[(size_t)i * m + j] = kernel_value(k, std::sqrt(s)) + (i == j ? sigma2 : 0.0);
+                }
+            // in-place Cholesky A = L L^T (lower triangle)
+            for (int j = 0; j < m; ++j) {
+                double dj = L[(size_t)j * m + j];
+                for (int q = 0; q < j; ++q) dj -= L[(size_t)j * m + q] * L[(size_t)j * m + q];
+                if (!(dj > 0.0)) { ok = false; return; }
+                dj = std::sqrt(dj);
+                L[(size_t)j * m + j] = dj;
+                for (int i = j + 1; i < m; ++i) {
+                    double s = L[(size_t)i * m + j];
+                    for (int q = 0; q < j; ++q) s -= L[(size_t)i * m + q] * L[(size_t)j * m + q];
+                    L[(size_t)i * m + j] = s / dj;
+                }
+            }
+            // Wt = (L^-1)^T (upper triangular, rows contiguous), A^-1 = W^T W
+            Wt.assign((size_t)m * m, 0.0);
+            for (int j = 0; j < m; ++j) {
+                double* wj = Wt.data() + (size_t)j * m;
+                wj[j] = 1.0 / L[(size_t)j * m + j];
+                for (int i = j + 1; i < m; ++i) {
+                    const double* li = L.data() + (size_t)i * m;
+                    double s = 0.0;
+                    for (int q = j; q < i; ++q) s += li[q] * wj[q];
+                    wj[i] = -s / li[i];
+                }
+            }
+            double* out = inv.data() + off[l];
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    const double *wi = Wt.data() + (size_t)i * m, *wj = Wt.data() + (size_t)j * m;
+                    double s = 0.0;
+                    for (int q = i; q < m; ++q) s += wi[q] * wj[q];
+                    out[(size_t)i * m + j] = s;
+                    out[(size_t)j * m + i] = s;
+                }
+        }
+    });
+    return ok;
+}
+
 }  // namespace fkt
