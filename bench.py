@@ -48,12 +48,13 @@ NEAR_FLOPS_PER_PAIR = {"laplace": 12, "matern32": 16}
 NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.376e9}
 
 
-def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets):
+def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True):
     dt = torch.float32 if prec == "f32" else torch.float64
     n = X.shape[0]
-    print(f"bench: n={n} kernel={kernel} prec={prec} theta={theta} leaf={leaf} p={order}", file=sys.stderr,
-          flush=True)
-    plan = F.fkt_plan(X, kernel, leaf, order, theta=theta, prec=prec, profile=True, **KERNEL_KW[kernel])
+    print(f"bench: n={n} kernel={kernel} prec={prec} theta={theta} leaf={leaf} p={order} overlap={overlap}",
+          file=sys.stderr, flush=True)
+    plan = F.fkt_plan(X, kernel, leaf, order, theta=theta, prec=prec, profile=True, overlap=overlap,
+                      **KERNEL_KW[kernel])
     info = plan.info()
     x = torch.as_tensor(x64, dtype=dt, device="cuda")
     y = torch.empty_like(x)
@@ -133,6 +134,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time budget of the CPU-oracle baseline sample; 0 skips")
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
+    ap.add_argument("--serial", action="store_true",
+                    help="run near and far fields one after the other on one stream (default: concurrently)")
     ap.add_argument("--gp-n", type=int, default=50_000,
                     help="points of the GP solve (the d = 4 mixture workload at 200k takes minutes); 0 skips it")
     a = ap.parse_args()
@@ -149,7 +152,7 @@ def main():
     x64 = W.normal_rhs(a.n, 1, 2002)[:, 0]
     theta = a.theta if a.theta is not None else DEFAULT_THETA[a.kernel]
     head = run_variant(F, torch, X, x64, a.kernel, a.prec, theta, a.leaf, a.order, a.steps, a.warmup,
-                       a.err_targets)
+                       a.err_targets, overlap=not a.serial)
 
     # roofline of the dominant kernel, the near field (ALU-bound)
     near_ms = head["stages_ms"]["near"]
@@ -168,7 +171,7 @@ def main():
             if (kern, prec) == (a.kernel, a.prec):
                 continue
             v = run_variant(F, torch, X, x64, kern, prec, DEFAULT_THETA[kern], a.leaf, a.order, max(5, a.steps // 2),
-                            1, min(a.err_targets, 1000))
+                            1, min(a.err_targets, 1000), overlap=not a.serial)
             v.pop("plan")
             variants.append(v)
 

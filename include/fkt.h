@@ -76,9 +76,15 @@ typedef struct {
     void *stream;       /* hipStream_t for all device work; NULL = null stream */
     int profile;        /* nonzero: fkt_mvm records HIP events between its
                            stages (see fkt_plan_stage_times)                   */
+    int overlap;        /* nonzero (default): the near field runs on a second,
+                           plan-owned stream (default priority) concurrently
+                           with the far field, joined back into `stream`
+                           before the scatter; 0: every stage in order on
+                           `stream`                                            */
 } fkt_options;
 
-/* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0. */
+/* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
+ * overlap 1. */
 void fkt_default_options(fkt_options *opt);
 
 /*
@@ -176,10 +182,12 @@ fkt_status fkt_plan_target_counts(fkt_plan_t p, int64_t *far_nodes, int64_t *far
  * Device time of fkt_mvm's stages, summed over the calls made since the plan
  * was built with opt.profile != 0 (or since the last reset): ms[0] gather into
  * tree order, ms[1] source-to-multipole moments (incl. partial sums), ms[2]
- * multipole-to-target far field, ms[3] near field (incl. the scatter to the
- * caller's order). Times come from HIP events recorded on the plan's stream
- * around each stage. Synchronises those events. calls (may be NULL)
- * receives the number of column passes timed. reset != 0 clears the record.
+ * multipole-to-target far field, ms[3] near field, ms[4] the whole column pass
+ * (gather to scatter). Times come from HIP events recorded on the stream each
+ * stage runs on; with opt.overlap the near field shares the device with the
+ * far field, so ms[3] then includes that sharing and ms[4] < the sum of the
+ * stages. Synchronises those events. calls (may be NULL) receives the number
+ * of column passes timed. reset != 0 clears the record.
  * Errors: FKT_EINVAL (NULL, plan built without profile), FKT_EDEVICE.
  */
 fkt_status fkt_plan_stage_times(fkt_plan_t p, double *ms, int64_t *calls, int reset);

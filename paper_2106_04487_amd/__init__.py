@@ -53,7 +53,8 @@ class _Kernel(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
-                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int)]
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
+                ("overlap", ctypes.c_int)]
 
 
 _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
@@ -138,11 +139,12 @@ class Plan:
 
     def stage_times(self, reset: bool = False):
         """(ms per stage summed over profiled passes, passes): stages are
-        gather, s2m, m2t, near. Needs a plan built with profile=True."""
-        ms = np.zeros(4)
+        gather, s2m, m2t, near and the whole column pass ("column"). Needs a
+        plan built with profile=True."""
+        ms = np.zeros(5)
         calls = ctypes.c_int64(0)
         _check(_lib.fkt_plan_stage_times(self.handle, ms.ctypes.data, ctypes.byref(calls), int(reset)))
-        return dict(zip(("gather", "s2m", "m2t", "near"), ms.tolist())), calls.value
+        return dict(zip(("gather", "s2m", "m2t", "near", "column"), ms.tolist())), calls.value
 
     def close(self):
         if self._h:
@@ -158,9 +160,10 @@ class Plan:
 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
              variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
-             device: int | None = 0, stream=None, profile: bool = False) -> Plan:
+             device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True) -> Plan:
     """Build a plan. points: (n, d) array-like (host or device; copied to host
-    FP64 for the tree build). device=None builds a host-only plan."""
+    FP64 for the tree build). device=None builds a host-only plan. overlap
+    runs the near field on a second stream beside the far field."""
     if hasattr(points, "detach"):
         points = points.detach().to("cpu").double().numpy()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -181,6 +184,7 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     sh = None if device is None else _stream_handle(stream)
     opt.stream = sh
     opt.profile = int(bool(profile))
+    opt.overlap = int(bool(overlap))
     h = _P()
     _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
     return Plan(h, n, d, prec, device, sh)

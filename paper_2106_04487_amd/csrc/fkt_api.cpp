@@ -77,9 +77,9 @@ struct fkt_plan_s {
     std::vector<void*> allocs;
     fkt::DevPlan dp{};
     fkt::DevWork wk{};
-    struct Ev5 { hipEvent_t e[5]; };
-    std::vector<Ev5> prof;   // events of profiled column passes not yet summed
-    double prof_ms[4] = {0, 0, 0, 0};
+    struct Ev7 { hipEvent_t e[7]; };
+    std::vector<Ev7> prof;   // events of profiled column passes not yet summed
+    double prof_ms[5] = {0, 0, 0, 0, 0};
     int64_t prof_calls = 0;
     // block-Jacobi factors, built on first use for a given sigma2
     double bj_sigma2 = -1.0;
@@ -103,6 +103,9 @@ struct fkt_plan_s {
             DeviceScope ds(opt.device);
             (void)hipStreamSynchronize(stream);
             drop_events();
+            if (wk.side) (void)hipStreamDestroy(wk.side);
+            if (wk.fork) (void)hipEventDestroy(wk.fork);
+            if (wk.join) (void)hipEventDestroy(wk.join);
             for (void* q : allocs) (void)hipFree(q);
             for (void* q : bj_allocs) (void)hipFree(q);
         }
@@ -140,6 +143,7 @@ void fkt_default_options(fkt_options* opt)
     opt->device = 0;
     opt->stream = nullptr;
     opt->profile = 0;
+    opt->overlap = 1;
 }
 
 const char* fkt_last_error(void) { return g_err.c_str(); }
@@ -222,6 +226,11 @@ static fkt_status upload_plan(fkt_plan_t P)
         return hip_fail(e, "moment buffer");
     if ((e = P->alloc(es * L.npartials * P->tab.rank, &P->wk.part)) != hipSuccess)
         return hip_fail(e, "partial-moment buffer");
+    // second stream (default priority) and fork/join events for running the
+    // near field beside the far field
+    if ((e = hipStreamCreateWithFlags(&P->wk.side, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    if ((e = hipEventCreateWithFlags(&P->wk.fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreateWithFlags(&P->wk.join, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
     return FKT_OK;
 }
 
@@ -311,13 +320,14 @@ fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
     for (int c = 0; c < nrhs; ++c) {
         hipEvent_t* ev = nullptr;
         if (P->opt.profile) {
-            fkt_plan_s::Ev5 q{};
+            fkt_plan_s::Ev7 q{};
             for (auto& e : q.e)
                 if (hipEventCreate(&e) != hipSuccess) return fail(FKT_EDEVICE, "hipEventCreate");
             P->prof.push_back(q);
             ev = P->prof.back().e;
         }
-        hipError_t e = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, P->stream, ev);
+        hipError_t e = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, P->stream,
+                                              P->opt.overlap != 0, ev);
         if (e != hipSuccess) return hip_fail(e, "fkt_mvm launch");
     }
     return FKT_OK;
@@ -329,17 +339,20 @@ fkt_status fkt_plan_stage_times(fkt_plan_t P, double* ms, int64_t* calls, int re
     if (!P->opt.profile) return fail(FKT_EINVAL, "plan was built without opt.profile");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    // intervals: gather e0-e1, s2m e1-e2, m2t e2-e3, near e4-e5, column e0-e6
+    static const int from[5] = {0, 1, 2, 4, 0}, to[5] = {1, 2, 3, 5, 6};
     for (auto& q : P->prof) {
-        if (hipEventSynchronize(q.e[4]) != hipSuccess) return fail(FKT_EDEVICE, "hipEventSynchronize");
-        for (int i = 0; i < 4; ++i) {
+        if (hipEventSynchronize(q.e[6]) != hipSuccess) return fail(FKT_EDEVICE, "hipEventSynchronize");
+        for (int i = 0; i < 5; ++i) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, q.e[i], q.e[i + 1]) != hipSuccess) return fail(FKT_EDEVICE, "hipEventElapsedTime");
+            if (hipEventElapsedTime(&t, q.e[from[i]], q.e[to[i]]) != hipSuccess)
+                return fail(FKT_EDEVICE, "hipEventElapsedTime");
             P->prof_ms[i] += t;
         }
         P->prof_calls += 1;
     }
     P->drop_events();
-    for (int i = 0; i < 4; ++i) ms[i] = P->prof_ms[i];
+    for (int i = 0; i < 5; ++i) ms[i] = P->prof_ms[i];
     if (calls) *calls = P->prof_calls;
     if (reset) {
         for (double& v : P->prof_ms) v = 0.0;

@@ -45,6 +45,8 @@ struct DevWork {
     void* zacc;   // [n] per-target sum (far field stored, near field added), tree order
     void* mom;    // [nslots][rank]
     void* part;   // [npartials][rank]
+    hipStream_t side;    // second stream: the near field runs beside the far field
+    hipEvent_t fork, join;
 };
 
 // Far nodes per 64-lane far-field job: as many node moment sets as fit in
@@ -66,6 +68,6 @@ bool far_supported(int d, int p);
 // ev: NULL, or 5 events recorded before the gather and after the gather,
 // s2m, m2t and near stages.
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,
-                             int prec, hipStream_t s, hipEvent_t* ev);
+                             int prec, hipStream_t s, bool overlap, hipEvent_t* ev);
 
 }  // namespace fkt

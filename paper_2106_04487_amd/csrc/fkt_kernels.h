@@ -326,16 +326,19 @@ template <> __device__ __forceinline__ const float* hn_ptr<float>(const DevPlan&
 // ------------------------------------------------------------------ gather
 //
 // Packed source records in tree order: D coordinates then the weight of the
-// current right-hand-side column, stride src_stride(D) elements.
+// current right-hand-side column, stride src_stride(D) elements; the
+// per-target accumulator is cleared on the way.
 constexpr int src_stride(int d) { return d == 3 ? 4 : 6; }
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict__ perm, const T* __restrict__ pts,
-                                                const T* __restrict__ x, int nrhs, int col, T* __restrict__ src)
+                                                const T* __restrict__ x, int nrhs, int col, T* __restrict__ src,
+                                                T* __restrict__ zacc)
 {
     constexpr int S = src_stride(D);
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    zacc[i] = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) src[(size_t)i * S + a] = pts[(size_t)i * D + a];
     src[(size_t)i * S + D] = x[perm[i] * nrhs + col];
@@ -434,7 +437,8 @@ __global__ __launch_bounds__(256) void k_s2m_reduce(int nred, int R, const int* 
 // job; a job's node moments and centres are staged in LDS (two buffers: the
 // next job is fetched into registers while the current one computes), and
 // each lane adds its pair's value to its target's LDS accumulator. The block
-// then stores its 64 sums, which initialises zacc for the near field.
+// then adds its 64 sums to zacc (the near field, possibly running
+// concurrently, adds to the same accumulators).
 template <int D, int P, int KIND, typename T>
 __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zacc)
 {
@@ -567,7 +571,7 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
         buf ^= 1;
     }
     __syncthreads();
-    if (lane < cnt) zacc[tb + lane] = T(zblk[lane]);
+    if (lane < cnt) unsafeAtomicAdd(zacc + tb + lane, T(zblk[lane]));
 }
 
 // -------------------------------------------------------------- near field
@@ -671,9 +675,8 @@ template <> struct NearKernel<FKT_LAPLACE, float> {
 // Source-major near field: one wave per work unit (a source leaf l and up to
 // kNearUnitTargets targets of N_l, 64 at a time, one per lane). The leaf's
 // points stream through scalar registers; each target's sum is added to its
-// accumulator (which the far-field stage initialised) with one FP64/FP32
-// atomic per (target, leaf), so no lane ever idles on a target whose own walk
-// does not reach l.
+// accumulator with one FP64/FP32 atomic per (target, leaf), so no lane ever
+// idles on a target whose own walk does not reach l.
 template <int D, int KIND, typename T>
 __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, T* __restrict__ zacc,
                                                 T c0, T c1, T scale)
@@ -720,13 +723,6 @@ __global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restric
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) y[perm[i] * nrhs + col] = zacc[i];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero(int n, T* __restrict__ z)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) z[i] = T(0);
 }
 
 // ------------------------------------------------- built orders per dimension

@@ -68,43 +68,64 @@ bool run_near_d(const DevPlan& a, const T* src, T* zacc, hipStream_t s)
     }
 }
 
+// Stream layout of one column (overlap on):
+//   s:    gather (+ clear accumulators) -> fork -> s2m -> m2t -> wait join -> scatter
+//   side:                        wait fork -> near field -> join
+// Far and near fields both add into the accumulators, so they may run
+// concurrently. With overlap off every stage runs in order on s. Profiling
+// events (7, optional): e0 start, e1 after gather, e2 after s2m, e3 after
+// m2t, e4/e5 around the near field on its own stream, e6 after the scatter.
 template <typename T>
 hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int nrhs, int col, hipStream_t s,
-                      hipEvent_t* ev)
+                      bool overlap, hipEvent_t* ev)
 {
     const T* pts = std::is_same<T, float>::value ? (const T*)a.pts32 : (const T*)a.pts64;
     T* src = (T*)wk.src;
     T* zacc = (T*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
-    if (ev) (void)hipEventRecord(ev[0], s);
+    hipError_t e;
+    auto mark = [&](int i, hipStream_t q) -> hipError_t { return ev ? hipEventRecord(ev[i], q) : hipSuccess; };
+    if ((e = mark(0, s)) != hipSuccess) return e;
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
     default: return hipErrorInvalidValue;
     }
-    if (ev) (void)hipEventRecord(ev[1], s);
+    if ((e = mark(1, s)) != hipSuccess) return e;
+    overlap = overlap && wk.side != nullptr;
+    const hipStream_t sn = overlap ? wk.side : s;
+    auto near = [&]() -> hipError_t {
+        hipError_t r;
+        if ((r = mark(4, sn)) != hipSuccess) return r;
+        bool ok = false;
+        switch (a.d) {
+        case 3: ok = run_near_d<3, T>(a, src, zacc, sn); break;
+        case 4: ok = run_near_d<4, T>(a, src, zacc, sn); break;
+        case 5: ok = run_near_d<5, T>(a, src, zacc, sn); break;
+        default: break;
+        }
+        if (!ok) return hipErrorInvalidValue;
+        return mark(5, sn);
+    };
+    if (overlap) {
+        if ((e = hipEventRecord(wk.fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(wk.side, wk.fork, 0)) != hipSuccess) return e;
+        if ((e = near()) != hipSuccess) return e;
+        if ((e = hipEventRecord(wk.join, wk.side)) != hipSuccess) return e;
+    }
     const int prec = std::is_same<T, float>::value ? 1 : 0;
-    if (a.nslots > 0) {
-        if (!launch_s2m(a, wk, prec, s)) return hipErrorInvalidValue;
-        if (ev) (void)hipEventRecord(ev[2], s);
-        // stores the far field of every target: initialises zacc
-        if (!launch_m2t(a.kind, a, wk, prec, s)) return hipErrorInvalidValue;
-    } else {
-        if (ev) (void)hipEventRecord(ev[2], s);
-        hipLaunchKernelGGL((k_zero<T>), gg, gb, 0, s, a.n, zacc);
+    if (a.nslots > 0 && !launch_s2m(a, wk, prec, s)) return hipErrorInvalidValue;
+    if ((e = mark(2, s)) != hipSuccess) return e;
+    if (a.nslots > 0 && !launch_m2t(a.kind, a, wk, prec, s)) return hipErrorInvalidValue;
+    if ((e = mark(3, s)) != hipSuccess) return e;
+    if (overlap) {
+        if ((e = hipStreamWaitEvent(s, wk.join, 0)) != hipSuccess) return e;
+    } else if ((e = near()) != hipSuccess) {
+        return e;
     }
-    if (ev) (void)hipEventRecord(ev[3], s);
-    bool ok = false;
-    switch (a.d) {
-    case 3: ok = run_near_d<3, T>(a, src, zacc, s); break;
-    case 4: ok = run_near_d<4, T>(a, src, zacc, s); break;
-    case 5: ok = run_near_d<5, T>(a, src, zacc, s); break;
-    default: break;
-    }
-    if (!ok) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_scatter<T>), gg, gb, 0, s, a.n, a.perm, (const T*)zacc, y, nrhs, col);
-    if (ev) (void)hipEventRecord(ev[4], s);
+    if ((e = mark(6, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -121,10 +142,10 @@ bool far_supported(int d, int p)
 }
 
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col, int prec,
-                             hipStream_t s, hipEvent_t* ev)
+                             hipStream_t s, bool overlap, hipEvent_t* ev)
 {
-    if (prec == 1) return mvm_column<float>(a, wk, (const float*)x, (float*)y, nrhs, col, s, ev);
-    return mvm_column<double>(a, wk, (const double*)x, (double*)y, nrhs, col, s, ev);
+    if (prec == 1) return mvm_column<float>(a, wk, (const float*)x, (float*)y, nrhs, col, s, overlap, ev);
+    return mvm_column<double>(a, wk, (const double*)x, (double*)y, nrhs, col, s, overlap, ev);
 }
 
 }  // namespace fkt
