@@ -211,6 +211,7 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.red_slot, a.red_slot);
     FKT_UP(L.red_off, a.red_off);
     FKT_UP(P->tab.tbar, a.tbar);
+    FKT_UP(P->tab.exp2tab, a.exp2tab);
     {
         std::vector<double> h2(P->tab.hnorm.size());
         for (size_t i = 0; i < h2.size(); ++i) h2[i] = P->tab.hnorm[i] * P->tab.hnorm[i];

@@ -37,6 +37,7 @@ struct DevPlan {
     const double* tbar;           // [(k*(p+1)+j)*(p+1)+m]
     const double* hn64;           // squared harmonic normalisation (x Z_k), FP64
     const float* hn32;            //   and FP32 copy
+    const double* exp2tab;        // [256] 2^(j/256), FP64 exponential table
 };
 
 // Per-call work buffers (device) for one right-hand-side column.

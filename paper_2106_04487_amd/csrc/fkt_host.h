@@ -70,7 +70,10 @@ struct Tables {
     int64_t rank = 0;
     std::vector<double> tbar;   // [(k*(p+1) + j)*(p+1) + m]
     std::vector<double> hnorm;  // [((e-3)*(p+1) + mu)*(p+1) + n], e = 3..d
+    std::vector<double> exp2tab;  // [kExpTab] 2^(j / kExpTab), rounded to nearest
 };
+
+constexpr int kExpTab = 256;
 
 void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T);
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);

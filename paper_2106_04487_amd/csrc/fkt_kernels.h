@@ -248,6 +248,43 @@ __device__ __forceinline__ double exp_nonpos(double x)
     return __builtin_ldexp(p, (int)k);
 }
 
+// exp(x) for finite x <= 0 through a table of 2^(j/256) held in LDS (Tang's
+// table-driven method): x = (n/256) ln2 + f with n = round(256 x / ln2) and
+// |f| <= ln2/512, so e^x = 2^(n >> 8) 2^((n & 255)/256) e^f, with e^f by its
+// Taylor polynomial to degree 4 (truncation < 4e-17 relative). n is read from
+// the low word of x 256/ln2 + 1.5 2^52, whose rounding is the rounding of n.
+// x is clamped at -1100, where e^x is already zero in FP64.
+constexpr int kExpTabLen = 256;
+__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab)
+{
+    constexpr double kShift = 6755399441055744.0;               // 1.5 * 2^52
+    constexpr double kInvL = 369.3299304675746;                 // 256 / ln2
+    constexpr double kLHi = 0x1.62e42ff000000p-9;               // ln2/256 to 32 bits: k * kLHi exact
+    constexpr double kLLo = -1.6409824502660487e-13;            // ln2/256 - kLHi
+    x = fmax(x, -1100.0);
+    const double kn = fma(x, kInvL, kShift);
+    const int n = __double2loint(kn);
+    const double k = kn - kShift;
+    double f = fma(k, -kLHi, x);
+    f = fma(k, -kLLo, f);
+    double q = fma(f, 4.16666666666666666667e-02, 1.66666666666666666667e-01);
+    q = fma(q, f, 0.5);
+    q = fma(q, f, 1.0);
+    q = fma(q, f, 1.0);
+    return __builtin_ldexp(tab[n & (kExpTabLen - 1)] * q, n >> 8);
+}
+
+// c sqrt(d2) for d2 > 0: estimate y of 1/sqrt(d2), g = d2 y, e = 1 - g y,
+// c g (1 + e/2 + 3e^2/8) (the correction of rsqrt_pos, applied to c g).
+__device__ __forceinline__ double scaled_sqrt_pos(double d2, double c)
+{
+    const double y = __builtin_amdgcn_rsq(d2);
+    const double g = d2 * y;
+    const double e = fma(-g, y, 1.0);
+    const double h = c * g;
+    return fma(h * e, fma(0.375, e, 0.5), h);
+}
+
 // ------------------------------------------------------- radial derivatives
 //
 // K^(m)(r), m = 0..P, in FP64 (closed forms / recurrences per kernel).
@@ -584,35 +621,57 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
 template <int KIND, typename T>
 struct NearKernel;
 
+// FP64 evaluations take the exponential table in LDS (exp_tab); the FP32
+// ones ignore it. kBias is added to every squared distance: kernels that take
+// a square root get d2 >= 1e-300 > 0, which keeps coincident points off the
+// singular path of the reciprocal square root (their r becomes ~1e-150, where
+// K(r) = K(0) in FP64) without a branch.
 template <> struct NearKernel<FKT_GAUSSIAN, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double) { return exp_nonpos(c0 * d2); }
+    static constexpr bool kTable = true;
+    static constexpr double kBias = 0.0;
+    static __device__ __forceinline__ double eval(double d2, double c0, double, const double* tab)
+    {
+        return exp_tab(c0 * d2, tab);
+    }
 };
 template <> struct NearKernel<FKT_EXPONENTIAL, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    static constexpr bool kTable = true;
+    static constexpr double kBias = 1e-300;
+    static __device__ __forceinline__ double eval(double d2, double c0, double, const double* tab)
     {
-        const double r = d2 > 0.0 ? d2 * rsqrt_pos(d2) : 0.0;
-        return exp_nonpos(c0 * r);
+        return exp_tab(scaled_sqrt_pos(d2, c0), tab);  // c0 = -1/ell
     }
 };
 template <> struct NearKernel<FKT_MATERN32, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    static constexpr bool kTable = true;
+    static constexpr double kBias = 1e-300;
+    static __device__ __forceinline__ double eval(double d2, double c0, double, const double* tab)
     {
-        const double ar = d2 > 0.0 ? c0 * (d2 * rsqrt_pos(d2)) : 0.0;
-        return (1.0 + ar) * exp_nonpos(-ar);
+        const double ar = scaled_sqrt_pos(d2, c0);
+        return (1.0 + ar) * exp_tab(-ar, tab);
     }
 };
 template <> struct NearKernel<FKT_MATERN52, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    static constexpr bool kTable = true;
+    static constexpr double kBias = 1e-300;
+    static __device__ __forceinline__ double eval(double d2, double c0, double, const double* tab)
     {
-        const double ar = d2 > 0.0 ? c0 * (d2 * rsqrt_pos(d2)) : 0.0;
-        return (1.0 + ar + ar * ar * (1.0 / 3.0)) * exp_nonpos(-ar);
+        const double ar = scaled_sqrt_pos(d2, c0);
+        return fma(ar, fma(ar, 1.0 / 3.0, 1.0), 1.0) * exp_tab(-ar, tab);
     }
 };
 template <> struct NearKernel<FKT_RATQUAD, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double c1) { return pow(1.0 + c0 * d2, c1); }
+    static constexpr bool kTable = false;
+    static constexpr double kBias = 0.0;
+    static __device__ __forceinline__ double eval(double d2, double c0, double c1, const double*)
+    {
+        return pow(1.0 + c0 * d2, c1);
+    }
 };
 template <> struct NearKernel<FKT_CAUCHY, double> {
-    static __device__ __forceinline__ double eval(double d2, double c0, double)
+    static constexpr bool kTable = false;
+    static constexpr double kBias = 0.0;
+    static __device__ __forceinline__ double eval(double d2, double c0, double, const double*)
     {
         const double b = 1.0 + c0 * d2;  // >= 1
         double y = __builtin_amdgcn_rcp(b);
@@ -621,7 +680,9 @@ template <> struct NearKernel<FKT_CAUCHY, double> {
     }
 };
 template <> struct NearKernel<FKT_LAPLACE, double> {
-    static __device__ __forceinline__ double eval(double d2, double, double)
+    static constexpr bool kTable = false;
+    static constexpr double kBias = 0.0;
+    static __device__ __forceinline__ double eval(double d2, double, double, const double*)
     {
         const double y = rsqrt_pos(d2);
         return d2 > 0.0 ? y : 0.0;
@@ -631,42 +692,56 @@ template <> struct NearKernel<FKT_LAPLACE, double> {
 // FP32: hardware transcendental approximations (v_exp_f32 / v_log_f32 are
 // base 2; c0 is pre-scaled by log2(e) where an exponential follows).
 template <> struct NearKernel<FKT_GAUSSIAN, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float) { return __builtin_amdgcn_exp2f(c0 * d2); }
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float, const double*) { return __builtin_amdgcn_exp2f(c0 * d2); }
 };
 template <> struct NearKernel<FKT_EXPONENTIAL, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float, const double*)
     {
         return __builtin_amdgcn_exp2f(c0 * __builtin_amdgcn_sqrtf(d2));
     }
 };
 template <> struct NearKernel<FKT_MATERN32, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1, const double*)
     {
         const float r = __builtin_amdgcn_sqrtf(d2);
         return (1.0f + c1 * r) * __builtin_amdgcn_exp2f(c0 * r);
     }
 };
 template <> struct NearKernel<FKT_MATERN52, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1, const double*)
     {
         const float ar = c1 * __builtin_amdgcn_sqrtf(d2);
         return (1.0f + ar + ar * ar * (1.0f / 3.0f)) * __builtin_amdgcn_exp2f(c0 * ar);
     }
 };
 template <> struct NearKernel<FKT_RATQUAD, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float c1)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float c1, const double*)
     {
         return __builtin_amdgcn_exp2f(c1 * __builtin_amdgcn_logf(1.0f + c0 * d2));
     }
 };
 template <> struct NearKernel<FKT_CAUCHY, float> {
-    static __device__ __forceinline__ float eval(float d2, float c0, float)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float c0, float, const double*)
     {
         return __builtin_amdgcn_rcpf(1.0f + c0 * d2);
     }
 };
 template <> struct NearKernel<FKT_LAPLACE, float> {
-    static __device__ __forceinline__ float eval(float d2, float, float)
+    static constexpr bool kTable = false;
+    static constexpr float kBias = 0.0f;
+    static __device__ __forceinline__ float eval(float d2, float, float, const double*)
     {
         return d2 > 0.0f ? __builtin_amdgcn_rsqf(d2) : 0.0f;
     }
@@ -682,8 +757,18 @@ __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __rest
                                                 T c0, T c1, T scale)
 {
     constexpr int S = src_stride(D);
+    using NK = NearKernel<KIND, T>;
+    __shared__ double tab[NK::kTable ? kExpTabLen : 1];
     const int u = blockIdx.x;
     const int lane = threadIdx.x;
+    if constexpr (NK::kTable) {
+        double tv[kExpTabLen / kWave];
+#pragma unroll
+        for (int j = 0; j < kExpTabLen / kWave; ++j) tv[j] = a.exp2tab[j * kWave + lane];
+#pragma unroll
+        for (int j = 0; j < kExpTabLen / kWave; ++j) tab[j * kWave + lane] = tv[j];
+        __syncthreads();
+    }
     const int s0 = a.nu_beg[u], m = a.nu_end[u] - s0;
     const int toff = a.nu_toff[u], tcnt = a.nu_tcnt[u];
     const T* __restrict__ q = src + (size_t)s0 * S;
@@ -695,13 +780,13 @@ __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __rest
 #pragma unroll
         for (int k = 0; k < D; ++k) tx[k] = src[(size_t)t * S + k];
         auto pair = [&](const T* __restrict__ p) {
-            T d2 = T(0);
+            T d2 = T(NK::kBias);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const T w = tx[k] - p[k];
                 d2 = fma(w, w, d2);
             }
-            return NearKernel<KIND, T>::eval(d2, c0, c1) * p[D];
+            return NK::eval(d2, c0, c1, tab) * p[D];
         };
         T acc0 = T(0), acc1 = T(0);
         int s = 0;

@@ -412,6 +412,8 @@ void build_tables(int d, int p, Tables& tab)
     tab.p = p;
     const ld alpha = (ld)d / 2 - 1;
     const int P1 = p + 1;
+    tab.exp2tab.resize(kExpTab);
+    for (int j = 0; j < kExpTab; ++j) tab.exp2tab[j] = (double)std::exp2((ld)j / kExpTab);
     tab.tbar.assign((size_t)P1 * P1 * P1, 0.0);
     // Tbar_{k,j,m} = sum_n A_{k,2n-j} (-2)^{2n-j} C(n, 2n-j) B_{n,m} / n!  (the
     // binomial of the binomial expansion of eps^n is kept).
