@@ -1,0 +1,144 @@
+"""Learned per-leaf spectral preconditioner: plain FP64 CPU reference.
+
+TEST INFRASTRUCTURE ONLY, like the rest of ``oracle/``: only ``tests/`` may
+use it. Shares no code with the HIP path.
+
+Not part of the paper (the paper solves Gaussian-process systems through
+kernel MVMs only, Sec. 5.3 and eq. gp_posterior); it is the preconditioner
+this project adds for CG on A = K~ + sigma2 I. Definitions:
+
+* leaf block  A_l = K(X_l, X_l) + sigma2 I = V_l^T diag(lam_l) V_l
+  (``numpy.linalg.eigh``; rows of V_l are eigenvectors, lam ascending);
+* features of eigenvalue i of leaf l (m points):
+  [log(lam_i / sigma2) / 8, log(lam_max / sigma2) / 8, m / leaf_size, (i + 1/2) / m];
+* network (per feature row f): h1 = tanh(f W1 + b1), h2 = tanh(h1 W2 + b2),
+  o = h2 . w3 + b3;
+* filter   h_{l,i} = exp(o_{l,i}) / lam_{l,i},  M_l = V_l^T diag(h_l) V_l;
+* loss     L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2;
+* gradient through the chain rule with A taken as symmetric:
+  dL/dw_b = (2 / (B |v_b|^2)) A (A M v_b - v_b), dL/dh_{l,i} = sum_b
+  (V_l dL/dw_b)_i (V_l v_b)_i, dL/do = h dL/dh, then back through the MLP.
+
+The parameter vector is ordered W1 [4][256], b1, W2 [256][256], b2, w3, b3.
+Pins (tests/test_oracle_learned.py): with o = 0 the filter is the exact
+inverse of every leaf block (block-Jacobi), and the analytic gradient
+matches central differences of L when A is an exactly symmetric matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dense_mvm
+
+H = 256
+F = 4
+SIZES = [("W1", (F, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", ())]
+NPARAMS = sum(int(np.prod(s)) for _, s in SIZES)
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    assert theta.shape == (NPARAMS,)
+    out, k = {}, 0
+    for name, shape in SIZES:
+        size = int(np.prod(shape))
+        out[name] = theta[k:k + size].reshape(shape)
+        k += size
+    return out
+
+
+def pack(p) -> np.ndarray:
+    return np.concatenate([np.ravel(np.asarray(p[name], dtype=np.float64)) for name, _ in SIZES])
+
+
+def leaf_ranges(tree):
+    """(start, end) tree positions of the leaves, in preorder."""
+    return [(int(tree.start[b]), int(tree.end[b])) for b in range(tree.nnodes) if tree.is_leaf(b)]
+
+
+def leaf_block(Xl, kind, sigma2, **kw) -> np.ndarray:
+    """K(X_l, X_l) + sigma2 I from the oracle's dense sum (identity columns)."""
+    m = Xl.shape[0]
+    A = np.zeros((m, m))
+    for c0 in range(0, m, 64):
+        c1 = min(m, c0 + 64)
+        E = np.zeros((m, c1 - c0))
+        E[np.arange(c0, c1), np.arange(c1 - c0)] = 1.0
+        A[:, c0:c1] = dense_mvm(Xl, E, kind, **kw)
+    A = 0.5 * (A + A.T)
+    return A + sigma2 * np.eye(m)
+
+
+def leaf_spectra(tree, X, kind, sigma2, leaf_size, **kw):
+    """Per leaf: dict(idx = original indices, lam, V (rows), feat [m][4])."""
+    X = np.asarray(X, dtype=np.float64)
+    out = []
+    for s, e in leaf_ranges(tree):
+        idx = tree.perm[s:e].copy()
+        A = leaf_block(X[idx], kind, sigma2, **kw)
+        lam, U = np.linalg.eigh(A)
+        m = e - s
+        feat = np.stack([np.log(lam / sigma2) / 8.0, np.full(m, np.log(lam[-1] / sigma2) / 8.0),
+                         np.full(m, m / leaf_size), (np.arange(m) + 0.5) / m], axis=1)
+        out.append(dict(idx=idx, lam=lam, V=U.T.copy(), feat=feat, A=A))
+    return out
+
+
+def mlp_forward(theta, feat):
+    p = unpack(theta)
+    h1 = np.tanh(feat @ p["W1"] + p["b1"])
+    h2 = np.tanh(h1 @ p["W2"] + p["b2"])
+    o = h2 @ p["w3"] + p["b3"]
+    return o, (feat, h1, h2)
+
+
+def mlp_backward(theta, cache, go) -> np.ndarray:
+    """Gradient of sum_s go[s] o[s] with respect to theta."""
+    p = unpack(theta)
+    feat, h1, h2 = cache
+    d2 = np.outer(go, p["w3"]) * (1.0 - h2 ** 2)
+    d1 = (d2 @ p["W2"].T) * (1.0 - h1 ** 2)
+    g = dict(W1=feat.T @ d1, b1=d1.sum(0), W2=h1.T @ d2, b2=d2.sum(0), w3=h2.T @ go, b3=np.sum(go))
+    return pack(g)
+
+
+def filters(spectra, theta):
+    """h for every leaf (list of arrays) and the MLP cache over all leaves."""
+    feat = np.concatenate([L["feat"] for L in spectra], axis=0)
+    o, cache = mlp_forward(theta, feat)
+    hs, k = [], 0
+    for L in spectra:
+        m = len(L["lam"])
+        hs.append(np.exp(o[k:k + m]) / L["lam"])
+        k += m
+    return hs, cache
+
+
+def apply_filter(spectra, hs, v) -> np.ndarray:
+    """M v for v (n x B) in the original order."""
+    v = np.asarray(v, dtype=np.float64)
+    w = np.zeros_like(v)
+    for L, h in zip(spectra, hs):
+        c = L["V"] @ v[L["idx"]]
+        w[L["idx"]] = L["V"].T @ (h[:, None] * c)
+    return w
+
+
+def loss_grad(spectra, theta, v, op):
+    """(L, dL/dtheta) for the batch v (n x B); op(x) = A x for n x B x."""
+    v = np.asarray(v, dtype=np.float64)
+    if v.ndim == 1:
+        v = v[:, None]
+    B = v.shape[1]
+    hs, cache = filters(spectra, theta)
+    w = apply_filter(spectra, hs, v)
+    r = op(w) - v
+    vv = np.sum(v * v, axis=0)
+    loss = float(np.mean(np.sum(r * r, axis=0) / vv))
+    g = op(r) * (2.0 / (B * vv))[None, :]
+    go = []
+    for L, h in zip(spectra, hs):
+        c = L["V"] @ v[L["idx"]]
+        q = L["V"] @ g[L["idx"]]
+        go.append(h * np.sum(c * q, axis=1))
+    return loss, mlp_backward(theta, cache, np.concatenate(go))
