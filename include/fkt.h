@@ -133,7 +133,8 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  *   rtol      stop when ||b - A x||_2 <= rtol ||b||_2 for every column.
  *   maxit     iteration cap, >= 1.
  *   precond   0 none, 1 block-Jacobi (per-leaf dense Cholesky of
- *             K_ll + sigma2 I).
+ *             K_ll + sigma2 I), 2 the learned per-leaf spectral filter
+ *             (fkt_learn_*, current weights; block-Jacobi until trained).
  *   iters     host, receives the iteration count (may be NULL).
  *   relres    host, receives max over columns of the final relative
  *             residual (may be NULL).
@@ -191,6 +192,46 @@ fkt_status fkt_plan_target_counts(fkt_plan_t p, int64_t *far_nodes, int64_t *far
  * Errors: FKT_EINVAL (NULL, plan built without profile), FKT_EDEVICE.
  */
 fkt_status fkt_plan_stage_times(fkt_plan_t p, double *ms, int64_t *calls, int reset);
+
+/*
+ * Learned per-leaf preconditioner (not part of the paper's method; used by
+ * fkt_cg_solve with precond = 2). For each leaf l, the near-field diagonal
+ * block A_l = K(X_l, X_l) + sigma2 I = V_l^T diag(lam_l) V_l is
+ * eigendecomposed on the host, and the preconditioner is
+ *     M = blockdiag(V_l^T diag(h_l) V_l),   h_{l,i} = exp(o_{l,i}) / lam_{l,i},
+ * with o_{l,i} the output of one MLP, FP32, 4 -> 256 (tanh) -> 256 (tanh) -> 1,
+ * applied to the features of eigenvalue i of leaf l:
+ *     [log(lam_i / sigma2) / 8, log(lam_max / sigma2) / 8, m_l / leaf_size, (i + 1/2) / m_l]
+ * (ascending eigenvalues, m_l points in the leaf). M is symmetric positive
+ * definite for any weights; o = 0 (the initial last layer is zero) makes it
+ * block-Jacobi. Training minimises L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2
+ * for Gaussian v_b with A = the plan's MVM + sigma2 I, its gradient taking A
+ * as symmetric. Needs leaves of at most 2048 points and sigma2 > 0; the first
+ * call for a sigma2 builds the spectra (host, O(leaf^3) per leaf).
+ *
+ * Parameters (FP32, fkt_learn_nparams() of them) in the order W1 [4][256],
+ * b1 [256], W2 [256][256] (hidden = tanh(h1 W2 + b2)), b2 [256], w3 [256], b3.
+ */
+int64_t fkt_learn_nparams(void);
+
+/* params: host buffer of fkt_learn_nparams() floats; set = 0 copies the
+ * current weights out, set != 0 replaces them. Errors: FKT_EINVAL,
+ * FKT_EUNSUPPORTED (leaves > 2048), FKT_EDEVICE, FKT_ENOMEM. */
+fkt_status fkt_learn_params(fkt_plan_t p, double sigma2, float *params, int set);
+
+/* Loss L and its gradient for the given batch. v: device, n x batch FP64
+ * row-major, caller's point order (1 <= batch <= 64). loss: host; grad: host
+ * buffer of fkt_learn_nparams() floats or NULL. Does not change the weights.
+ * Synchronises the plan's stream. */
+fkt_status fkt_learn_loss_grad(fkt_plan_t p, double sigma2, const double *v, int batch, double *loss, float *grad);
+
+/* `steps` Adam steps (lr, beta1 0.9, beta2 0.999, eps 1e-8), each on a fresh
+ * batch of `batch` Gaussian vectors drawn on the device (SplitMix64 counter
+ * hash + Box-Muller, keyed by seed and step). loss_first / loss_last (host,
+ * may be NULL) receive the loss of the first and of the last step's batch
+ * (before that step's update). Synchronises the plan's stream. */
+fkt_status fkt_learn_train(fkt_plan_t p, double sigma2, int steps, int batch, double lr, uint64_t seed,
+                           double *loss_first, double *loss_last);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,8 @@ STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "F
           5: "FKT_ENOTCONV"}
 
 EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_destroy", "fkt_last_error",
-            "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times"]
+            "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times",
+            "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train"]
 
 
 class FktError(RuntimeError):
@@ -85,6 +86,15 @@ _lib.fkt_plan_target_counts.restype = ctypes.c_int
 _lib.fkt_plan_target_counts.argtypes = [_P, _P, _P, _P, _P]
 _lib.fkt_plan_stage_times.restype = ctypes.c_int
 _lib.fkt_plan_stage_times.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+_lib.fkt_learn_nparams.restype = ctypes.c_int64
+_lib.fkt_learn_nparams.argtypes = []
+_lib.fkt_learn_params.restype = ctypes.c_int
+_lib.fkt_learn_params.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int]
+_lib.fkt_learn_loss_grad.restype = ctypes.c_int
+_lib.fkt_learn_loss_grad.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]
+_lib.fkt_learn_train.restype = ctypes.c_int
+_lib.fkt_learn_train.argtypes = [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 
 
 def _check(status: int):
@@ -216,10 +226,15 @@ def fkt_mvm(plan: Plan, x, y=None):
     return y
 
 
+PRECONDS = {"none": 0, "block_jacobi": 1, "learned": 2}
+
+
 def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,
-                 precond: int = 0):
-    """Solve (K~ + sigma2 I) x = b by CG. Returns (x, iters, relres); if maxit
-    is reached raises FktError(FKT_ENOTCONV) carrying .x, .iters, .relres."""
+                 precond=0):
+    """Solve (K~ + sigma2 I) x = b by CG. precond: 0/"none", 1/"block_jacobi",
+    2/"learned". Returns (x, iters, relres); if maxit is reached raises
+    FktError(FKT_ENOTCONV) carrying .x, .iters, .relres."""
+    precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
     import torch
     b = _device_matrix(plan, b, "b")
     x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0").clone()
@@ -234,6 +249,46 @@ def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, m
         raise err
     _check(st)
     return x, it.value, rr.value
+
+
+def fkt_learn_nparams() -> int:
+    return int(_lib.fkt_learn_nparams())
+
+
+def fkt_learn_params(plan: Plan, sigma2: float, params=None) -> np.ndarray:
+    """Current weights of the learned preconditioner (FP32 vector); with
+    params given, replaces them first."""
+    buf = np.zeros(fkt_learn_nparams(), dtype=np.float32)
+    if params is not None:
+        buf[:] = np.asarray(params, dtype=np.float32)
+        _check(_lib.fkt_learn_params(plan.handle, float(sigma2), buf.ctypes.data, 1))
+    _check(_lib.fkt_learn_params(plan.handle, float(sigma2), buf.ctypes.data, 0))
+    return buf
+
+
+def fkt_learn_loss_grad(plan: Plan, sigma2: float, v):
+    """(loss, gradient) of the learned preconditioner's training objective
+    for the batch v (n x B, FP64; host or device)."""
+    import torch
+    v = torch.as_tensor(v, dtype=torch.float64, device="cuda")
+    if v.dim() == 1:
+        v = v[:, None]
+    v = v.contiguous()
+    loss = ctypes.c_double(0.0)
+    grad = np.zeros(fkt_learn_nparams(), dtype=np.float32)
+    _check(_lib.fkt_learn_loss_grad(plan.handle, float(sigma2), v.data_ptr(), v.shape[1], ctypes.byref(loss),
+                                    grad.ctypes.data))
+    return loss.value, grad
+
+
+def fkt_learn_train(plan: Plan, sigma2: float, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 1):
+    """Adam steps on device-drawn Gaussian batches; returns (loss of the
+    first step, loss of the last step)."""
+    l0 = ctypes.c_double(float("nan"))
+    l1 = ctypes.c_double(float("nan"))
+    _check(_lib.fkt_learn_train(plan.handle, float(sigma2), int(steps), int(batch), float(lr), int(seed),
+                                ctypes.byref(l0), ctypes.byref(l1)))
+    return l0.value, l1.value
 
 
 def fkt_destroy(plan: Plan):

@@ -35,6 +35,9 @@ def _jobs():
         ([*dev, "-c", os.path.join(CSRC, "mvm.hip"), "-o", os.path.join(BUILD, "mvm.o")]),
         ([*dev, "-c", os.path.join(CSRC, "stage_s2m.hip"), "-o", os.path.join(BUILD, "stage_s2m.o")]),
         ([*dev, "-c", os.path.join(CSRC, "cg.hip"), "-o", os.path.join(BUILD, "cg.o")]),
+        (["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-c",
+          os.path.join(CSRC, "learn_host.cpp"), "-o", os.path.join(BUILD, "learn_host.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "learn.hip"), "-o", os.path.join(BUILD, "learn.o")]),
     ]
     # one multipole-to-target object per kernel kind (fkt_kernel_kind 0..6)
     for kind in range(7):

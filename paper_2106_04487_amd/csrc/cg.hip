@@ -11,6 +11,8 @@
 #include <vector>
 
 #include "../../include/fkt.h"
+#include "fkt_device.h"
+#include "fkt_learn.h"
 
 namespace {
 
@@ -127,19 +129,6 @@ struct Buf {
 }  // namespace
 
 namespace fkt {
-// set by the C-ABI layer: plan precision, size, stream and device
-struct CgPlanView {
-    int64_t n;
-    int prec;
-    int device;
-    hipStream_t stream;
-    const int64_t* perm;     // device: tree position -> original index
-    int nleaf, maxleaf;      // block-Jacobi blocks (precond = 1)
-    const int* bj_begin;
-    const int* bj_count;
-    const int64_t* bj_off;
-    const double* bj_inv;
-};
 fkt_status cg_set_error(fkt_status st, const std::string& msg);
 }  // namespace fkt
 
@@ -184,6 +173,11 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
                 hipLaunchKernelGGL(k_bj_apply, dim3(v.nleaf), dim3(kThreads), sizeof(double) * v.maxleaf, s, v.bj_begin,
                                    v.bj_count, v.bj_off, v.bj_inv, v.perm, nrhs, c2, in, out);
             return hipGetLastError() == hipSuccess;
+        }
+        if (precond == 2) {
+            for (int c2 = 0; c2 < nrhs; ++c2)
+                if (learn_apply(v.learn, in, out, nrhs, c2, s) != hipSuccess) return false;
+            return true;
         }
         return hipMemcpyAsync(out, in, sizeof(double) * m, hipMemcpyDeviceToDevice, s) == hipSuccess;
     };
@@ -245,7 +239,10 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres)
 {
-    if (precond != 0 && precond != 1) return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
+    if (precond < 0 || precond > 2 || (precond == 2 && !v.learn))
+        return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
+    if (precond == 2 && learn_prepare_filter(v.learn) != hipSuccess)
+        return cg_set_error(FKT_EDEVICE, "learned preconditioner forward pass");
     if (v.prec == 1)
         return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters, relres);
     return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters, relres);

@@ -11,6 +11,7 @@
 #include "../../include/fkt.h"
 #include "fkt_device.h"
 #include "fkt_host.h"
+#include "fkt_learn.h"
 
 namespace {
 
@@ -46,18 +47,6 @@ struct DeviceScope {
 }  // namespace
 
 namespace fkt {
-struct CgPlanView {
-    int64_t n;
-    int prec;
-    int device;
-    hipStream_t stream;
-    const int64_t* perm;
-    int nleaf, maxleaf;
-    const int* bj_begin;
-    const int* bj_count;
-    const int64_t* bj_off;
-    const double* bj_inv;
-};
 fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres);
@@ -89,6 +78,9 @@ struct fkt_plan_s {
     const int64_t* bj_off = nullptr;
     const double* bj_inv = nullptr;
     std::vector<void*> bj_allocs;
+    // learned spectral preconditioner, built on first use for a given sigma2
+    fkt::LearnState* learn = nullptr;
+    double learn_sigma2 = -1.0;
 
     void drop_events()
     {
@@ -108,6 +100,7 @@ struct fkt_plan_s {
             if (wk.join) (void)hipEventDestroy(wk.join);
             for (void* q : allocs) (void)hipFree(q);
             for (void* q : bj_allocs) (void)hipFree(q);
+            fkt::learn_destroy(learn);
         }
     }
 
@@ -410,6 +403,31 @@ fkt_status fkt_plan_target_counts(fkt_plan_t P, int64_t* far_nodes, int64_t* far
     return FKT_OK;
 }
 
+// Spectra of the leaf blocks for sigma2 (host eigendecompositions) and the
+// network's device state; weights are kept across sigma2 changes.
+static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
+{
+    if (P->learn && P->learn_sigma2 == sigma2) return FKT_OK;
+    int64_t big = 0;
+    for (int64_t b = 0; b < P->T.nnodes(); ++b)
+        if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
+    if (big > fkt::kLearnMaxLeaf) return fail(FKT_EUNSUPPORTED, "the learned preconditioner needs leaves of at most 2048 points");
+    if (!(sigma2 > 0.0)) return fail(FKT_EINVAL, "the learned preconditioner needs sigma2 > 0");
+    fkt::LeafSpectra S;
+    if (!fkt::build_leaf_spectra(P->T, P->kern, sigma2, P->leaf, S))
+        return fail(FKT_EINVAL, "a leaf block K_ll + sigma2 I has no positive spectrum (or the eigensolver failed)");
+    if (!P->learn) {
+        std::string err;
+        P->learn = fkt::learn_create(P->opt.device, P->stream, S, P->dp.perm, P->n, 0x5EEDull, err);
+        if (!P->learn) return fail(FKT_ENOMEM, err);
+    } else {
+        const hipError_t e = fkt::learn_update_spectra(P->learn, S);
+        if (e != hipSuccess) return hip_fail(e, "learned preconditioner spectra upload");
+    }
+    P->learn_sigma2 = sigma2;
+    return FKT_OK;
+}
+
 fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
                         int precond, int* iters, double* relres)
 {
@@ -420,9 +438,13 @@ fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int
     if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be >= 0");
     if (!(rtol > 0.0)) return fail(FKT_EINVAL, "rtol must be > 0");
     if (maxit < 1) return fail(FKT_EINVAL, "maxit must be >= 1");
-    if (precond < 0 || precond > 1) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
+    if (precond < 0 || precond > 2) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    if (precond == 2) {
+        const fkt_status st = ensure_learn(P, sigma2);
+        if (st != FKT_OK) return st;
+    }
     if (precond == 1 && P->st.nleaves > 0) {
         int64_t big = 0;
         for (int64_t b = 0; b < P->T.nnodes(); ++b)
@@ -458,9 +480,61 @@ fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int
         for (int32_t c : lc) P->bj_maxleaf = std::max(P->bj_maxleaf, (int)c);
         P->bj_sigma2 = sigma2;
     }
-    fkt::CgPlanView v{P->n, (int)P->opt.prec, P->opt.device, P->stream, P->dp.perm, P->bj_nleaf, P->bj_maxleaf,
-                      P->bj_begin, P->bj_count, P->bj_off, P->bj_inv};
+    fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream, P->dp.perm, P->bj_nleaf,
+                      P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off, P->bj_inv, P->learn};
     return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres);
+}
+
+static fkt_status learn_entry(fkt_plan_t P, double sigma2)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) has no learned preconditioner");
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be > 0");
+    return ensure_learn(P, sigma2);
+}
+
+int64_t fkt_learn_nparams(void) { return fkt::kLearnParams; }
+
+fkt_status fkt_learn_params(fkt_plan_t P, double sigma2, float* params, int set)
+{
+    if (!params) return fail(FKT_EINVAL, "params is NULL");
+    DeviceScope ds(P ? P->opt.device : 0);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt_status st = learn_entry(P, sigma2);
+    if (st != FKT_OK) return st;
+    const hipError_t e = fkt::learn_params(P->learn, params, set != 0);
+    return e == hipSuccess ? FKT_OK : hip_fail(e, "learned preconditioner parameters");
+}
+
+fkt_status fkt_learn_loss_grad(fkt_plan_t P, double sigma2, const double* v, int batch, double* loss, float* grad)
+{
+    if (!v || !loss) return fail(FKT_EINVAL, "v or loss is NULL");
+    if (batch < 1 || batch > 64) return fail(FKT_EINVAL, "batch must be in [1, 64]");
+    DeviceScope ds(P ? P->opt.device : 0);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt_status st = learn_entry(P, sigma2);
+    if (st != FKT_OK) return st;
+    st = fkt::learn_loss_grad(P, P->learn, (int)P->opt.prec, sigma2, v, batch, loss);
+    if (st != FKT_OK) return fail(st, "learned preconditioner loss/gradient");
+    if (grad) {
+        const hipError_t e = fkt::learn_grad(P->learn, grad);
+        if (e != hipSuccess) return hip_fail(e, "learned preconditioner gradient copy");
+    }
+    return FKT_OK;
+}
+
+fkt_status fkt_learn_train(fkt_plan_t P, double sigma2, int steps, int batch, double lr, uint64_t seed,
+                           double* loss_first, double* loss_last)
+{
+    if (steps < 0) return fail(FKT_EINVAL, "steps must be >= 0");
+    if (batch < 1 || batch > 64) return fail(FKT_EINVAL, "batch must be in [1, 64]");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return fail(FKT_EINVAL, "lr must be > 0");
+    DeviceScope ds(P ? P->opt.device : 0);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt_status st = learn_entry(P, sigma2);
+    if (st != FKT_OK) return st;
+    st = fkt::learn_train(P, P->learn, (int)P->opt.prec, sigma2, steps, batch, lr, seed, loss_first, loss_last);
+    return st == FKT_OK ? FKT_OK : fail(st, "learned preconditioner training");
 }
 
 }  // extern "C"

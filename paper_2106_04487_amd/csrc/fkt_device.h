@@ -68,6 +68,22 @@ bool far_supported(int d, int p);
 // prec: 0 FP64, 1 FP32.
 // ev: NULL, or 5 events recorded before the gather and after the gather,
 // s2m, m2t and near stages.
+// What CG needs of a plan (set by the C-ABI layer).
+struct LearnState;
+struct CgPlanView {
+    int64_t n;
+    int prec;
+    int device;
+    hipStream_t stream;
+    const int64_t* perm;     // device: tree position -> original index
+    int nleaf, maxleaf;      // block-Jacobi blocks (precond = 1)
+    const int* bj_begin;
+    const int* bj_count;
+    const int64_t* bj_off;
+    const double* bj_inv;
+    LearnState* learn;       // learned spectral filter (precond = 2)
+};
+
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,
                              int prec, hipStream_t s, bool overlap, hipEvent_t* ev);
 

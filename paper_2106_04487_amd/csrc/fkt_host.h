@@ -93,4 +93,22 @@ int64_t binom(int64_t a, int64_t b);
 // Simple parallel-for over [0, n) on host threads.
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn);
 
+// Symmetric eigendecomposition of the n x n row-major matrix a (overwritten):
+// on return w holds the eigenvalues in ascending order and row i of a the
+// unit eigenvector of w[i]. False if the QR iteration does not converge.
+bool sym_eig(int n, double* a, double* w);
+
+// Spectra of the leaves' near-field diagonal blocks K(X_l, X_l) + sigma2 I
+// (tree order) and the network's features, one row per eigenvalue.
+constexpr int kLearnFeat = 4;
+struct LeafSpectra {
+    std::vector<int32_t> leaf_begin, leaf_count;
+    std::vector<int64_t> off;   // [nleaves + 1] into vecs
+    std::vector<double> vecs;   // per leaf m x m, row i = eigenvector i
+    std::vector<double> vals;   // [n] eigenvalues, ascending within each leaf
+    std::vector<float> feat;    // [n][kLearnFeat]
+    int max_leaf = 0;
+};
+bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int leaf_cap, LeafSpectra& S);
+
 }  // namespace fkt

@@ -1,0 +1,36 @@
+// Learned per-leaf spectral preconditioner (device state and operations);
+// see learn.hip for the method.
+#ifndef FKT_LEARN_H
+#define FKT_LEARN_H
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fkt_host.h"
+
+namespace fkt {
+
+constexpr int kLearnHidden = 256;
+constexpr int kLearnFeatures = kLearnFeat;
+constexpr int kLearnParams = kLearnFeatures * kLearnHidden + kLearnHidden + kLearnHidden * kLearnHidden + kLearnHidden +
+                             kLearnHidden + 1;
+constexpr int kLearnMaxLeaf = 2048;  // LDS of the apply kernel: 2 x leaf doubles
+
+struct LearnState;
+LearnState* learn_create(int device, hipStream_t s, const LeafSpectra& S, const int64_t* perm, int64_t n, uint64_t seed,
+                         std::string& err);
+void learn_destroy(LearnState* L);
+hipError_t learn_update_spectra(LearnState* L, const LeafSpectra& S);
+hipError_t learn_params(LearnState* L, float* host, bool set);
+hipError_t learn_grad(LearnState* L, float* host);
+hipError_t learn_prepare_filter(LearnState* L);
+hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s);
+fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, const double* v, int B, double* loss);
+fkt_status learn_train(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int B, double lr, uint64_t seed,
+                       double* loss_first, double* loss_last);
+
+}  // namespace fkt
+
+#endif

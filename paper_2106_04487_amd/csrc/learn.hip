@@ -1,0 +1,682 @@
+// Learned per-leaf preconditioner for CG on (K~ + sigma2 I) x = b.
+//
+// Not part of the paper's method (the paper solves Gaussian-process systems
+// through MVMs, Sec. 5.3); it is built on the near-field diagonal blocks the
+// plan produces. Each leaf block A_l = K(X_l, X_l) + sigma2 I = V_l^T
+// diag(lam_l) V_l (host eigendecomposition) gets the filter
+//     M_l = V_l^T diag(h_l) V_l,   h_{l,i} = exp(o_{l,i}) / lam_{l,i},
+// where o is the output of one MLP (4 features -> 256 tanh -> 256 tanh -> 1,
+// FP32) evaluated for every eigenvalue of every leaf. M = blockdiag(M_l) is
+// symmetric positive definite for any weights, so plain PCG stays valid;
+// with o = 0 it is block-Jacobi exactly (the initial state: the last layer
+// starts at zero).
+//
+// Training minimises L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2 over
+// Gaussian v_b, with A the plan's own operator (FKT MVM + sigma2). Its
+// gradient takes A as symmetric (the kernel matrix is; the FKT operator is
+// within its approximation error):
+//   g_b = (2 / (B |v_b|^2)) A (A M v_b - v_b),
+//   dL/dh_{l,i} = sum_b (V_l g_{l,b})_i (V_l v_{l,b})_i,   dL/do = h dL/dh,
+// then back through the MLP with this file's kernels (MFMA GEMMs for the
+// 256 x 256 layer), and an Adam step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fkt.h"
+#include "fkt_learn.h"
+
+namespace fkt {
+namespace {
+
+constexpr int kH = kLearnHidden;
+constexpr int kF = kLearnFeatures;
+constexpr int kT = 256;  // threads of the elementwise / per-leaf kernels
+
+// parameter layout (FP32): W1 [F][H], b1 [H], W2 [H][H], b2 [H], w3 [H], b3
+constexpr int oW1 = 0, ob1 = oW1 + kF * kH, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH, ob3 = ow3 + kH;
+constexpr int kNP = ob3 + 1;
+static_assert(kNP == kLearnParams, "parameter count");
+
+unsigned blocks_of(int64_t m, int per = kT) { return (unsigned)((m + per - 1) / per); }
+
+// ------------------------------------------------------------ MFMA GEMM
+//
+// C[M x N] = op(A) op(B), FP32, v_mfma_f32_16x16x4f32. A workgroup of four
+// waves owns a 64 x 64 tile of C (each wave 32 x 32: 2 x 2 MFMA tiles) and
+// walks K in steps of 16 staged through LDS. op(A) = A (stored [M][K]) or
+// A^T (stored [K][M]); op(B) = B (stored [K][N]) or B^T (stored [N][K]).
+// M, N multiples of 64 and K (per split) a multiple of 16, checked by the
+// host. Epilogues:
+//   kEpiStore      C = acc
+//   kEpiTanhBias   C = tanh(acc + bias[n])
+//   kEpiDTanh      C = acc * (1 - aux[m][n]^2)
+//   kEpiSplit      C[z] = acc over the z-th K range (partial sums)
+enum { kEpiStore = 0, kEpiTanhBias = 1, kEpiDTanh = 2, kEpiSplit = 3 };
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int kchunk, const float* __restrict__ A,
+                                              const float* __restrict__ B, float* __restrict__ C,
+                                              const float* __restrict__ aux)
+{
+    __shared__ float As[64][17];   // [m][k]
+    __shared__ float Bs[16][68];   // [k][n]
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        if (!TA) {  // A [M][K]: thread -> row m, 4 consecutive k
+            const int m = t >> 2, k4 = (t & 3) * 4;
+            const f4 v = *(const f4*)(A + (size_t)(m0 + m) * K + k0 + k4);
+            As[m][k4 + 0] = v[0]; As[m][k4 + 1] = v[1]; As[m][k4 + 2] = v[2]; As[m][k4 + 3] = v[3];
+        } else {    // A stored [K][M]: thread -> row k, 4 consecutive m
+            const int k = t >> 4, m4 = (t & 15) * 4;
+            const f4 v = *(const f4*)(A + (size_t)(k0 + k) * M + m0 + m4);
+            As[m4 + 0][k] = v[0]; As[m4 + 1][k] = v[1]; As[m4 + 2][k] = v[2]; As[m4 + 3][k] = v[3];
+        }
+        if (!TB) {  // B [K][N]
+            const int k = t >> 4, n4 = (t & 15) * 4;
+            const f4 v = *(const f4*)(B + (size_t)(k0 + k) * N + n0 + n4);
+            Bs[k][n4 + 0] = v[0]; Bs[k][n4 + 1] = v[1]; Bs[k][n4 + 2] = v[2]; Bs[k][n4 + 3] = v[3];
+        } else {    // B stored [N][K]
+            const int n = t >> 2, k4 = (t & 3) * 4;
+            const f4 v = *(const f4*)(B + (size_t)(n0 + n) * K + k0 + k4);
+            Bs[k4 + 0][n] = v[0]; Bs[k4 + 1][n] = v[1]; Bs[k4 + 2][n] = v[2]; Bs[k4 + 3][n] = v[3];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            float a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wn + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* __restrict__ Cz = EPI == kEpiSplit ? C + (size_t)blockIdx.z * M * N : C;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r, n = n0 + wn + j * 16 + (lane & 15);
+                float v = acc[i][j][r];
+                if constexpr (EPI == kEpiTanhBias) v = tanhf(v + aux[n]);
+                if constexpr (EPI == kEpiDTanh) {
+                    const float hv = aux[(size_t)m * N + n];
+                    v *= 1.f - hv * hv;
+                }
+                Cz[(size_t)m * N + n] = v;
+            }
+}
+
+// ------------------------------------------------------------ MLP pieces
+
+// H1 = tanh(X W1 + b1), X [Sp][F]
+__global__ __launch_bounds__(kT) void k_layer1(int64_t Sp, const float* __restrict__ X, const float* __restrict__ P,
+                                               float* __restrict__ H1)
+{
+    const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (g >= Sp * kH) return;
+    const int64_t s = g / kH;
+    const int c = (int)(g % kH);
+    float v = P[ob1 + c];
+#pragma unroll
+    for (int f = 0; f < kF; ++f) v = fmaf(X[s * kF + f], P[oW1 + f * kH + c], v);
+    H1[g] = tanhf(v);
+}
+
+// o[s] = H2[s,:] . w3 + b3: one wave per row
+__global__ __launch_bounds__(kT) void k_layer3(int64_t Sp, const float* __restrict__ H2, const float* __restrict__ P,
+                                               float* __restrict__ o)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (s >= Sp) return;
+    float v = 0.f;
+#pragma unroll
+    for (int j = 0; j < kH / 64; ++j) v = fmaf(H2[s * kH + lane + 64 * j], P[ow3 + lane + 64 * j], v);
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) v += __shfl_xor(v, w, 64);
+    if (lane == 0) o[s] = v + P[ob3];
+}
+
+// h = exp(o) / lam (FP64)
+__global__ __launch_bounds__(kT) void k_filter(int64_t n, const float* __restrict__ o, const double* __restrict__ lam,
+                                               double* __restrict__ h)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) h[i] = exp((double)o[i]) / lam[i];
+}
+
+// D2 = go (x) w3 * (1 - H2^2)
+__global__ __launch_bounds__(kT) void k_dlayer2(int64_t Sp, const float* __restrict__ go, const float* __restrict__ P,
+                                                const float* __restrict__ H2, float* __restrict__ D2)
+{
+    const int64_t g = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (g >= Sp * kH) return;
+    const int64_t s = g / kH;
+    const int c = (int)(g % kH);
+    const float hv = H2[g];
+    D2[g] = go[s] * P[ow3 + c] * (1.f - hv * hv);
+}
+
+// partial[chunk][r][c] = sum over rows s of the chunk of w_r(s) A[s][c] for
+// c < ncols: rows r < nw take weights W[s][r] (W is [Sp][nw]), and with
+// ones a last row of weight 1 follows.
+constexpr int kRedRows = 1024;
+__global__ __launch_bounds__(kT) void k_colred(int64_t Sp, int ncols, const float* __restrict__ A, int lda, bool ones,
+                                               const float* __restrict__ W, int nw, float* __restrict__ partial)
+{
+    const int c = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * kRedRows, s1 = min(Sp, s0 + kRedRows);
+    const int R = nw + (ones ? 1 : 0);
+    float accw[kF], acc1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < kF; ++q) accw[q] = 0.f;
+    if (c >= ncols) return;
+    for (int64_t s = s0; s < s1; ++s) {
+        const float a = A[s * lda + c];
+        acc1 += a;
+#pragma unroll
+        for (int q = 0; q < kF; ++q)
+            if (q < nw) accw[q] = fmaf(W[s * nw + q], a, accw[q]);
+    }
+    float* out = partial + (size_t)blockIdx.x * R * ncols;
+#pragma unroll
+    for (int q = 0; q < kF; ++q)
+        if (q < nw) out[(size_t)q * ncols + c] = accw[q];
+    if (ones) out[(size_t)nw * ncols + c] = acc1;
+}
+
+// out[i] = sum_z part[z][i], i < len
+__global__ __launch_bounds__(kT) void k_sum_partials(int nz, int64_t len, const float* __restrict__ part,
+                                                     float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= len) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += part[(size_t)z * len + i];
+    out[i] = s;
+}
+
+// Adam (beta1 0.9, beta2 0.999, eps 1e-8), step t >= 1
+__global__ __launch_bounds__(kT) void k_adam(int np, float* __restrict__ p, const float* __restrict__ g,
+                                             float* __restrict__ m, float* __restrict__ v, float lr, float c1,
+                                             float c2)
+{
+    const int i = blockIdx.x * kT + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi, vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// ------------------------------------------------------ spectral kernels
+//
+// One workgroup per leaf; leaf points are tree positions b..b+m-1, the
+// caller's rows perm[b + i]. V [m][m] row i = eigenvector i, Vt = V^T.
+
+// out[tree b+i][col] = sum_j V[i][j] x[perm[b+j]][col]   (c = V x)
+__global__ __launch_bounds__(kT) void k_spec_proj(const int* __restrict__ begin, const int* __restrict__ count,
+                                                  const int64_t* __restrict__ off, const double* __restrict__ Vt,
+                                                  const int64_t* __restrict__ perm, int nrhs, int col,
+                                                  const double* __restrict__ x, double* __restrict__ out, int ldo)
+{
+    extern __shared__ double xl[];
+    const int l = blockIdx.x, b = begin[l], m = count[l];
+    const double* __restrict__ Q = Vt + off[l];
+    for (int j = threadIdx.x; j < m; j += kT) xl[j] = x[perm[b + j] * nrhs + col];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kT) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s = fma(Q[(size_t)j * m + i], xl[j], s);
+        out[(size_t)(b + i) * ldo + col] = s;
+    }
+}
+
+// y[perm[b+j]][col] = sum_i V[i][j] h[b+i] c[tree b+i][col]   (y = V^T (h c))
+__global__ __launch_bounds__(kT) void k_spec_recon(const int* __restrict__ begin, const int* __restrict__ count,
+                                                   const int64_t* __restrict__ off, const double* __restrict__ V,
+                                                   const int64_t* __restrict__ perm, const double* __restrict__ h,
+                                                   const double* __restrict__ c, int ldc, int nrhs, int col,
+                                                   double* __restrict__ y)
+{
+    extern __shared__ double cl[];
+    const int l = blockIdx.x, b = begin[l], m = count[l];
+    const double* __restrict__ Q = V + off[l];
+    for (int i = threadIdx.x; i < m; i += kT) cl[i] = h[b + i] * c[(size_t)(b + i) * ldc + col];
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += kT) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s = fma(Q[(size_t)i * m + j], cl[i], s);
+        y[perm[b + j] * nrhs + col] = s;
+    }
+}
+
+// z = M r for one column (CG): c = V r in LDS, scaled by h, then V^T.
+__global__ __launch_bounds__(kT) void k_spec_apply(const int* __restrict__ begin, const int* __restrict__ count,
+                                                   const int64_t* __restrict__ off, const double* __restrict__ V,
+                                                   const double* __restrict__ Vt, const int64_t* __restrict__ perm,
+                                                   const double* __restrict__ h, int nrhs, int col,
+                                                   const double* __restrict__ r, double* __restrict__ z)
+{
+    extern __shared__ double sh[];
+    const int l = blockIdx.x, b = begin[l], m = count[l];
+    double* rl = sh;
+    double* cl = sh + m;
+    for (int j = threadIdx.x; j < m; j += kT) rl[j] = r[perm[b + j] * nrhs + col];
+    __syncthreads();
+    const double* __restrict__ Qt = Vt + off[l];
+    for (int i = threadIdx.x; i < m; i += kT) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s = fma(Qt[(size_t)j * m + i], rl[j], s);
+        cl[i] = h[b + i] * s;
+    }
+    __syncthreads();
+    const double* __restrict__ Q = V + off[l];
+    for (int j = threadIdx.x; j < m; j += kT) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s = fma(Q[(size_t)i * m + j], cl[i], s);
+        z[perm[b + j] * nrhs + col] = s;
+    }
+}
+
+// go[i] = h_i (2/B) sum_b c[i][b] p[i][b] / vv[b]  (FP32 out), 0 for padding
+__global__ __launch_bounds__(kT) void k_dout(int64_t n, int64_t Sp, int B, const double* __restrict__ h,
+                                             const double* __restrict__ c, const double* __restrict__ p,
+                                             const double* __restrict__ vv, float* __restrict__ go)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= Sp) return;
+    if (i >= n) {
+        go[i] = 0.f;
+        return;
+    }
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += c[i * B + b] * p[i * B + b] / vv[b];
+    go[i] = (float)(h[i] * 2.0 / B * s);
+}
+
+// ------------------------------------------------------ batch helpers
+
+// per-block partial column dots of a and b ([n][B] row-major)
+constexpr int kDotBlocks = 256;
+__global__ __launch_bounds__(kT) void k_coldot(int64_t n, int B, const double* __restrict__ a,
+                                               const double* __restrict__ b, double* __restrict__ partial)
+{
+    __shared__ double sh[kT];
+    for (int c = 0; c < B; ++c) {
+        double s = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+            s += a[i * B + c] * b[i * B + c];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = kT / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blockIdx.x * B + c] = sh[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_cvt(int64_t m, const double* __restrict__ a, T* __restrict__ b)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < m) b[i] = (T)a[i];
+}
+
+// r = (double)kw + sigma2 w - v ; ([n][B])
+template <typename T>
+__global__ __launch_bounds__(kT) void k_resid(int64_t m, const T* __restrict__ kw, const double* __restrict__ w,
+                                              const double* __restrict__ v, double sigma2, double* __restrict__ r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < m) r[i] = (double)kw[i] + sigma2 * w[i] - (v ? v[i] : 0.0);
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) as a counter-based hash,
+// then Box-Muller: x[i] ~ N(0, 1).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(kT) void k_randn(int64_t m, uint64_t key, double* __restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t a = splitmix64(key ^ (2 * (uint64_t)i)), b = splitmix64(key ^ (2 * (uint64_t)i + 1));
+    const double u1 = ((a >> 11) + 1) * 0x1.0p-53;  // (0, 1]
+    const double u2 = (b >> 11) * 0x1.0p-53;        // [0, 1)
+    x[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ state
+
+struct LearnState {
+    int device = 0;
+    hipStream_t s = nullptr;
+    int64_t n = 0, Sp = 0;
+    int nleaf = 0, maxleaf = 0;
+    const int64_t* perm = nullptr;  // plan's, not owned
+    int* leaf_begin = nullptr;
+    int* leaf_count = nullptr;
+    int64_t* off = nullptr;
+    double *V = nullptr, *Vt = nullptr, *lam = nullptr, *h = nullptr;
+    float *X = nullptr, *P = nullptr, *G = nullptr, *Am = nullptr, *Av = nullptr;
+    float *H1 = nullptr, *H2 = nullptr, *D2 = nullptr, *D1 = nullptr, *o = nullptr, *go = nullptr;
+    float *part = nullptr;
+    int nsplit = 1, nchunks = 1;
+    int64_t adam_t = 0;
+    std::vector<void*> allocs;
+
+    template <class T>
+    hipError_t get(size_t count, T** out)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+        if (e == hipSuccess) allocs.push_back(q);
+        *out = (T*)q;
+        return e;
+    }
+    ~LearnState()
+    {
+        (void)hipStreamSynchronize(s);
+        for (void* q : allocs) (void)hipFree(q);
+    }
+};
+
+void learn_destroy(LearnState* L) { delete L; }
+
+// deterministic initial weights: W1, W2 ~ N(0, 1/fan_in) from SplitMix64 and
+// Box-Muller on the host, biases 0, last layer 0 (so that o = 0: block-Jacobi)
+static void init_params(uint64_t seed, std::vector<float>& p)
+{
+    p.assign(kNP, 0.f);
+    auto mix = [](uint64_t z) {
+        z += 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto normal = [&](uint64_t i) {
+        const double u1 = ((mix(seed ^ (2 * i)) >> 11) + 1) * 0x1.0p-53, u2 = (mix(seed ^ (2 * i + 1)) >> 11) * 0x1.0p-53;
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+    };
+    for (int i = 0; i < kF * kH; ++i) p[oW1 + i] = (float)(normal(i) / std::sqrt((double)kF));
+    for (int i = 0; i < kH * kH; ++i) p[oW2 + i] = (float)(normal(kF * kH + i) / std::sqrt((double)kH));
+}
+
+LearnState* learn_create(int device, hipStream_t s, const LeafSpectra& S, const int64_t* perm, int64_t n, uint64_t seed,
+                         std::string& err)
+{
+    LearnState* L = new LearnState();
+    L->device = device;
+    L->s = s;
+    L->n = n;
+    L->Sp = (n + 63) / 64 * 64;
+    L->nleaf = (int)S.leaf_begin.size();
+    L->maxleaf = S.max_leaf;
+    L->perm = perm;
+    L->nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, L->Sp / 2048));
+    L->nchunks = (int)((L->Sp + kRedRows - 1) / kRedRows);
+    const int64_t Sp = L->Sp;
+    std::vector<double> vt(S.vecs.size());
+    for (int l = 0; l < L->nleaf; ++l) {
+        const int m = S.leaf_count[l];
+        const double* a = S.vecs.data() + S.off[l];
+        double* b = vt.data() + S.off[l];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) b[(size_t)j * m + i] = a[(size_t)i * m + j];
+    }
+    std::vector<float> X((size_t)Sp * kF, 0.f);
+    std::copy(S.feat.begin(), S.feat.end(), X.begin());
+    std::vector<float> p0;
+    init_params(seed, p0);
+    auto up = [&](const void* src, size_t bytes, void* dst) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
+    hipError_t e = hipSuccess;
+    const size_t part_n = std::max((size_t)L->nsplit * kH * kH, (size_t)L->nchunks * (1 + kF) * kH);
+    if ((e = L->get(L->nleaf, &L->leaf_begin)) || (e = L->get(L->nleaf, &L->leaf_count)) ||
+        (e = L->get(L->nleaf + 1, &L->off)) || (e = L->get(S.vecs.size(), &L->V)) || (e = L->get(vt.size(), &L->Vt)) ||
+        (e = L->get(n, &L->lam)) || (e = L->get(n, &L->h)) || (e = L->get((size_t)Sp * kF, &L->X)) ||
+        (e = L->get(kNP, &L->P)) || (e = L->get(kNP, &L->G)) || (e = L->get(kNP, &L->Am)) || (e = L->get(kNP, &L->Av)) ||
+        (e = L->get((size_t)Sp * kH, &L->H1)) || (e = L->get((size_t)Sp * kH, &L->H2)) ||
+        (e = L->get((size_t)Sp * kH, &L->D2)) || (e = L->get((size_t)Sp * kH, &L->D1)) || (e = L->get(Sp, &L->o)) ||
+        (e = L->get(Sp, &L->go)) || (e = L->get(part_n, &L->part)) ||
+        (e = up(S.leaf_begin.data(), sizeof(int) * L->nleaf, L->leaf_begin)) ||
+        (e = up(S.leaf_count.data(), sizeof(int) * L->nleaf, L->leaf_count)) ||
+        (e = up(S.off.data(), sizeof(int64_t) * (L->nleaf + 1), L->off)) ||
+        (e = up(S.vecs.data(), sizeof(double) * S.vecs.size(), L->V)) ||
+        (e = up(vt.data(), sizeof(double) * vt.size(), L->Vt)) || (e = up(S.vals.data(), sizeof(double) * n, L->lam)) ||
+        (e = up(X.data(), sizeof(float) * X.size(), L->X)) || (e = up(p0.data(), sizeof(float) * kNP, L->P)) ||
+        (e = hipMemset(L->Am, 0, sizeof(float) * kNP)) || (e = hipMemset(L->Av, 0, sizeof(float) * kNP))) {
+        err = std::string("learned preconditioner allocation/upload: ") + hipGetErrorString(e);
+        delete L;
+        return nullptr;
+    }
+    return L;
+}
+
+// new spectra and features (another sigma2); weights and Adam state kept
+hipError_t learn_update_spectra(LearnState* L, const LeafSpectra& S)
+{
+    std::vector<double> vt(S.vecs.size());
+    for (int l = 0; l < L->nleaf; ++l) {
+        const int m = S.leaf_count[l];
+        const double* a = S.vecs.data() + S.off[l];
+        double* b = vt.data() + S.off[l];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) b[(size_t)j * m + i] = a[(size_t)i * m + j];
+    }
+    std::vector<float> X((size_t)L->Sp * kF, 0.f);
+    std::copy(S.feat.begin(), S.feat.end(), X.begin());
+    hipError_t e;
+    if ((e = hipStreamSynchronize(L->s)) != hipSuccess) return e;
+    if ((e = hipMemcpy(L->V, S.vecs.data(), sizeof(double) * S.vecs.size(), hipMemcpyHostToDevice))) return e;
+    if ((e = hipMemcpy(L->Vt, vt.data(), sizeof(double) * vt.size(), hipMemcpyHostToDevice))) return e;
+    if ((e = hipMemcpy(L->lam, S.vals.data(), sizeof(double) * L->n, hipMemcpyHostToDevice))) return e;
+    return hipMemcpy(L->X, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t learn_params(LearnState* L, float* host, bool set)
+{
+    hipError_t e = hipStreamSynchronize(L->s);
+    if (e != hipSuccess) return e;
+    if (set) return hipMemcpy(L->P, host, sizeof(float) * kNP, hipMemcpyHostToDevice);
+    return hipMemcpy(host, L->P, sizeof(float) * kNP, hipMemcpyDeviceToHost);
+}
+
+// forward pass over all eigenvalues, then h = exp(o) / lam
+static hipError_t forward(LearnState* L)
+{
+    const int64_t Sp = L->Sp;
+    hipStream_t s = L->s;
+    hipLaunchKernelGGL(k_layer1, dim3(blocks_of(Sp * kH)), dim3(kT), 0, s, Sp, L->X, L->P, L->H1);
+    hipLaunchKernelGGL((k_gemm<false, false, kEpiTanhBias>), dim3(Sp / 64, kH / 64, 1), dim3(256), 0, s, (int)Sp, kH,
+                       kH, kH, L->H1, L->P + oW2, L->H2, L->P + ob2);
+    hipLaunchKernelGGL(k_layer3, dim3(blocks_of(Sp, kT / 64)), dim3(kT), 0, s, Sp, L->H2, L->P, L->o);
+    hipLaunchKernelGGL(k_filter, dim3(blocks_of(L->n)), dim3(kT), 0, s, L->n, L->o, L->lam, L->h);
+    return hipGetLastError();
+}
+
+hipError_t learn_prepare_filter(LearnState* L) { return forward(L); }
+
+hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spec_apply, dim3(L->nleaf), dim3(kT), sizeof(double) * 2 * L->maxleaf, s, L->leaf_begin,
+                       L->leaf_count, L->off, L->V, L->Vt, L->perm, L->h, nrhs, col, r, z);
+    return hipGetLastError();
+}
+
+// backward from go (set by k_dout) into G
+static hipError_t backward(LearnState* L)
+{
+    const int64_t Sp = L->Sp;
+    hipStream_t s = L->s;
+    hipLaunchKernelGGL(k_dlayer2, dim3(blocks_of(Sp * kH)), dim3(kT), 0, s, Sp, L->go, L->P, L->H2, L->D2);
+    // dW2 = H1^T D2 (split over the rows), into G + oW2
+    const int kchunk = (int)((Sp / L->nsplit + 15) / 16 * 16);
+    hipLaunchKernelGGL((k_gemm<true, false, kEpiSplit>), dim3(kH / 64, kH / 64, L->nsplit), dim3(256), 0, s, kH, kH,
+                       (int)Sp, kchunk, L->H1, L->D2, L->part, (const float*)nullptr);
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of((int64_t)kH * kH)), dim3(kT), 0, s, L->nsplit,
+                       (int64_t)kH * kH, L->part, L->G + oW2);
+    // db2 = colsum D2 (G + ob2); dw3 = H2^T go (G + ow3); db3 = sum go (G + ob3)
+    hipLaunchKernelGGL(k_colred, dim3(L->nchunks), dim3(kT), 0, s, Sp, kH, L->D2, kH, true, (const float*)nullptr, 0,
+                       L->part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, L->nchunks, (int64_t)kH, L->part, L->G + ob2);
+    hipLaunchKernelGGL(k_colred, dim3(L->nchunks), dim3(kT), 0, s, Sp, kH, L->H2, kH, false, L->go, 1, L->part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, L->nchunks, (int64_t)kH, L->part, L->G + ow3);
+    hipLaunchKernelGGL(k_colred, dim3(L->nchunks), dim3(kT), 0, s, Sp, 1, L->go, 1, true, (const float*)nullptr, 0,
+                       L->part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kT), 0, s, L->nchunks, (int64_t)1, L->part, L->G + ob3);
+    // D1 = (D2 W2^T) * (1 - H1^2)
+    hipLaunchKernelGGL((k_gemm<false, true, kEpiDTanh>), dim3(Sp / 64, kH / 64, 1), dim3(256), 0, s, (int)Sp, kH, kH,
+                       kH, L->D2, L->P + oW2, L->D1, L->H1);
+    // [dW1; db1] = [X, 1]^T D1: rows W1[0..F-1] then b1, contiguous at G + oW1
+    hipLaunchKernelGGL(k_colred, dim3(L->nchunks), dim3(kT), 0, s, Sp, kH, L->D1, kH, true, L->X, kF, L->part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks_of((int64_t)(1 + kF) * kH)), dim3(kT), 0, s, L->nchunks,
+                       (int64_t)(1 + kF) * kH, L->part, L->G + oW1);
+    return hipGetLastError();
+}
+
+// loss and gradient for the batch v ([n][B] caller order, FP64, device)
+fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, const double* v, int B, double* loss)
+{
+    const int64_t n = L->n, m = n * B;
+    hipStream_t s = L->s;
+    std::vector<void*> tmp;
+    auto get = [&](size_t bytes, void** out) {
+        hipError_t e = hipMalloc(out, bytes ? bytes : 256);
+        if (e == hipSuccess) tmp.push_back(*out);
+        return e;
+    };
+    struct Free {
+        std::vector<void*>& t;
+        ~Free()
+        {
+            for (void* q : t) (void)hipFree(q);
+        }
+    } fr{tmp};
+    double *c, *w, *r, *g, *pp, *part, *vv;
+    void *op_in, *op_out;
+    const size_t es = prec == 1 ? sizeof(float) : sizeof(double);
+    if (get(sizeof(double) * m, (void**)&c) || get(sizeof(double) * m, (void**)&w) || get(sizeof(double) * m, (void**)&r) ||
+        get(sizeof(double) * m, (void**)&g) || get(sizeof(double) * m, (void**)&pp) ||
+        get(sizeof(double) * kDotBlocks * B, (void**)&part) || get(sizeof(double) * B, (void**)&vv) ||
+        get(es * m, &op_in) || get(es * m, &op_out))
+        return FKT_ENOMEM;
+    std::vector<double> hp((size_t)kDotBlocks * B), nv(B), nr(B);
+    auto coldots = [&](const double* a, const double* b, std::vector<double>& out) -> bool {
+        hipLaunchKernelGGL(k_coldot, dim3(kDotBlocks), dim3(kT), 0, s, n, B, a, b, part);
+        if (hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        out.assign(B, 0.0);
+        for (int k = 0; k < kDotBlocks; ++k)
+            for (int q = 0; q < B; ++q) out[q] += hp[(size_t)k * B + q];
+        return true;
+    };
+    auto op = [&](const double* in, const double* sub, double* out) -> fkt_status {
+        // out = A in - sub, A = FKT MVM (plan precision) + sigma2
+        if (prec == 1) {
+            hipLaunchKernelGGL((k_cvt<float>), dim3(blocks_of(m)), dim3(kT), 0, s, m, in, (float*)op_in);
+            fkt_status st = fkt_mvm(P, op_in, op_out, B);
+            if (st != FKT_OK) return st;
+            hipLaunchKernelGGL((k_resid<float>), dim3(blocks_of(m)), dim3(kT), 0, s, m, (const float*)op_out, in, sub,
+                               sigma2, out);
+        } else {
+            fkt_status st = fkt_mvm(P, in, op_out, B);
+            if (st != FKT_OK) return st;
+            hipLaunchKernelGGL((k_resid<double>), dim3(blocks_of(m)), dim3(kT), 0, s, m, (const double*)op_out, in, sub,
+                               sigma2, out);
+        }
+        return hipGetLastError() == hipSuccess ? FKT_OK : FKT_EDEVICE;
+    };
+    if (forward(L) != hipSuccess) return FKT_EDEVICE;
+    const size_t lds = sizeof(double) * L->maxleaf;
+    for (int b = 0; b < B; ++b) {
+        hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
+                           L->perm, B, b, v, c, B);
+        hipLaunchKernelGGL(k_spec_recon, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->V,
+                           L->perm, L->h, c, B, B, b, w);
+    }
+    fkt_status st = op(w, v, r);  // r = A M v - v
+    if (st != FKT_OK) return st;
+    if (!coldots(v, v, nv) || !coldots(r, r, nr)) return FKT_EDEVICE;
+    double lsum = 0.0;
+    for (int b = 0; b < B; ++b) lsum += nv[b] > 0.0 ? nr[b] / nv[b] : 0.0;
+    *loss = lsum / B;
+    st = op(r, nullptr, g);  // g = A r (A taken as symmetric)
+    if (st != FKT_OK) return st;
+    for (int b = 0; b < B; ++b)
+        hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
+                           L->perm, B, b, g, pp, B);
+    if (hipMemcpyAsync(vv, nv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s) != hipSuccess) return FKT_EDEVICE;
+    hipLaunchKernelGGL(k_dout, dim3(blocks_of(L->Sp)), dim3(kT), 0, s, n, L->Sp, B, L->h, c, pp, vv, L->go);
+    if (backward(L) != hipSuccess) return FKT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return FKT_EDEVICE;
+    return FKT_OK;
+}
+
+hipError_t learn_grad(LearnState* L, float* host)
+{
+    hipError_t e = hipStreamSynchronize(L->s);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(host, L->G, sizeof(float) * kNP, hipMemcpyDeviceToHost);
+}
+
+fkt_status learn_train(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int B, double lr, uint64_t seed,
+                       double* loss_first, double* loss_last)
+{
+    const int64_t m = L->n * B;
+    double* v = nullptr;
+    if (hipMalloc(&v, sizeof(double) * m) != hipSuccess) return FKT_ENOMEM;
+    fkt_status st = FKT_OK;
+    for (int it = 0; it < steps; ++it) {
+        const uint64_t key = seed * 0x2545F4914F6CDD1Dull + (uint64_t)it * 0x9E3779B97F4A7C15ull;
+        hipLaunchKernelGGL(k_randn, dim3(blocks_of(m)), dim3(kT), 0, L->s, m, key, v);
+        double loss = 0.0;
+        st = learn_loss_grad(P, L, prec, sigma2, v, B, &loss);
+        if (st != FKT_OK) break;
+        if (it == 0 && loss_first) *loss_first = loss;
+        if (loss_last) *loss_last = loss;
+        L->adam_t += 1;
+        const float c1 = 1.f - std::pow(0.9f, (float)L->adam_t), c2 = 1.f - std::pow(0.999f, (float)L->adam_t);
+        hipLaunchKernelGGL(k_adam, dim3(blocks_of(kNP)), dim3(kT), 0, L->s, kNP, L->P, L->G, L->Am, L->Av, (float)lr, c1,
+                           c2);
+        if (hipGetLastError() != hipSuccess) {
+            st = FKT_EDEVICE;
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(L->s);
+    (void)hipFree(v);
+    return st;
+}
+
+}  // namespace fkt

@@ -1,0 +1,93 @@
+"""Learned per-leaf spectral preconditioner on the GPU against the oracle
+(oracle/learned.py): parameters, loss and gradient parity, the block-Jacobi
+starting point, and what training gains CG over no preconditioner."""
+import numpy as np
+import pytest
+
+import fkt_workloads as W
+import oracle
+from oracle import learned as LR
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2106_04487_amd as F
+    return F
+
+
+def _gp_points(n, seed):
+    return W.gaussian_mixture(n, 4, 8, 0.15, seed)
+
+
+def test_params_roundtrip(F):
+    X = _gp_points(1500, 61)
+    plan = F.fkt_plan(X, "matern52", 128, 4, theta=0.4, lengthscale=0.3)
+    p0 = F.fkt_learn_params(plan, 1e-2)
+    assert p0.shape == (LR.NPARAMS,) and F.fkt_learn_nparams() == LR.NPARAMS
+    P = LR.unpack(p0.astype(np.float64))
+    assert np.all(P["w3"] == 0.0) and P["b3"] == 0.0  # initial state: block-Jacobi
+    q = np.random.default_rng(3).normal(0, 0.1, LR.NPARAMS).astype(np.float32)
+    got = F.fkt_learn_params(plan, 1e-2, q)
+    assert np.array_equal(got, q)
+    plan.close()
+
+
+def test_initial_filter_is_block_jacobi(F):
+    import torch
+    X = _gp_points(3000, 62)
+    sig2 = 1e-2
+    plan = F.fkt_plan(X, "matern52", 128, 6, theta=0.35, lengthscale=0.1)
+    b = torch.as_tensor(W.normal_rhs(3000, 1, 63)[:, 0], device="cuda")
+    its = {}
+    for pc in ("block_jacobi", "learned"):
+        _, it, rr = F.fkt_cg_solve(plan, sig2, b, rtol=1e-8, maxit=2000, precond=pc)
+        its[pc] = it
+    print("CG iterations at the initial weights:", its)
+    assert abs(its["learned"] - its["block_jacobi"]) <= 2
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64"])
+def test_loss_and_gradient_match_oracle(F, prec):
+    n, leaf, theta, p, sig2 = 2500, 100, 0.4, 5, 1e-2
+    X = _gp_points(n, 64)
+    kw = dict(lengthscale=0.3)
+    plan = F.fkt_plan(X, "matern52", leaf, p, theta=theta, prec=prec, **kw)
+    params = np.random.default_rng(5).normal(0.0, 0.15, LR.NPARAMS).astype(np.float32)
+    F.fkt_learn_params(plan, sig2, params)
+    v = W.normal_rhs(n, 3, 65)
+    loss, grad = F.fkt_learn_loss_grad(plan, sig2, v)
+
+    T = oracle.Tree(X, leaf)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, leaf, **kw)
+    op = lambda x: oracle.fkt_alg1(T, x, "matern52", theta, p, **kw) + sig2 * x
+    lref, gref = LR.loss_grad(sp, params.astype(np.float64), v, op)
+    gerr = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
+    print(f"loss gpu {loss:.10e} oracle {lref:.10e}; gradient rel err {gerr:.3e}")
+    # FP32 network: o (and so h) carries ~1e-6 relative rounding
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert gerr <= 2e-3
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in LR.SIZES])
+    for (name, _), a, b in zip(LR.SIZES, offs[:-1], offs[1:]):
+        e = np.linalg.norm(grad[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-30)
+        assert e <= 5e-3, (name, e)
+    plan.close()
+
+
+def test_training_lowers_loss_and_cg_iterations(F):
+    import torch
+    n, sig2 = 8000, 1e-2
+    X = _gp_points(n, 66)
+    plan = F.fkt_plan(X, "matern52", 128, 6, theta=0.35, lengthscale=0.05)
+    b = torch.as_tensor(W.gp_targets(X, 0.05, sig2, 512, 67), device="cuda")
+    its = {}
+    _, its["none"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="none")
+    _, its["block_jacobi"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="block_jacobi")
+    l0, l1 = F.fkt_learn_train(plan, sig2, steps=40, batch=8, lr=3e-3, seed=7)
+    _, its["learned"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="learned")
+    print(f"training loss {l0:.4f} -> {l1:.4f}; CG iterations {its}")
+    assert l1 < l0
+    assert its["learned"] < its["none"]
+    plan.close()
