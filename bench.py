@@ -87,23 +87,27 @@ def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmu
             "rel_err_vs_dense": rel_err, "stages_ms": stages, "plan": info}
 
 
-def gp_solve(F, torch, n, theta, order, rtol, maxit):
-    """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM,
-    without and with the block-Jacobi preconditioner; d = 4 mixture."""
+def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
+    """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM
+    on the d = 4 mixture: no preconditioner, block-Jacobi, and the learned
+    per-leaf spectral filter after train_steps Adam steps (batch 8)."""
     spec = W.WORKLOADS["gmm4_n200k_gp"]
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
     y = W.gp_targets(X, spec["lengthscale"], spec["sigma2"], spec["nfeat"], spec["rhs_seed"])
     t0 = time.perf_counter()
-    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, lengthscale=spec["lengthscale"])
+    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, lengthscale=lengthscale)
     plan_s = time.perf_counter() - t0
     b = torch.as_tensor(y, device="cuda")
-    out = {"workload": f"gmm{spec['d']}_n{n}_matern52_gp", "n": n, "d": spec["d"], "theta": theta, "p": order,
-           "sigma2": spec["sigma2"], "rtol": rtol, "plan_seconds": plan_s}
-    for name, pc in (("none", 0), ("block_jacobi", 1)):
+    sig2 = spec["sigma2"]
+    out = {"workload": f"gmm{spec['d']}_n{n}_matern52_l{lengthscale}_gp", "n": n, "d": spec["d"],
+           "lengthscale": lengthscale, "theta": theta, "p": order, "sigma2": sig2, "rtol": rtol, "maxit": maxit,
+           "plan_seconds": plan_s}
+
+    def solve(name, pc):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            x, it, rr = F.fkt_cg_solve(plan, spec["sigma2"], b, rtol=rtol, maxit=maxit, precond=pc)
+            x, it, rr = F.fkt_cg_solve(plan, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
             ok = True
         except F.FktError as e:
             if e.status != 5:
@@ -112,8 +116,22 @@ def gp_solve(F, torch, n, theta, order, rtol, maxit):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         out[name] = {"iterations": it, "relres": rr, "converged": ok, "seconds": sec}
-        print(f"bench: gp solve n={n} precond={name}: {it} iterations, {sec:.2f} s, relres {rr:.2e}",
+        print(f"bench: gp solve n={n} l={lengthscale} precond={name}: {it} iterations, {sec:.2f} s, relres {rr:.2e}",
               file=sys.stderr, flush=True)
+
+    solve("none", "none")
+    solve("block_jacobi", "block_jacobi")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F.fkt_learn_params(plan, sig2)  # leaf spectra (host eigendecompositions)
+    spectra_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    l0, l1 = F.fkt_learn_train(plan, sig2, steps=train_steps, batch=8, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    solve("learned", "learned")
+    out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
+                           "train_loss_first": l0, "train_loss_last": l1})
     plan.close()
     return out
 
@@ -137,7 +155,9 @@ def main():
     ap.add_argument("--serial", action="store_true",
                     help="run near and far fields one after the other on one stream (default: concurrently)")
     ap.add_argument("--gp-n", type=int, default=50_000,
-                    help="points of the GP solve (the d = 4 mixture workload at 200k takes minutes); 0 skips it")
+                    help="points of the GP solves (the d = 4 mixture workload at 200k takes minutes); 0 skips them")
+    ap.add_argument("--gp-maxit", type=int, default=3000)
+    ap.add_argument("--gp-train-steps", type=int, default=100)
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -177,7 +197,8 @@ def main():
 
     gp = None
     if a.gp_n > 0 and not a.no_variants:
-        gp = gp_solve(F, torch, a.gp_n, 0.35, 6, 1e-6, 6000)
+        # the workload's length scale 0.3, and 0.1 where per-leaf preconditioning has something to act on
+        gp = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
 
     cpu = None
     if a.cpu_seconds > 0:

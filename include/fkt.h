@@ -204,9 +204,9 @@ fkt_status fkt_plan_stage_times(fkt_plan_t p, double *ms, int64_t *calls, int re
  *     [log(lam_i / sigma2) / 8, log(lam_max / sigma2) / 8, m_l / leaf_size, (i + 1/2) / m_l]
  * (ascending eigenvalues, m_l points in the leaf). M is symmetric positive
  * definite for any weights; o = 0 (the initial last layer is zero) makes it
- * block-Jacobi. Training minimises L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2
- * for Gaussian v_b with A = the plan's MVM + sigma2 I, its gradient taking A
- * as symmetric. Needs leaves of at most 2048 points and sigma2 > 0; the first
+ * block-Jacobi. Training minimises L = (1/B) sum_b min_a |a A M v_b - v_b|^2 /
+ * |v_b|^2 (invariant to the scale of M, as PCG is) for Gaussian v_b with A =
+ * the plan's MVM + sigma2 I, its gradient taking A as symmetric. Needs leaves of at most 2048 points and sigma2 > 0; the first
  * call for a sigma2 builds the spectra (host, O(leaf^3) per leaf).
  *
  * Parameters (FP32, fkt_learn_nparams() of them) in the order W1 [4][256],

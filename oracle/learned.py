@@ -14,10 +14,14 @@ this project adds for CG on A = K~ + sigma2 I. Definitions:
 * network (per feature row f): h1 = tanh(f W1 + b1), h2 = tanh(h1 W2 + b2),
   o = h2 . w3 + b3;
 * filter   h_{l,i} = exp(o_{l,i}) / lam_{l,i},  M_l = V_l^T diag(h_l) V_l;
-* loss     L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2;
-* gradient through the chain rule with A taken as symmetric:
-  dL/dw_b = (2 / (B |v_b|^2)) A (A M v_b - v_b), dL/dh_{l,i} = sum_b
-  (V_l dL/dw_b)_i (V_l v_b)_i, dL/do = h dL/dh, then back through the MLP.
+* loss     L = (1/B) sum_b min_a |a A M v_b - v_b|^2 / |v_b|^2, the optimal
+  a_b = <u_b, v_b> / |u_b|^2 with u_b = A M v_b (PCG does not see the scale
+  of M, so neither does L; without the minimisation over a the loss is
+  lowered by shrinking M towards zero, which changes no CG iterate);
+* gradient through the chain rule with A taken as symmetric (a_b is
+  stationary, so it is held fixed): dL/dw_b = (2 a_b / (B |v_b|^2)) A
+  (a_b A M v_b - v_b), dL/dh_{l,i} = sum_b (V_l dL/dw_b)_i (V_l v_b)_i,
+  dL/do = h dL/dh, then back through the MLP.
 
 The parameter vector is ordered W1 [4][256], b1, W2 [256][256], b2, w3, b3.
 Pins (tests/test_oracle_learned.py): with o = 0 the filter is the exact
@@ -132,10 +136,12 @@ def loss_grad(spectra, theta, v, op):
     B = v.shape[1]
     hs, cache = filters(spectra, theta)
     w = apply_filter(spectra, hs, v)
-    r = op(w) - v
+    u = op(w)
     vv = np.sum(v * v, axis=0)
+    a = np.sum(u * v, axis=0) / np.sum(u * u, axis=0)
+    r = a[None, :] * u - v
     loss = float(np.mean(np.sum(r * r, axis=0) / vv))
-    g = op(r) * (2.0 / (B * vv))[None, :]
+    g = op(r) * (2.0 * a / (B * vv))[None, :]
     go = []
     for L, h in zip(spectra, hs):
         c = L["V"] @ v[L["idx"]]

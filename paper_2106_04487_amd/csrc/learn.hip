@@ -11,11 +11,13 @@
 // with o = 0 it is block-Jacobi exactly (the initial state: the last layer
 // starts at zero).
 //
-// Training minimises L = (1/B) sum_b |A M v_b - v_b|^2 / |v_b|^2 over
-// Gaussian v_b, with A the plan's own operator (FKT MVM + sigma2). Its
-// gradient takes A as symmetric (the kernel matrix is; the FKT operator is
-// within its approximation error):
-//   g_b = (2 / (B |v_b|^2)) A (A M v_b - v_b),
+// Training minimises L = (1/B) sum_b min_a |a A M v_b - v_b|^2 / |v_b|^2
+// over Gaussian v_b, with A the plan's own operator (FKT MVM + sigma2) and
+// the optimal a_b = <u_b, v_b> / |u_b|^2, u_b = A M v_b: like PCG, L does not
+// see the scale of M. Its gradient holds a_b fixed (it is stationary) and
+// takes A as symmetric (the kernel matrix is; the FKT operator is within its
+// approximation error):
+//   g_b = (2 a_b / (B |v_b|^2)) A (a_b u_b - v_b),
 //   dL/dh_{l,i} = sum_b (V_l g_{l,b})_i (V_l v_{l,b})_i,   dL/do = h dL/dh,
 // then back through the MLP with this file's kernels (MFMA GEMMs for the
 // 256 x 256 layer), and an Adam step.
@@ -301,10 +303,10 @@ __global__ __launch_bounds__(kT) void k_spec_apply(const int* __restrict__ begin
     }
 }
 
-// go[i] = h_i (2/B) sum_b c[i][b] p[i][b] / vv[b]  (FP32 out), 0 for padding
+// go[i] = h_i sum_b c[i][b] p[i][b] scale[b]  (FP32 out), 0 for padding
 __global__ __launch_bounds__(kT) void k_dout(int64_t n, int64_t Sp, int B, const double* __restrict__ h,
                                              const double* __restrict__ c, const double* __restrict__ p,
-                                             const double* __restrict__ vv, float* __restrict__ go)
+                                             const double* __restrict__ scale, float* __restrict__ go)
 {
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (i >= Sp) return;
@@ -313,8 +315,17 @@ __global__ __launch_bounds__(kT) void k_dout(int64_t n, int64_t Sp, int B, const
         return;
     }
     double s = 0.0;
-    for (int b = 0; b < B; ++b) s += c[i * B + b] * p[i * B + b] / vv[b];
-    go[i] = (float)(h[i] * 2.0 / B * s);
+    for (int b = 0; b < B; ++b) s += c[i * B + b] * p[i * B + b] * scale[b];
+    go[i] = (float)(h[i] * s);
+}
+
+// r[i][b] = a[b] u[i][b] - v[i][b]
+__global__ __launch_bounds__(kT) void k_scaled_resid(int64_t m, int B, const double* __restrict__ a,
+                                                     const double* __restrict__ u, const double* __restrict__ v,
+                                                     double* __restrict__ r)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < m) r[i] = a[i % B] * u[i] - v[i];
 }
 
 // ------------------------------------------------------ batch helpers
@@ -625,9 +636,14 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
         hipLaunchKernelGGL(k_spec_recon, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->V,
                            L->perm, L->h, c, B, B, b, w);
     }
-    fkt_status st = op(w, v, r);  // r = A M v - v
+    fkt_status st = op(w, nullptr, g);  // u = A M v (in g)
     if (st != FKT_OK) return st;
-    if (!coldots(v, v, nv) || !coldots(r, r, nr)) return FKT_EDEVICE;
+    std::vector<double> uv, uu, ab(2 * B);
+    if (!coldots(v, v, nv) || !coldots(g, v, uv) || !coldots(g, g, uu)) return FKT_EDEVICE;
+    for (int b = 0; b < B; ++b) ab[b] = uu[b] > 0.0 ? uv[b] / uu[b] : 0.0;
+    if (hipMemcpyAsync(vv, ab.data(), sizeof(double) * B, hipMemcpyHostToDevice, s) != hipSuccess) return FKT_EDEVICE;
+    hipLaunchKernelGGL(k_scaled_resid, dim3(blocks_of(m)), dim3(kT), 0, s, m, B, vv, g, v, r);  // r = a u - v
+    if (!coldots(r, r, nr)) return FKT_EDEVICE;  // also retires the use of vv
     double lsum = 0.0;
     for (int b = 0; b < B; ++b) lsum += nv[b] > 0.0 ? nr[b] / nv[b] : 0.0;
     *loss = lsum / B;
@@ -636,7 +652,9 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
     for (int b = 0; b < B; ++b)
         hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
                            L->perm, B, b, g, pp, B);
-    if (hipMemcpyAsync(vv, nv.data(), sizeof(double) * B, hipMemcpyHostToDevice, s) != hipSuccess) return FKT_EDEVICE;
+    for (int b = 0; b < B; ++b) ab[B + b] = nv[b] > 0.0 ? 2.0 * ab[b] / (B * nv[b]) : 0.0;
+    if (hipMemcpyAsync(vv, ab.data() + B, sizeof(double) * B, hipMemcpyHostToDevice, s) != hipSuccess)
+        return FKT_EDEVICE;
     hipLaunchKernelGGL(k_dout, dim3(blocks_of(L->Sp)), dim3(kT), 0, s, n, L->Sp, B, L->h, c, pp, vv, L->go);
     if (backward(L) != hipSuccess) return FKT_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return FKT_EDEVICE;
