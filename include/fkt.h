@@ -99,7 +99,7 @@ void fkt_default_options(fkt_options *opt);
  *   leaf_size maximum points per leaf, >= 1 (a node with more is split).
  *   order     truncation order p of eq. (finaltrunc): radial powers j <= p,
  *             harmonic degrees k <= p; expansion rank C(p+d, d).
- *             Built: 0 <= p <= 10 for d = 3, 0 <= p <= 8 for d = 4, 5.
+ *             Built: 0 <= p <= 8 for d = 3 and d = 5, 0 <= p <= 6 for d = 4.
  *   opt       NULL for defaults.
  *   out       receives the plan on FKT_OK, NULL otherwise.
  * Errors: FKT_EINVAL (bad n, d, leaf_size, order, theta, kernel parameters,

@@ -33,16 +33,22 @@ def _jobs():
           os.path.join(CSRC, "plan_host.cpp"), "-o", os.path.join(BUILD, "plan_host.o")]),
         ([HIPCC, *COMMON, "-c", os.path.join(CSRC, "fkt_api.cpp"), "-o", os.path.join(BUILD, "fkt_api.o")]),
         ([*dev, "-c", os.path.join(CSRC, "mvm.hip"), "-o", os.path.join(BUILD, "mvm.o")]),
-        ([*dev, "-c", os.path.join(CSRC, "stage_s2m.hip"), "-o", os.path.join(BUILD, "stage_s2m.o")]),
         ([*dev, "-c", os.path.join(CSRC, "cg.hip"), "-o", os.path.join(BUILD, "cg.o")]),
         (["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-c",
           os.path.join(CSRC, "learn_host.cpp"), "-o", os.path.join(BUILD, "learn_host.o")]),
         ([*dev, "-c", os.path.join(CSRC, "learn.hip"), "-o", os.path.join(BUILD, "learn.o")]),
     ]
+    # one source-to-multipole object per (dimension, precision)
+    for d in (3, 4, 5):
+        for prec in (0, 1):
+            jobs.append([*dev, f"-DFKT_S2M_D={d}", f"-DFKT_S2M_PREC={prec}", "-c", os.path.join(CSRC, "stage_s2m.hip"),
+                         "-o", os.path.join(BUILD, f"stage_s2m_d{d}_p{prec}.o")])
     # one multipole-to-target object per kernel kind (fkt_kernel_kind 0..6)
     for kind in range(7):
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "stage_m2t.hip"),
                      "-o", os.path.join(BUILD, f"stage_m2t_{kind}.o")])
+    # longest compiles first (the high-order d = 5 moment kernels)
+    jobs.sort(key=lambda j: 0 if "-DFKT_S2M_D=5" in j else 1)
     return jobs
 
 
@@ -50,7 +56,21 @@ def _objects():
     return [j[j.index("-o") + 1] for j in _jobs()]
 
 
-def build(jobs: int = 8, verbose: bool = False) -> str:
+def _stale(cmd) -> bool:
+    """An object is stale when it is older than its source or any header."""
+    out = cmd[cmd.index("-o") + 1]
+    if not os.path.exists(out):
+        return True
+    deps = [a for a in cmd if a.endswith((".cpp", ".hip"))]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    t = os.path.getmtime(out)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int = 8, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every object (or, with incremental, only the stale ones) and
+    link libfkt.so."""
     os.makedirs(BUILD, exist_ok=True)
 
     def run(cmd):
@@ -61,8 +81,9 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
             raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
         return r
 
+    todo = [j for j in _jobs() if not incremental or _stale(j)]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(run, _jobs()))
+        list(ex.map(run, todo))
     tmp = LIB + ".tmp"
     run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *_objects(), "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
@@ -73,6 +94,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", action="store_true")
+    ap.add_argument("--incremental", action="store_true", help="recompile only objects older than their inputs")
     a = ap.parse_args()
-    print(build(a.jobs, a.v))
+    print(build(a.jobs, a.v, a.incremental))
     sys.exit(0)

@@ -815,7 +815,7 @@ __global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restric
 template <int D> struct PMax;
 template <> struct PMax<3> { static constexpr int value = 8; };
 template <> struct PMax<4> { static constexpr int value = 6; };
-template <> struct PMax<5> { static constexpr int value = 6; };
+template <> struct PMax<5> { static constexpr int value = 8; };
 
 constexpr int kChunk = 128;  // s2m moment entries accumulated per lane and launch
 
@@ -823,6 +823,14 @@ constexpr int kChunk = 128;  // s2m moment entries accumulated per lane and laun
 
 // Launchers implemented in the per-stage translation units.
 bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
+#define FKT_DECLARE_S2M(D, PR) bool launch_s2m_d##D##_p##PR(const DevPlan& a, const DevWork& wk, hipStream_t s);
+FKT_DECLARE_S2M(3, 0)
+FKT_DECLARE_S2M(3, 1)
+FKT_DECLARE_S2M(4, 0)
+FKT_DECLARE_S2M(4, 1)
+FKT_DECLARE_S2M(5, 0)
+FKT_DECLARE_S2M(5, 1)
+#undef FKT_DECLARE_S2M
 bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
 #define FKT_DECLARE_M2T(K) bool launch_m2t_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
 FKT_DECLARE_M2T(0)

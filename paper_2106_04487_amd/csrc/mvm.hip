@@ -131,6 +131,19 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
 
 }  // namespace
 
+bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+{
+    switch (a.d * 2 + (prec == 1 ? 1 : 0)) {
+    case 6: return launch_s2m_d3_p0(a, wk, s);
+    case 7: return launch_s2m_d3_p1(a, wk, s);
+    case 8: return launch_s2m_d4_p0(a, wk, s);
+    case 9: return launch_s2m_d4_p1(a, wk, s);
+    case 10: return launch_s2m_d5_p0(a, wk, s);
+    case 11: return launch_s2m_d5_p1(a, wk, s);
+    default: return false;
+    }
+}
+
 bool far_supported(int d, int p)
 {
     switch (d) {

@@ -1,6 +1,12 @@
 // s2m launches (source-to-multipole moments and partial-sum reduction).
 #include "fkt_kernels.h"
 
+#if !defined(FKT_S2M_D) || !defined(FKT_S2M_PREC)
+#error "compile with -DFKT_S2M_D=<3|4|5> -DFKT_S2M_PREC=<0|1>"
+#endif
+#define FKT_CAT2(a, b) a##b
+#define FKT_CAT(a, b) FKT_CAT2(a, b)
+
 namespace fkt {
 namespace {
 
@@ -40,22 +46,19 @@ bool s2m_d(const DevPlan& a, const DevWork& wk, hipStream_t s)
     }
 }
 
-template <typename T>
-bool s2m_t(const DevPlan& a, const DevWork& wk, hipStream_t s)
-{
-    switch (a.d) {
-    case 3: return s2m_d<3, T>(a, wk, s);
-    case 4: return s2m_d<4, T>(a, wk, s);
-    case 5: return s2m_d<5, T>(a, wk, s);
-    default: return false;
-    }
-}
-
 }  // namespace
 
-bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+// One translation unit per (dimension, precision): FKT_S2M_D and FKT_S2M_PREC
+// (0 FP64, 1 FP32) are set when compiling, so the large high-order
+// instantiations build in parallel.
+bool FKT_CAT(FKT_CAT(launch_s2m_d, FKT_S2M_D), FKT_CAT(_p, FKT_S2M_PREC))(const DevPlan& a, const DevWork& wk,
+                                                                         hipStream_t s)
 {
-    return prec == 1 ? s2m_t<float>(a, wk, s) : s2m_t<double>(a, wk, s);
+#if FKT_S2M_PREC == 1
+    return s2m_d<FKT_S2M_D, float>(a, wk, s);
+#else
+    return s2m_d<FKT_S2M_D, double>(a, wk, s);
+#endif
 }
 
 }  // namespace fkt

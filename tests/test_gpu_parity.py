@@ -78,6 +78,9 @@ SMALL = [
     ("d5_gauss", lambda: W.gaussian_mixture(5000, 5, 10, 0.1, 39), 1, "gaussian", dict(lengthscale=0.2), 128, 4, 0.6),
     ("d4_p6", lambda: W.uniform_cube(3000, 4, 40), 1, "gaussian", dict(lengthscale=0.4), 64, 6, 0.6),
     ("d5_p6_laplace", lambda: W.uniform_cube(2500, 5, 41), 1, "laplace", dict(), 64, 6, 0.6),
+    ("d5_p8_gauss", lambda: W.gaussian_mixture(3000, 5, 10, 0.1, 47), 1, "gaussian", dict(lengthscale=0.2), 128, 8, 0.5),
+    ("d5_p7_matern32", lambda: W.gaussian_mixture(2500, 5, 10, 0.1, 48), 1, "matern32", dict(lengthscale=0.3), 100, 7,
+     0.6),
     ("nrhs3", lambda: W.uniform_cube(3000, 3, 42), 3, "matern32", dict(lengthscale=0.1), 64, 4, 0.5),
     ("dups", lambda: W.clustered_duplicates(3000, 3, 50, 43), 1, "gaussian", dict(lengthscale=0.2), 32, 4, 0.5),
     ("ragged_n65", lambda: W.uniform_cube(65, 3, 44), 1, "gaussian", dict(lengthscale=0.2), 8, 4, 0.6),
