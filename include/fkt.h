@@ -81,10 +81,16 @@ typedef struct {
                            with the far field, joined back into `stream`
                            before the scatter; 0: every stage in order on
                            `stream`                                            */
+    int mrhs;           /* FP32 plans: fkt_mvm with nrhs a multiple of 32 runs
+                           the near field on the matrix cores for 32 columns
+                           at once: 1 FP32 MFMA, 2 bf16 MFMA (kernel values
+                           and weights rounded to bf16, FP32 accumulation);
+                           the far field stays FP32, column by column.
+                           0 (default): every column on its own.            */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
- * overlap 1. */
+ * overlap 1, mrhs 0. */
 void fkt_default_options(fkt_options *opt);
 
 /*

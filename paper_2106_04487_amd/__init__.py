@@ -55,7 +55,7 @@ class _Kernel(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("overlap", ctypes.c_int)]
+                ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int)]
 
 
 _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
@@ -170,10 +170,13 @@ class Plan:
 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
              variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
-             device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True) -> Plan:
+             device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
+             mrhs: str | None = None) -> Plan:
     """Build a plan. points: (n, d) array-like (host or device; copied to host
     FP64 for the tree build). device=None builds a host-only plan. overlap
-    runs the near field on a second stream beside the far field."""
+    runs the near field on a second stream beside the far field. mrhs ("f32"
+    or "bf16", FP32 plans) runs the near field of groups of 32 right-hand
+    sides on the matrix cores."""
     if hasattr(points, "detach"):
         points = points.detach().to("cpu").double().numpy()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -195,6 +198,7 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     opt.stream = sh
     opt.profile = int(bool(profile))
     opt.overlap = int(bool(overlap))
+    opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
     h = _P()
     _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
     return Plan(h, n, d, prec, device, sh)

@@ -37,6 +37,7 @@ def _jobs():
         (["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-c",
           os.path.join(CSRC, "learn_host.cpp"), "-o", os.path.join(BUILD, "learn_host.o")]),
         ([*dev, "-c", os.path.join(CSRC, "learn.hip"), "-o", os.path.join(BUILD, "learn.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "mrhs.hip"), "-o", os.path.join(BUILD, "mrhs.o")]),
     ]
     # one source-to-multipole object per (dimension, precision)
     for d in (3, 4, 5):

@@ -12,6 +12,7 @@
 #include "fkt_device.h"
 #include "fkt_host.h"
 #include "fkt_learn.h"
+#include "fkt_mrhs.h"
 
 namespace {
 
@@ -66,6 +67,7 @@ struct fkt_plan_s {
     std::vector<void*> allocs;
     fkt::DevPlan dp{};
     fkt::DevWork wk{};
+    fkt::DevMrhs mr{};   // many-RHS layout (opt.mrhs != 0)
     struct Ev7 { hipEvent_t e[7]; };
     std::vector<Ev7> prof;   // events of profiled column passes not yet summed
     double prof_ms[5] = {0, 0, 0, 0, 0};
@@ -137,6 +139,7 @@ void fkt_default_options(fkt_options* opt)
     opt->stream = nullptr;
     opt->profile = 0;
     opt->overlap = 1;
+    opt->mrhs = 0;
 }
 
 const char* fkt_last_error(void) { return g_err.c_str(); }
@@ -220,6 +223,49 @@ static fkt_status upload_plan(fkt_plan_t P)
         return hip_fail(e, "moment buffer");
     if ((e = P->alloc(es * L.npartials * P->tab.rank, &P->wk.part)) != hipSuccess)
         return hip_fail(e, "partial-moment buffer");
+    // many-RHS near field: leaves padded to multiples of 32 points, SoA
+    // coordinates, target-major near lists with padded ranges
+    if (P->opt.mrhs != 0) {
+        const int d = P->d;
+        std::vector<int32_t> pbeg_of(P->n + 1, -1);
+        std::vector<int32_t> src;
+        for (int64_t b = 0; b < T.nnodes(); ++b) {
+            if (!T.leaf(b)) continue;
+            const int64_t b0 = T.begin[b], m = T.end[b] - b0;
+            pbeg_of[b0] = (int32_t)src.size();
+            for (int64_t i = 0; i < m; ++i) src.push_back((int32_t)(b0 + i));
+            while (src.size() % 32) src.push_back(-1 - (int32_t)b0);  // pad: -1 - leaf start
+        }
+        const int64_t npad = (int64_t)src.size();
+        if (npad > 0x7fffffff / 32) return fail(FKT_EUNSUPPORTED, "too many points for the many-RHS layout");
+        std::vector<float> pts((size_t)d * npad);
+        for (int64_t p = 0; p < npad; ++p) {
+            const int64_t t = src[p] >= 0 ? src[p] : -1 - (int64_t)src[p];
+            for (int k = 0; k < d; ++k) pts[(size_t)k * npad + p] = (float)T.pts[t * d + k];
+            if (src[p] < 0) src[p] = -1;
+        }
+        std::vector<int32_t> pb(L.near_beg.size()), pc(L.near_beg.size());
+        for (size_t e2 = 0; e2 < L.near_beg.size(); ++e2) {
+            pb[e2] = pbeg_of[L.near_beg[e2]];
+            pc[e2] = (L.near_end[e2] - L.near_beg[e2] + 31) / 32 * 32;
+            if (pb[e2] < 0) return fail(FKT_EDEVICE, "many-RHS layout: near entry is not a leaf");
+        }
+        P->mr.npad = (int)npad;
+        P->mr.bf16 = P->opt.mrhs == 2;
+#define FKT_UP2(vec, dst) \
+    if ((e = P->upload(vec, &dst)) != hipSuccess) return hip_fail(e, "many-RHS upload")
+        FKT_UP2(pts, P->mr.pts);
+        FKT_UP2(src, P->mr.src);
+        FKT_UP2(L.near_off, P->mr.near_off);
+        FKT_UP2(pb, P->mr.near_pbeg);
+        FKT_UP2(pc, P->mr.near_pcnt);
+        FKT_UP2(L.near_mask, P->mr.near_mask);
+#undef FKT_UP2
+        if ((e = P->alloc((P->mr.bf16 ? 2 : 4) * (size_t)fkt::kMrCols * npad, &P->mr.xt)) != hipSuccess)
+            return hip_fail(e, "many-RHS weights");
+        if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * P->n, &P->mr.zf)) != hipSuccess)
+            return hip_fail(e, "many-RHS far-field buffer");
+    }
     // second stream (default priority) and fork/join events for running the
     // near field beside the far field
     if ((e = hipStreamCreateWithFlags(&P->wk.side, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
@@ -247,6 +293,8 @@ fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int le
         return fail(FKT_EUNSUPPORTED, "order " + std::to_string(order) + " not built for d = " + std::to_string(d));
     if (!(opt.theta > 0.0 && opt.theta < 1.0)) return fail(FKT_EINVAL, "theta must be in (0, 1)");
     if (opt.prec != FKT_F64 && opt.prec != FKT_F32) return fail(FKT_EINVAL, "unknown precision");
+    if (opt.mrhs < 0 || opt.mrhs > 2) return fail(FKT_EINVAL, "mrhs must be 0, 1 or 2");
+    if (opt.mrhs != 0 && opt.prec != FKT_F32) return fail(FKT_EUNSUPPORTED, "mrhs needs an FP32 plan");
     if (opt.max_depth < 1 || opt.max_depth > 60) return fail(FKT_EINVAL, "max_depth must be in [1, 60]");
     if (opt.device < -1) return fail(FKT_EINVAL, "device must be >= -1");
     fkt_status s = check_kernel(k);
@@ -311,6 +359,10 @@ fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
     if (xb < yb + bytes && yb < xb + bytes) return fail(FKT_EINVAL, "x and y overlap");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    if (P->opt.mrhs != 0 && nrhs % fkt::kMrCols == 0) {
+        const hipError_t e = fkt::launch_mvm_mrhs(P->dp, P->wk, P->mr, (const float*)x, (float*)y, nrhs, P->stream);
+        return e == hipSuccess ? FKT_OK : hip_fail(e, "fkt_mvm many-RHS launch");
+    }
     for (int c = 0; c < nrhs; ++c) {
         hipEvent_t* ev = nullptr;
         if (P->opt.profile) {

@@ -1,0 +1,40 @@
+// Many-right-hand-side MVM (groups of 32 columns, FP32 plans): padded leaf
+// layout for the matrix-core near field, and the launchers (mrhs.hip, mvm.hip).
+#ifndef FKT_MRHS_H
+#define FKT_MRHS_H
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fkt_device.h"
+
+namespace fkt {
+
+constexpr int kMrCols = 32;  // columns per group
+
+struct DevMrhs {
+    int npad = 0;                     // leaves padded to multiples of 32 points
+    const float* pts = nullptr;       // [d][npad] SoA coordinates (pad: leaf's first point)
+    const int* src = nullptr;         // [npad] tree position, -1 on padding
+    const int* near_off = nullptr;    // [nblocks + 1] target-major near lists of the 64-target blocks
+    const int* near_pbeg = nullptr;   //   padded first point of the leaf (multiple of 32)
+    const int* near_pcnt = nullptr;   //   padded point count (multiple of 32)
+    const uint64_t* near_mask = nullptr;  // targets of the block that have the leaf in their near set
+    void* xt = nullptr;               // [32][npad] weights of the group (bf16 or FP32)
+    void* zf = nullptr;               // [32][n] far field of the group, FP32, tree order
+    bool bf16 = false;
+};
+
+// far field of one column (gather clearing wk.zacc, s2m, m2t into wk.zacc)
+hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* x, int nrhs, int col, int prec,
+                             hipStream_t s);
+// FP32 near-kernel constants (log2(e) folded where an exponential follows)
+void near_consts_f32(const DevPlan& a, float& c0, float& c1);
+// y = K~ x for nrhs (a multiple of 32) FP32 columns
+hipError_t launch_mvm_mrhs(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, const float* x, float* y, int nrhs,
+                           hipStream_t s);
+
+}  // namespace fkt
+
+#endif

@@ -1,0 +1,214 @@
+// Many right-hand sides (groups of 32 columns, FP32 plans): the near field
+// runs on the matrix cores, the far field column by column.
+//
+// Near field (Algorithm 1, near_mat, for 32 columns at once): one wave owns
+// a 64-target block and walks the union of its targets' near leaves. For
+// every 32 points of a leaf each lane evaluates 32 kernel values (4 row
+// tiles of 16 targets x 8 points; rows whose target does not have the leaf
+// in its own near set get 0), and the 64 x 32 block of K times the 32 x 32
+// block of weights is accumulated by MFMA: v_mfma_f32_16x16x32_bf16 (kernel
+// values and weights rounded to bf16, FP32 accumulation) or
+// v_mfma_f32_16x16x4f32 (FP32 throughout). Lane l of a 16 x 16 tile holds
+// row l % 16 and points 8 (l / 16) .. + 7 of the 32, for both variants (the
+// points are a reduction index, so the order within a step is free). The
+// block's 64 x 32 result is final: the epilogue adds the far field and
+// writes y in the caller's order, once per (target, column); no atomics.
+//
+// Leaves are laid out padded to multiples of 32 points (pad weight 0,
+// coordinates of the leaf's first point), so every step loads aligned runs.
+#include <hip/hip_runtime.h>
+
+#include "fkt_kernels.h"
+#include "fkt_mrhs.h"
+
+namespace fkt {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// XT[c][p] = x[perm[src[p]]][col0 + c] (0 on padding), c < 32
+template <typename TC>
+__global__ __launch_bounds__(256) void k_mr_gather(int npad, const int* __restrict__ src,
+                                                   const int64_t* __restrict__ perm, const float* __restrict__ x,
+                                                   int nrhs, int col0, TC* __restrict__ XT)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npad) return;
+    const int s = src[p];
+    const float* xr = s >= 0 ? x + perm[s] * nrhs + col0 : nullptr;
+#pragma unroll 8
+    for (int c = 0; c < kMrCols; ++c) XT[(size_t)c * npad + p] = (TC)(xr ? xr[c] : 0.f);
+}
+
+template <int D, int KIND, typename TC>
+__global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevMrhs mr, const TC* __restrict__ XT,
+                                                     const float* __restrict__ zf, float* __restrict__ y, int nrhs,
+                                                     int col0, float c0, float c1, float scale)
+{
+    using NK = NearKernel<KIND, float>;
+    constexpr bool kBf16 = std::is_same<TC, __bf16>::value;
+    const int blk = blockIdx.x, lane = threadIdx.x;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
+    float tx[4][D];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const int row = rt * 16 + r16;
+        const int t = tb + (row < cnt ? row : 0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) tx[rt][k] = a.pts32[(size_t)t * D + k];
+    }
+    f4 acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+
+    const int e0 = mr.near_off[blk], e1 = mr.near_off[blk + 1];
+    for (int e = e0; e < e1; ++e) {
+        const uint64_t mask = mr.near_mask[e];
+        float flag[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) flag[rt] = (float)((mask >> (rt * 16 + r16)) & 1ull);
+        const int pb = mr.near_pbeg[e], pe = pb + mr.near_pcnt[e];
+        for (int s0 = pb; s0 < pe; s0 += 32) {
+            const int sp = s0 + 8 * g;  // this lane's 8 points
+            float sx[D][8];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const f4 u0 = *(const f4*)(mr.pts + (size_t)k * mr.npad + sp);
+                const f4 u1 = *(const f4*)(mr.pts + (size_t)k * mr.npad + sp + 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sx[k][q] = u0[q];
+                    sx[k][q + 4] = u1[q];
+                }
+            }
+            if constexpr (kBf16) {
+                bf8 b[2];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) b[ct] = *(const bf8*)(XT + (size_t)(ct * 16 + r16) * mr.npad + sp);
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    bf8 av;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        float d2 = 0.f;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float w = tx[rt][k] - sx[k][q];
+                            d2 = fmaf(w, w, d2);
+                        }
+                        av[q] = (__bf16)(flag[rt] * NK::eval(d2, c0, c1, nullptr));
+                    }
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[ct], acc[rt][ct], 0, 0, 0);
+                }
+            } else {
+                float b[2][8];
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct) {
+                    const float* xp = (const float*)XT + (size_t)(ct * 16 + r16) * mr.npad + sp;
+                    const f4 u0 = *(const f4*)xp, u1 = *(const f4*)(xp + 4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        b[ct][q] = u0[q];
+                        b[ct][q + 4] = u1[q];
+                    }
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        float d2 = 0.f;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float w = tx[rt][k] - sx[k][q];
+                            d2 = fmaf(w, w, d2);
+                        }
+                        const float kv = flag[rt] * NK::eval(d2, c0, c1, nullptr);
+#pragma unroll
+                        for (int ct = 0; ct < 2; ++ct)
+                            acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv, b[ct][q], acc[rt][ct], 0, 0, 0);
+                    }
+            }
+        }
+    }
+    // C layout of a 16 x 16 tile: lane l, entry r -> row 4 (l / 16) + r, column l % 16
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + 4 * g + r, col = ct * 16 + r16;
+                if (row < cnt) {
+                    const int t = tb + row;
+                    y[a.perm[t] * nrhs + col0 + col] = scale * acc[rt][ct][r] + zf[(size_t)col * a.n + t];
+                }
+            }
+}
+
+template <int D, typename TC>
+bool launch_near_mrhs_d(const DevPlan& a, const DevMrhs& mr, const TC* XT, const float* zf, float* y, int nrhs,
+                        int col0, hipStream_t s)
+{
+    float c0, c1;
+    near_consts_f32(a, c0, c1);
+    const float scale = (float)a.var;
+    switch (a.kind) {
+#define FKT_MR_CASE(K) \
+    case K: hipLaunchKernelGGL((k_near_mrhs<D, K, TC>), dim3(a.nblocks), dim3(kWave), 0, s, a, mr, XT, zf, y, nrhs, \
+                               col0, c0, c1, scale); return true;
+        FKT_MR_CASE(FKT_GAUSSIAN)
+        FKT_MR_CASE(FKT_EXPONENTIAL)
+        FKT_MR_CASE(FKT_MATERN32)
+        FKT_MR_CASE(FKT_MATERN52)
+        FKT_MR_CASE(FKT_RATQUAD)
+        FKT_MR_CASE(FKT_CAUCHY)
+        FKT_MR_CASE(FKT_LAPLACE)
+#undef FKT_MR_CASE
+    default: return false;
+    }
+}
+
+template <typename TC>
+hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, const float* x, float* y, int nrhs,
+                      hipStream_t s)
+{
+    TC* XT = (TC*)mr.xt;
+    float* zf = (float*)mr.zf;
+    for (int col0 = 0; col0 < nrhs; col0 += kMrCols) {
+        // far field of each column into zf[c] (the gather clears it)
+        for (int c = 0; c < kMrCols; ++c) {
+            DevWork w = wk;
+            w.zacc = zf + (size_t)c * a.n;
+            hipError_t e = launch_far_column(a, w, x, nrhs, col0 + c, 1, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_mr_gather<TC>), dim3((mr.npad + 255) / 256), dim3(256), 0, s, mr.npad, mr.src, a.perm, x,
+                           nrhs, col0, XT);
+        bool ok = false;
+        switch (a.d) {
+        case 3: ok = launch_near_mrhs_d<3, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
+        case 4: ok = launch_near_mrhs_d<4, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
+        case 5: ok = launch_near_mrhs_d<5, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
+        default: break;
+        }
+        if (!ok) return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mvm_mrhs(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, const float* x, float* y, int nrhs,
+                           hipStream_t s)
+{
+    if (nrhs % kMrCols != 0) return hipErrorInvalidValue;
+    return mr.bf16 ? mvm_mrhs_t<__bf16>(a, wk, mr, x, y, nrhs, s) : mvm_mrhs_t<float>(a, wk, mr, x, y, nrhs, s);
+}
+
+}  // namespace fkt
