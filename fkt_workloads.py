@@ -76,6 +76,23 @@ def gp_targets(X: np.ndarray, lengthscale: float, sigma2: float, nfeat: int, see
     return f + np.sqrt(sigma2) * rng.standard_normal(size=n)
 
 
+def instance_sizes(ninst: int, nmin: int, nmax: int, seed: int) -> np.ndarray:
+    """ninst sizes, log-uniform in [nmin, nmax] (rounded to integers)."""
+    rng = np.random.default_rng(seed)
+    return np.rint(np.exp(rng.uniform(np.log(nmin), np.log(nmax), size=ninst))).astype(np.int64)
+
+
+def batched_instances(sizes, d: int, seed: int):
+    """Independent point sets uniform in [0, 1]^d, one per size (instance i
+    drawn with seed + i); returns (concatenated points, int64 offsets)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    X = np.concatenate([uniform_cube(int(m), d, seed + i) for i, m in enumerate(sizes)], axis=0) if len(sizes) else \
+        np.zeros((0, d))
+    return X, off
+
+
 # Named workloads: (points recipe, rhs recipe). Sizes follow the problem
 # statements; seeds are fixed so every consumer sees identical inputs.
 WORKLOADS = {
@@ -89,6 +106,14 @@ WORKLOADS = {
                               kernel="laplace", lengthscale=1.0, leaf=256, order=6),
     # Gaussian-process solve: 200k points from an 8-component mixture in d=4
     # (std 0.15), Matern-5/2 length scale 0.3, noise variance 1e-2
+    # many independent instances: 256 sets in d = 3, sizes log-uniform in
+    # [1e3, 1e5], rational quadratic (alpha 1, length scale 0.2), 4 RHS, FP32
+    "batch256_rq": dict(ninst=256, nmin=1000, nmax=100_000, d=3, size_seed=1004, pts_seed=10_000, rhs_seed=2004,
+                        nrhs=4, kernel="ratquad", lengthscale=0.2, alpha=1.0, order=6),
+    # mixed precision, many RHS: 500k points, 10-component mixture in d = 5
+    # (std 0.1), Gaussian length scale 0.2, 32 RHS, p = 8
+    "gmm5_n500k_gauss32": dict(n=500_000, d=5, ncomp=10, std=0.1, pts_seed=1003, rhs_seed=2003, nrhs=32,
+                               kernel="gaussian", lengthscale=0.2, order=8),
     "gmm4_n200k_gp": dict(n=200_000, d=4, ncomp=8, std=0.15, pts_seed=1005, rhs_seed=2005,
                           kernel="matern52", lengthscale=0.3, sigma2=1e-2, nfeat=2048, leaf=256),
 }

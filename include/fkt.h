@@ -200,6 +200,45 @@ fkt_status fkt_plan_target_counts(fkt_plan_t p, int64_t *far_nodes, int64_t *far
 fkt_status fkt_plan_stage_times(fkt_plan_t p, double *ms, int64_t *calls, int reset);
 
 /*
+ * fkt_plan_batch -- one plan over ninst independent point sets (a forest):
+ * instance i is rows offsets[i] .. offsets[i+1]-1 of points (host, FP64,
+ * offsets host int64 [ninst + 1], offsets[0] = 0, non-decreasing; empty
+ * instances allowed). Each instance gets its own tree (Sec. 3.1) and its
+ * own near/far sets; nothing interacts across instances, so fkt_mvm on the
+ * concatenated x computes every instance's K~_i x_i in the same launches
+ * (one launch per stage over all instances' work). Arguments, options and
+ * errors otherwise as fkt_plan.
+ */
+fkt_status fkt_plan_batch(const double *points, const int64_t *offsets, int ninst, int d, fkt_kernel k, int leaf_size,
+                          int order, const fkt_options *opt, fkt_plan_t *out);
+
+/*
+ * A whole fkt_mvm(p, x, y, nrhs) captured once into a HIP graph (stages in
+ * order on one stream; x and y are baked in) and replayed with
+ * fkt_graph_launch on the plan's stream. The plan must outlive the graph;
+ * replays of graphs of one plan must not overlap (they share its work
+ * buffers). Errors: FKT_EINVAL, FKT_EDEVICE, FKT_ENOMEM.
+ */
+typedef struct fkt_graph_s *fkt_graph_t;
+fkt_status fkt_graph_create(fkt_plan_t p, const void *x, void *y, int nrhs, fkt_graph_t *out);
+fkt_status fkt_graph_launch(fkt_graph_t g);
+void fkt_graph_destroy(fkt_graph_t g);
+
+/*
+ * Leaf-size autotuner: builds a plan (fkt_plan_batch when offsets is not
+ * NULL, else fkt_plan over n points) for each of the ncand candidate leaf
+ * sizes, times reps MVMs of nrhs zero columns after one untimed pass (HIP
+ * events on the plan's stream) and returns the fastest in *best; ms (host,
+ * ncand doubles, may be NULL) receives each candidate's time per MVM.
+ * opt->device must be >= 0. Time alone decides: theta and p fix the
+ * expansion, and a larger leaf only moves interactions of nodes below the
+ * leaf level from the far to the exact near field.
+ */
+fkt_status fkt_autotune_leaf(const double *points, const int64_t *offsets, int ninst, int64_t n, int d, fkt_kernel k,
+                             int order, const fkt_options *opt, const int *candidates, int ncand, int nrhs, int reps,
+                             int *best, double *ms);
+
+/*
  * Learned per-leaf preconditioner (not part of the paper's method; used by
  * fkt_cg_solve with precond = 2). For each leaf l, the near-field diagonal
  * block A_l = K(X_l, X_l) + sigma2 I = V_l^T diag(lam_l) V_l is

@@ -38,7 +38,8 @@ STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "F
 
 EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_destroy", "fkt_last_error",
             "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times",
-            "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train"]
+            "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
+            "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
 
 
 class FktError(RuntimeError):
@@ -86,6 +87,18 @@ _lib.fkt_plan_target_counts.restype = ctypes.c_int
 _lib.fkt_plan_target_counts.argtypes = [_P, _P, _P, _P, _P]
 _lib.fkt_plan_stage_times.restype = ctypes.c_int
 _lib.fkt_plan_stage_times.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+_lib.fkt_plan_batch.restype = ctypes.c_int
+_lib.fkt_plan_batch.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, _Kernel, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(_Options), ctypes.POINTER(_P)]
+_lib.fkt_graph_create.restype = ctypes.c_int
+_lib.fkt_graph_create.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.POINTER(_P)]
+_lib.fkt_graph_launch.restype = ctypes.c_int
+_lib.fkt_graph_launch.argtypes = [_P]
+_lib.fkt_graph_destroy.argtypes = [_P]
+_lib.fkt_autotune_leaf.restype = ctypes.c_int
+_lib.fkt_autotune_leaf.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _Kernel, ctypes.c_int,
+                                   ctypes.POINTER(_Options), _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int), _P]
 _lib.fkt_learn_nparams.restype = ctypes.c_int64
 _lib.fkt_learn_nparams.argtypes = []
 _lib.fkt_learn_params.restype = ctypes.c_int
@@ -166,6 +179,104 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs):
+    opt = _Options()
+    _lib.fkt_default_options(ctypes.byref(opt))
+    opt.theta = float(theta)
+    opt.prec = PRECISIONS[prec]
+    opt.max_depth = int(max_depth)
+    opt.device = -1 if device is None else int(device)
+    opt.stream = None if device is None else _stream_handle(stream)
+    opt.profile = int(bool(profile))
+    opt.overlap = int(bool(overlap))
+    opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
+    return opt
+
+
+def _kernel(kernel, lengthscale, alpha, variance):
+    if kernel not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}; one of {sorted(KERNELS)}")
+    return _Kernel(KERNELS[kernel], float(lengthscale), float(alpha), float(variance))
+
+
+def _batch_points(points):
+    """(concatenated FP64 rows, int64 offsets) from a list of (n_i, d) arrays
+    or from an (X, offsets) pair."""
+    if isinstance(points, tuple) and len(points) == 2 and np.ndim(points[1]) == 1:
+        X = np.ascontiguousarray(points[0], dtype=np.float64)
+        off = np.ascontiguousarray(points[1], dtype=np.int64)
+    else:
+        arrs = [np.asarray(p, dtype=np.float64) for p in points]
+        off = np.zeros(len(arrs) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([a.shape[0] for a in arrs])
+        X = np.ascontiguousarray(np.concatenate(arrs, axis=0))
+    return X, off
+
+
+def fkt_plan_batch(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
+                   variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
+                   device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
+                   mrhs: str | None = None) -> Plan:
+    """One plan over independent point sets: points is a list of (n_i, d)
+    arrays or (X, offsets). fkt_mvm then takes the concatenated rows."""
+    X, off = _batch_points(points)
+    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs)
+    h = _P()
+    _check(_lib.fkt_plan_batch(X.ctypes.data, off.ctypes.data, len(off) - 1, X.shape[1],
+                               _kernel(kernel, lengthscale, alpha, variance), int(leaf_size), int(order),
+                               ctypes.byref(opt), ctypes.byref(h)))
+    plan = Plan(h, X.shape[0], X.shape[1], prec, device, opt.stream)
+    plan.offsets = off
+    return plan
+
+
+class Graph:
+    """fkt_mvm(plan, x, y) captured into a HIP graph; launch() replays it on
+    the plan's stream. x and y (device tensors) must stay alive."""
+
+    def __init__(self, plan: Plan, x, y):
+        self.plan, self.x, self.y = plan, x, y
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        self._h = _P()
+        _check(_lib.fkt_graph_create(plan.handle, x.data_ptr(), y.data_ptr(), nrhs, ctypes.byref(self._h)))
+
+    def launch(self):
+        _check(_lib.fkt_graph_launch(self._h))
+
+    def close(self):
+        if self._h:
+            _lib.fkt_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fkt_autotune_leaf(points, kernel: str, order: int, candidates, *, nrhs: int = 1, reps: int = 3,
+                      lengthscale: float = 1.0, alpha: float = 1.0, variance: float = 1.0, theta: float = 0.5,
+                      prec: str = "f64", batch: bool = False, device: int = 0, mrhs: str | None = None):
+    """(best leaf size, {candidate: ms per MVM}) from the library's autotuner;
+    points as fkt_plan, or as fkt_plan_batch with batch=True."""
+    if batch:
+        X, off = _batch_points(points)
+        offp, ninst = off.ctypes.data, len(off) - 1
+    else:
+        X = np.ascontiguousarray(points, dtype=np.float64)
+        off, offp, ninst = None, None, 1
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    ms = np.zeros(len(cand))
+    best = ctypes.c_int(-1)
+    opt = _options(theta, prec, 48, device, None, False, True, mrhs)
+    _check(_lib.fkt_autotune_leaf(X.ctypes.data, offp, ninst, X.shape[0], X.shape[1],
+                                  _kernel(kernel, lengthscale, alpha, variance), int(order), ctypes.byref(opt),
+                                  cand.ctypes.data, len(cand), int(nrhs), int(reps), ctypes.byref(best),
+                                  ms.ctypes.data))
+    return best.value, dict(zip(cand.tolist(), ms.tolist()))
 
 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,

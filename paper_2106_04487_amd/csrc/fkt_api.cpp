@@ -274,8 +274,8 @@ static fkt_status upload_plan(fkt_plan_t P)
     return FKT_OK;
 }
 
-fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int leaf_size, int order,
-                    const fkt_options* opt_in, fkt_plan_t* out)
+static fkt_status make_plan(const double* points, int64_t n, int d, const int64_t* offsets, int ninst, fkt_kernel k,
+                            int leaf_size, int order, const fkt_options* opt_in, fkt_plan_t* out)
 {
     if (!out) return fail(FKT_EINVAL, "out is NULL");
     *out = nullptr;
@@ -312,7 +312,10 @@ fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int le
         P->leaf = leaf_size;
         P->kern = k;
         P->opt = opt;
-        fkt::build_tree(points, n, d, leaf_size, opt.max_depth, P->T);
+        if (offsets)
+            fkt::build_forest(points, offsets, ninst, d, leaf_size, opt.max_depth, P->T);
+        else
+            fkt::build_tree(points, n, d, leaf_size, opt.max_depth, P->T);
         fkt::build_lists(P->T, opt.theta,
                          fkt::m2t_max_job_nodes(d, order, opt.prec == FKT_F32 ? (int)sizeof(float) : (int)sizeof(double)),
                          P->L, P->st);
@@ -345,6 +348,25 @@ fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int le
     st.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P;
     return FKT_OK;
+}
+
+fkt_status fkt_plan(const double* points, int64_t n, int d, fkt_kernel k, int leaf_size, int order,
+                    const fkt_options* opt_in, fkt_plan_t* out)
+{
+    return make_plan(points, n, d, nullptr, 1, k, leaf_size, order, opt_in, out);
+}
+
+fkt_status fkt_plan_batch(const double* points, const int64_t* offsets, int ninst, int d, fkt_kernel k, int leaf_size,
+                          int order, const fkt_options* opt, fkt_plan_t* out)
+{
+    if (!out) return fail(FKT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!offsets) return fail(FKT_EINVAL, "offsets is NULL");
+    if (ninst < 1) return fail(FKT_EINVAL, "ninst must be >= 1");
+    if (offsets[0] != 0) return fail(FKT_EINVAL, "offsets[0] must be 0");
+    for (int i = 0; i < ninst; ++i)
+        if (offsets[i + 1] < offsets[i]) return fail(FKT_EINVAL, "offsets must be non-decreasing");
+    return make_plan(points, offsets[ninst], d, offsets, ninst, k, leaf_size, order, opt, out);
 }
 
 fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
@@ -587,6 +609,126 @@ fkt_status fkt_learn_train(fkt_plan_t P, double sigma2, int steps, int batch, do
     if (st != FKT_OK) return st;
     st = fkt::learn_train(P, P->learn, (int)P->opt.prec, sigma2, steps, batch, lr, seed, loss_first, loss_last);
     return st == FKT_OK ? FKT_OK : fail(st, "learned preconditioner training");
+}
+
+struct fkt_graph_s {
+    fkt_plan_t plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~fkt_graph_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+fkt_status fkt_graph_create(fkt_plan_t P, const void* x, void* y, int nrhs, fkt_graph_t* out)
+{
+    if (!out) return fail(FKT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_mvm");
+    if (!x || !y) return fail(FKT_EINVAL, "x or y is NULL");
+    if (nrhs < 1 || nrhs > 64) return fail(FKT_EINVAL, "nrhs must be in [1, 64]");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+    fkt_graph_s* G = new (std::nothrow) fkt_graph_s();
+    if (!G) {
+        (void)hipStreamDestroy(cap);
+        return fail(FKT_ENOMEM, "graph allocation");
+    }
+    G->plan = P;
+    // the whole MVM, stages in order on one stream (no memset nodes: the
+    // accumulators are cleared by the gather kernel)
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipSuccess;
+        if (P->opt.mrhs != 0 && nrhs % fkt::kMrCols == 0)
+            le = fkt::launch_mvm_mrhs(P->dp, P->wk, P->mr, (const float*)x, (float*)y, nrhs, cap);
+        else
+            for (int c = 0; c < nrhs && le == hipSuccess; ++c)
+                le = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, cap, false, nullptr);
+        e = hipStreamEndCapture(cap, &G->graph);
+        if (e == hipSuccess && le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        delete G;
+        return hip_fail(e, "graph capture");
+    }
+    *out = G;
+    return FKT_OK;
+}
+
+fkt_status fkt_graph_launch(fkt_graph_t G)
+{
+    if (!G) return fail(FKT_EINVAL, "graph is NULL");
+    DeviceScope ds(G->plan->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    const hipError_t e = hipGraphLaunch(G->exec, G->plan->stream);
+    return e == hipSuccess ? FKT_OK : hip_fail(e, "graph launch");
+}
+
+void fkt_graph_destroy(fkt_graph_t G) { delete G; }
+
+fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int ninst, int64_t n, int d, fkt_kernel k,
+                             int order, const fkt_options* opt, const int* candidates, int ncand, int nrhs, int reps,
+                             int* best, double* ms)
+{
+    if (!candidates || ncand < 1 || !best) return fail(FKT_EINVAL, "candidates, ncand or best invalid");
+    if (nrhs < 1 || nrhs > 64 || reps < 1) return fail(FKT_EINVAL, "nrhs must be in [1, 64] and reps >= 1");
+    fkt_options o;
+    fkt_default_options(&o);
+    if (opt) o = *opt;
+    if (o.device < 0) return fail(FKT_EINVAL, "autotuning needs a device");
+    o.profile = 0;
+    const int64_t ntot = offsets ? offsets[ninst] : n;
+    const size_t bytes = (o.prec == FKT_F32 ? sizeof(float) : sizeof(double)) * (size_t)ntot * nrhs;
+    DeviceScope ds(o.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    void *x = nullptr, *y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t he;
+    if ((he = hipMalloc(&x, bytes)) || (he = hipMalloc(&y, bytes)) || (he = hipMemset(x, 0, bytes)) ||
+        (he = hipEventCreate(&e0)) || (he = hipEventCreate(&e1))) {
+        if (x) (void)hipFree(x);
+        if (y) (void)hipFree(y);
+        return hip_fail(he, "autotune buffers");
+    }
+    fkt_status st = FKT_OK;
+    double best_ms = 0.0;
+    *best = -1;
+    for (int c = 0; c < ncand && st == FKT_OK; ++c) {
+        fkt_plan_t P = nullptr;
+        st = offsets ? fkt_plan_batch(points, offsets, ninst, d, k, candidates[c], order, &o, &P)
+                     : fkt_plan(points, n, d, k, candidates[c], order, &o, &P);
+        if (st != FKT_OK) break;
+        // one untimed pass, then reps timed passes bracketed by events
+        st = fkt_mvm(P, x, y, nrhs);
+        if (st == FKT_OK && hipEventRecord(e0, P->stream) != hipSuccess) st = fail(FKT_EDEVICE, "event record");
+        for (int r = 0; r < reps && st == FKT_OK; ++r) st = fkt_mvm(P, x, y, nrhs);
+        float t = 0.f;
+        if (st == FKT_OK && (hipEventRecord(e1, P->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+            st = fail(FKT_EDEVICE, "autotune timing");
+        fkt_destroy(P);
+        if (st != FKT_OK) break;
+        const double per = (double)t / reps;
+        if (ms) ms[c] = per;
+        if (*best < 0 || per < best_ms) {
+            best_ms = per;
+            *best = candidates[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    return st;
 }
 
 }  // extern "C"

@@ -31,6 +31,11 @@ struct Tree {
     std::vector<double> rho2;    // squared radius: max over the node's points of |x - ctr|^2
     std::vector<int64_t> begin, end;    // point range [begin, end) in tree order
     std::vector<int32_t> kid0, kid1, parent, level;
+    // independent instances (a forest): instance i owns tree positions
+    // [inst_begin[i], inst_begin[i + 1]) and the tree rooted at inst_root[i]
+    // (-1 for an empty instance); one instance for a plain plan
+    std::vector<int64_t> inst_begin;
+    std::vector<int32_t> inst_root;
     int64_t nnodes() const { return (int64_t)rho2.size(); }
     bool leaf(int64_t b) const { return kid0[b] < 0 && kid1[b] < 0; }
 };
@@ -76,6 +81,9 @@ struct Tables {
 constexpr int kExpTab = 256;
 
 void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth, Tree& T);
+// One tree per instance (points of instance i: rows offsets[i] .. offsets[i+1]
+// of X), concatenated in instance order; no interaction crosses instances.
+void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int leaf_size, int max_depth, Tree& T);
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 void build_tables(int d, int p, Tables& tab);
 

@@ -170,6 +170,8 @@ void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth,
     T.pts.resize((size_t)n * d);
     for (int64_t i = 0; i < n; ++i)
         for (int a = 0; a < d; ++a) T.pts[i * d + a] = X[T.perm[i] * d + a];
+    T.inst_begin = {0, n};
+    T.inst_root = {0};
 
     const int64_t nn = T.nnodes();
     parallel_for(nn, 64, [&](int64_t b0, int64_t b1) {
@@ -186,6 +188,37 @@ void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth,
             T.rho2[b] = m;
         }
     });
+}
+
+void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int leaf_size, int max_depth, Tree& T)
+{
+    T = Tree();
+    T.d = d;
+    T.n = offsets[ninst];
+    T.inst_begin.assign(offsets, offsets + ninst + 1);
+    T.inst_root.assign(ninst, -1);
+    Tree Ti;
+    for (int i = 0; i < ninst; ++i) {
+        const int64_t po = offsets[i], ni = offsets[i + 1] - po;
+        if (ni <= 0) continue;
+        build_tree(X + po * d, ni, d, leaf_size, max_depth, Ti);
+        const int32_t no = (int32_t)T.nnodes();
+        T.inst_root[i] = no;
+        for (int64_t q : Ti.perm) T.perm.push_back(q + po);
+        T.pts.insert(T.pts.end(), Ti.pts.begin(), Ti.pts.end());
+        T.lo.insert(T.lo.end(), Ti.lo.begin(), Ti.lo.end());
+        T.side.insert(T.side.end(), Ti.side.begin(), Ti.side.end());
+        T.ctr.insert(T.ctr.end(), Ti.ctr.begin(), Ti.ctr.end());
+        T.rho2.insert(T.rho2.end(), Ti.rho2.begin(), Ti.rho2.end());
+        for (int64_t b = 0; b < Ti.nnodes(); ++b) {
+            T.begin.push_back(Ti.begin[b] + po);
+            T.end.push_back(Ti.end[b] + po);
+            T.kid0.push_back(Ti.kid0[b] >= 0 ? Ti.kid0[b] + no : -1);
+            T.kid1.push_back(Ti.kid1[b] >= 0 ? Ti.kid1[b] + no : -1);
+            T.parent.push_back(Ti.parent[b] >= 0 ? Ti.parent[b] + no : -1);
+            T.level.push_back(Ti.level[b]);
+        }
+    }
 }
 
 // ------------------------------------------------------------- partition
@@ -224,7 +257,17 @@ void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_p
             const int cnt = L.blk_count[q];
             BlockLists& out = per[q];
             stack.clear();
-            stack.emplace_back(0, cnt == 64 ? ~uint64_t(0) : ((uint64_t(1) << cnt) - 1));
+            // one walk per instance the block's targets belong to, from its root
+            int64_t i = std::upper_bound(T.inst_begin.begin(), T.inst_begin.end(), tb) - T.inst_begin.begin() - 1;
+            for (; i + 1 < (int64_t)T.inst_begin.size() && T.inst_begin[i] < tb + cnt; ++i) {
+                if (T.inst_root[i] < 0) continue;
+                const int64_t l0 = std::max<int64_t>(T.inst_begin[i], tb) - tb;
+                const int64_t l1 = std::min<int64_t>(T.inst_begin[i + 1], tb + cnt) - tb;
+                if (l1 <= l0) continue;
+                const uint64_t hi = l1 == 64 ? ~uint64_t(0) : ((uint64_t(1) << l1) - 1);
+                const uint64_t lo = (uint64_t(1) << l0) - 1;
+                stack.emplace_back(T.inst_root[i], hi & ~lo);
+            }
             while (!stack.empty()) {
                 auto [b, active] = stack.back();
                 stack.pop_back();

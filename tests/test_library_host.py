@@ -120,3 +120,34 @@ def test_duplicate_points_hit_depth_cap():
     T = oracle.Tree(X, 8, max_depth=20)
     for mine, ref in zip(p.target_counts(), T.counts(0.5)):
         np.testing.assert_array_equal(mine, ref)
+
+
+def test_batch_plan_is_a_forest_of_oracle_trees():
+    """fkt_plan_batch: each instance partitioned exactly as the oracle's own
+    tree of that instance alone; no (target, source) pair crosses instances."""
+    sizes = [700, 1, 0, 64, 2500, 129]
+    X, off = W.batched_instances(sizes, 3, 500)
+    theta = 0.45
+    p = F.fkt_plan_batch((X, off), "gaussian", 50, 3, lengthscale=0.2, theta=theta, device=None)
+    counts = p.target_counts()
+    perm = p.perm()
+    nnodes = 0
+    for i, m in enumerate(sizes):
+        if m == 0:
+            continue
+        a, b = off[i], off[i + 1]
+        T = oracle.Tree(X[a:b], 50)
+        nnodes += T.nnodes
+        for mine, ref in zip(counts, T.counts(theta)):
+            np.testing.assert_array_equal(mine[a:b], ref)
+        assert int(counts[1][a:b].sum() + counts[3][a:b].sum()) == m * m
+        assert sorted(perm[a:b].tolist()) == list(range(a, b))   # tree positions stay in the instance
+    assert p.info()["nnodes"] == nnodes
+
+
+def test_batch_plan_rejects_bad_offsets():
+    X = W.uniform_cube(10, 3, 1)
+    with pytest.raises(F.FktError):
+        F.fkt_plan_batch((X, np.array([0, 6, 4, 10])), "gaussian", 8, 2, lengthscale=0.2, device=None)
+    with pytest.raises(F.FktError):
+        F.fkt_plan_batch((X, np.array([1, 10])), "gaussian", 8, 2, lengthscale=0.2, device=None)
