@@ -136,6 +136,107 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     return out
 
 
+def _sync_time(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def batch_leg(F, torch, reps, theta, err_per_inst):
+    """Batched uneven instances: 256 sets in d = 3 with log-uniform sizes in
+    [1e3, 1e5], rational quadratic kernel, 4 RHS, FP32: one forest plan
+    (eager launches and one HIP graph) against per-instance plans and
+    launches; leaf size from the library's autotuner."""
+    import oracle
+    spec = W.WORKLOADS["batch256_rq"]
+    sizes = W.instance_sizes(spec["ninst"], spec["nmin"], spec["nmax"], spec["size_seed"])
+    X, off = W.batched_instances(sizes, spec["d"], spec["pts_seed"])
+    n = X.shape[0]
+    x64 = W.normal_rhs(n, spec["nrhs"], spec["rhs_seed"])
+    kw = dict(lengthscale=spec["lengthscale"], alpha=spec["alpha"])
+    p = spec["order"]
+    t0 = time.perf_counter()
+    leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [64, 128, 256, 512], nrhs=spec["nrhs"], reps=2,
+                                     theta=theta, prec="f32", batch=True, **kw)
+    tune_s = time.perf_counter() - t0
+    print(f"bench: batch autotune {tune} -> leaf {leaf} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    x = torch.as_tensor(x64, dtype=torch.float32, device="cuda").contiguous()
+    y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    plan = F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
+    plan_s = time.perf_counter() - t0
+    F.fkt_mvm(plan, x, y)
+    eager_ms = _sync_time(torch, lambda: F.fkt_mvm(plan, x, y), reps)
+    g = F.Graph(plan, x, y)
+    g.launch()
+    graph_ms = _sync_time(torch, g.launch, reps)
+    yb = y.double().cpu().numpy()
+    g.close()
+    plan.close()
+    # per-instance plans, one fkt_mvm each
+    t0 = time.perf_counter()
+    plans = [F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
+             for i in range(len(sizes))]
+    plans_s = time.perf_counter() - t0
+    xs = [x[off[i]:off[i + 1]] for i in range(len(sizes))]
+    ys = [y[off[i]:off[i + 1]] for i in range(len(sizes))]
+
+    def per_instance():
+        for q, xi, yi in zip(plans, xs, ys):
+            F.fkt_mvm(q, xi, yi)
+    per_instance()
+    per_ms = _sync_time(torch, per_instance, reps)
+    for q in plans:
+        q.close()
+    # error against the dense FP64 sum on sampled targets of a few instances
+    errs = []
+    for i in W.subsample(len(sizes), 8, 3005):
+        a, b = off[i], off[i + 1]
+        tg = W.subsample(b - a, err_per_inst, 3006 + int(i))
+        zd = oracle.dense_mvm(X[a:b], x64[a:b], "ratquad", targets=tg, lengthscale=spec["lengthscale"],
+                              shape=spec["alpha"])
+        errs.append(float(np.linalg.norm(yb[a:b][tg] - zd) / np.linalg.norm(zd)))
+    out = {"workload": f"batch{len(sizes)}_rq_d3_n{n}", "instances": len(sizes), "n_total": int(n),
+           "size_min": int(sizes.min()), "size_max": int(sizes.max()), "nrhs": spec["nrhs"], "dtype": "f32",
+           "theta": theta, "p": p, "leaf": leaf, "autotune_ms": tune, "batched_graph_ms": graph_ms,
+           "batched_eager_ms": eager_ms, "per_instance_ms": per_ms,
+           "batched_graph_mpoints_per_s": n / graph_ms / 1e3, "speedup_graph_vs_per_instance": per_ms / graph_ms,
+           "plan_seconds_batched": plan_s, "plan_seconds_per_instance_total": plans_s,
+           "rel_err_vs_dense_max_of_8_instances": max(errs)}
+    print(f"bench: batch {len(sizes)} instances n={n}: graph {graph_ms:.2f} ms, eager {eager_ms:.2f} ms, "
+          f"per-instance {per_ms:.2f} ms; err {max(errs):.2e}", file=sys.stderr, flush=True)
+    return out
+
+
+def mrhs_leg(F, torch, reps, theta, err_targets):
+    """Mixed precision, many RHS: 500k points of a 10-component mixture in
+    d = 5, Gaussian length scale 0.2, p = 8, 32 RHS, FP32 plan: column by
+    column against the matrix-core near field in FP32 and in bf16."""
+    import oracle
+    spec = W.WORKLOADS["gmm5_n500k_gauss32"]
+    n = spec["n"]
+    X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
+    x64 = W.normal_rhs(n, spec["nrhs"], spec["rhs_seed"])
+    x = torch.as_tensor(x64, dtype=torch.float32, device="cuda").contiguous()
+    tg = W.subsample(n, err_targets, 3007)
+    zd = oracle.dense_mvm(X, x64, spec["kernel"], targets=tg, lengthscale=spec["lengthscale"])
+    out = {"workload": f"gmm5_n{n}_gauss_32rhs", "n": n, "d": 5, "p": spec["order"], "theta": theta, "nrhs": 32}
+    for name, mr in (("columns_f32", None), ("mfma_f32", "f32"), ("mfma_bf16", "bf16")):
+        plan = F.fkt_plan(X, spec["kernel"], 256, spec["order"], theta=theta, prec="f32", mrhs=mr,
+                          lengthscale=spec["lengthscale"])
+        y = F.fkt_mvm(plan, x)
+        ms = _sync_time(torch, lambda: F.fkt_mvm(plan, x, y), reps)
+        z = y.double().cpu().numpy()[tg]
+        err = float(np.linalg.norm(z - zd) / np.linalg.norm(zd))
+        out[name] = {"ms_per_mvm_32rhs": ms, "mpoints_rhs_per_s": n * 32 / ms / 1e3, "rel_err_vs_dense_fp64": err}
+        print(f"bench: mrhs {name}: {ms:.1f} ms per 32-column MVM, err {err:.2e}", file=sys.stderr, flush=True)
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +259,8 @@ def main():
                     help="points of the GP solves (the d = 4 mixture workload at 200k takes minutes); 0 skips them")
     ap.add_argument("--gp-maxit", type=int, default=3000)
     ap.add_argument("--gp-train-steps", type=int, default=100)
+    ap.add_argument("--batch-theta", type=float, default=0.35)
+    ap.add_argument("--mrhs-theta", type=float, default=0.4)
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -200,6 +303,11 @@ def main():
         # the workload's length scale 0.3, and 0.1 where per-leaf preconditioning has something to act on
         gp = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
 
+    batch = mrhs = None
+    if not a.no_variants:
+        batch = batch_leg(F, torch, 3, a.batch_theta, min(200, max(a.err_targets // 10, 50)))
+        mrhs = mrhs_leg(F, torch, 2, a.mrhs_theta, min(a.err_targets, 500))
+
     cpu = None
     if a.cpu_seconds > 0:
         # the oracle as it stands: rows of its Algorithm 1 (pairwise far
@@ -234,6 +342,8 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "gp_solve": gp,
+        "batched_instances": batch,
+        "many_rhs": mrhs,
     }
     print(json.dumps(out))
 

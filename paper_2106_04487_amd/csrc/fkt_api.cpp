@@ -323,6 +323,11 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
             delete P;
             return fail(FKT_EUNSUPPORTED, "near sets exceed 2^31 (target, leaf) pairs; use fewer points or a smaller theta");
         }
+        std::string err;
+        if (!fkt::check_lists(P->T, P->L, err)) {
+            delete P;
+            return fail(FKT_EINVAL, "internal error: " + err);
+        }
         fkt::build_tables(d, order, P->tab);
     } catch (const std::bad_alloc&) {
         delete P;

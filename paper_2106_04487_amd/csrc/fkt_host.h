@@ -86,6 +86,8 @@ void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth,
 void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int leaf_size, int max_depth, Tree& T);
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 void build_tables(int d, int p, Tables& tab);
+// Bounds of every index the kernels derive from the lists (false + err).
+bool check_lists(const Tree& T, const Lists& L, std::string& err);
 
 // K(r) for a kernel (K(0) = 0 for the singular 1/r), FP64, host side.
 double kernel_value(const fkt_kernel& k, double r);

@@ -502,15 +502,15 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
     double pgeo = 0.0;
     // Fetch job j's node moments and centres into registers: lane i of row q
     // holds entry q*64 + i of the job's concatenated moments. Entries past
-    // the job's last node are clamped to it (valid addresses; never read).
+    // the job's nn * R are clamped to its last entry (a valid address; the
+    // value is never read).
     auto fetch = [&](int j) {
         const int n0 = a.job_noff[j], nn = a.job_noff[j + 1] - n0;
         const int myslot = a.job_nodes[n0 + (lane < nn ? lane : nn - 1)];
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int i = q * kWave + lane;
-            int node = i / R;
-            node = node < nn ? node : nn - 1;
+            const int i = min(q * kWave + lane, nn * R - 1);
+            const int node = i / R;
             const int slot = __shfl(myslot, node, kWave);
             pre[q] = mom[(unsigned)(slot * R + (i - node * R))];
         }

@@ -583,4 +583,75 @@ bool build_block_jacobi(const Tree& T, const fkt_kernel& k, double sigma2, std::
     return ok;
 }
 
+// Every index a device kernel derives from the work lists, checked against
+// the sizes of the buffers it reads (a plan that fails is never launched).
+bool check_lists(const Tree& T, const Lists& L, std::string& err)
+{
+    const int64_t n = T.n, nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
+    const int64_t njobs = (int64_t)L.job_noff.size() - 1;
+    auto bad = [&](const std::string& what, int64_t i) {
+        err = "plan check: " + what + " at " + std::to_string(i);
+        return false;
+    };
+    if ((int64_t)L.blk_count.size() != nb) return bad("block arrays", 0);
+    for (int64_t q = 0; q < nb; ++q)
+        if (L.blk_count[q] < 1 || L.blk_count[q] > kBlock || L.blk_begin[q] < 0 || L.blk_begin[q] + L.blk_count[q] > n)
+            return bad("block range", q);
+    // near units (source-major near field)
+    const int64_t nu = (int64_t)L.nu_beg.size();
+    if ((int64_t)L.nu_end.size() != nu || (int64_t)L.nu_toff.size() != nu || (int64_t)L.nu_tcnt.size() != nu)
+        return bad("near-unit arrays", 0);
+    for (int64_t u = 0; u < nu; ++u) {
+        if (L.nu_beg[u] < 0 || L.nu_beg[u] > L.nu_end[u] || L.nu_end[u] > n) return bad("near-unit sources", u);
+        if (L.nu_tcnt[u] < 1 || L.nu_tcnt[u] > kNearUnitTargets || L.nu_toff[u] < 0 ||
+            (int64_t)L.nu_toff[u] + L.nu_tcnt[u] > (int64_t)L.near_tgt.size())
+            return bad("near-unit targets", u);
+    }
+    for (size_t i = 0; i < L.near_tgt.size(); ++i)
+        if (L.near_tgt[i] < 0 || L.near_tgt[i] >= n) return bad("near target", (int64_t)i);
+    // target-major near lists (many-RHS near field)
+    if ((int64_t)L.near_off.size() != nb + 1 || L.near_off[0] != 0 || L.near_off[nb] != (int64_t)L.near_beg.size())
+        return bad("near list offsets", 0);
+    for (int64_t q = 0; q < nb; ++q)
+        if (L.near_off[q + 1] < L.near_off[q]) return bad("near list offsets", q);
+    for (size_t e = 0; e < L.near_beg.size(); ++e)
+        if (L.near_beg[e] < 0 || L.near_beg[e] > L.near_end[e] || L.near_end[e] > n) return bad("near entry", (int64_t)e);
+    // far-field jobs
+    if ((int64_t)L.job_off.size() != nb + 1 || L.job_off[0] != 0 || L.job_off[nb] != njobs)
+        return bad("job offsets", 0);
+    if (L.job_noff[0] != 0 || L.job_noff[njobs] != (int64_t)L.job_nodes.size() ||
+        (int64_t)L.job_pairs.size() != njobs * kBlock)
+        return bad("job arrays", 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        if (L.job_off[q + 1] < L.job_off[q]) return bad("job offsets", q);
+        for (int64_t j = L.job_off[q]; j < L.job_off[q + 1]; ++j) {
+            const int nn = L.job_noff[j + 1] - L.job_noff[j];
+            if (nn < 1 || nn > L.max_job_nodes) return bad("job node count", j);
+            for (int k = 0; k < nn; ++k) {
+                const int32_t sl = L.job_nodes[L.job_noff[j] + k];
+                if (sl < 0 || sl >= ns) return bad("job node slot", j);
+            }
+            for (int lane = 0; lane < kBlock; ++lane) {
+                const uint16_t pw = L.job_pairs[(size_t)j * kBlock + lane];
+                if (pw == 0xffffu) continue;
+                if ((pw & 63) >= L.blk_count[q] || (pw >> 6) >= nn) return bad("job pair", j);
+            }
+        }
+    }
+    if ((int64_t)L.slot_ctr.size() != ns * T.d || (int64_t)L.slot_scale.size() != ns) return bad("slot arrays", 0);
+    // s2m units and partial sums
+    for (size_t u = 0; u < L.unit_slot.size(); ++u) {
+        if (L.unit_slot[u] < 0 || L.unit_slot[u] >= ns) return bad("s2m unit slot", (int64_t)u);
+        if (L.unit_begin[u] < 0 || L.unit_begin[u] >= L.unit_end[u] || L.unit_end[u] > n ||
+            L.unit_end[u] - L.unit_begin[u] > kUnitPoints)
+            return bad("s2m unit range", (int64_t)u);
+        const int32_t dst = L.unit_dst[u];
+        if (dst >= 0 ? dst >= ns : (int64_t)(-1 - (int64_t)dst) >= L.npartials) return bad("s2m unit target", (int64_t)u);
+    }
+    if (L.red_off.size() != L.red_slot.size() + 1 || L.red_off.back() != L.npartials) return bad("partial lists", 0);
+    for (size_t r = 0; r < L.red_slot.size(); ++r)
+        if (L.red_slot[r] < 0 || L.red_slot[r] >= ns || L.red_off[r + 1] < L.red_off[r]) return bad("partial list", (int64_t)r);
+    return true;
+}
+
 }  // namespace fkt
