@@ -43,9 +43,9 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 # and the multiply-accumulate with the weight (2).
 NEAR_FLOPS_PER_PAIR = {"laplace": 12, "matern32": 16}
 # HBM bytes per near-field launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (scale factors of a plain copy), profiles/k_near_matern32_f64_n1m_counters.md;
-# to be re-measured whenever the near kernel changes.
-NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.376e9}
+# (scale factors of a plain copy) of the current near kernel, from the
+# counter profile under profiles/; empty until re-measured after a change.
+NEAR_TRAFFIC_BYTES = {}
 
 
 def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True):
