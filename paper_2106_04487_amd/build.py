@@ -48,8 +48,12 @@ def _jobs():
     for kind in range(7):
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "stage_m2t.hip"),
                      "-o", os.path.join(BUILD, f"stage_m2t_{kind}.o")])
+    # many-RHS multipole-to-target on the matrix cores, one object per kernel kind
+    for kind in range(7):
+        jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "m2t_mrhs.hip"),
+                     "-o", os.path.join(BUILD, f"m2t_mrhs_{kind}.o")])
     # longest compiles first (the high-order d = 5 moment kernels)
-    jobs.sort(key=lambda j: 0 if "-DFKT_S2M_D=5" in j else 1)
+    jobs.sort(key=lambda j: 0 if ("-DFKT_S2M_D=5" in j or any("m2t_mrhs" in a for a in j)) else 1)
     return jobs
 
 

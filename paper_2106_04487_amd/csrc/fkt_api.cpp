@@ -265,6 +265,17 @@ static fkt_status upload_plan(fkt_plan_t P)
             return hip_fail(e, "many-RHS weights");
         if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * P->n, &P->mr.zf)) != hipSuccess)
             return hip_fail(e, "many-RHS far-field buffer");
+        // far field on the matrix cores: moments of the 32 columns and their
+        // bf16 high/low B fragments (rank padded to a multiple of 64)
+        const int64_t ns = (int64_t)L.slot_node.size(), R = P->tab.rank;
+        P->mr.ks = (int)((R + 63) / 64 * 2);
+        if (ns > 0) {
+            if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * ns * R, &P->mr.mom)) != hipSuccess)
+                return hip_fail(e, "many-RHS moments");
+            const size_t fb = (size_t)ns * P->mr.ks * 2 * 64 * 16;
+            if ((e = P->alloc(fb, &P->mr.bhi)) != hipSuccess || (e = P->alloc(fb, &P->mr.blo)) != hipSuccess)
+                return hip_fail(e, "many-RHS moment fragments");
+        }
     }
     // second stream (default priority) and fork/join events for running the
     // near field beside the far field

@@ -24,6 +24,11 @@ struct DevMrhs {
     void* xt = nullptr;               // [32][npad] weights of the group (bf16 or FP32)
     void* zf = nullptr;               // [32][n] far field of the group, FP32, tree order
     bool bf16 = false;
+    // far field of the group on the matrix cores
+    void* mom = nullptr;              // [32][nslots][rank] FP32 moments (one s2m per column)
+    void* bhi = nullptr;              // [nslots][ks][2][64] bf16 x 8 MFMA B fragments, high part
+    void* blo = nullptr;              //   and low part (m - hi)
+    int ks = 0;                       // 32-entry k-steps per node (rank padded to a multiple of 64)
 };
 
 // far field of one column (gather clearing wk.zacc, s2m, m2t into wk.zacc)
@@ -31,6 +36,18 @@ hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* x,
                              hipStream_t s);
 // FP32 near-kernel constants (log2(e) folded where an exponential follows)
 void near_consts_f32(const DevPlan& a, float& c0, float& c1);
+#define FKT_DECLARE_M2T_MRHS(K) bool launch_m2t_mrhs_kind##K(const DevPlan& a, const DevMrhs& mr, hipStream_t s);
+FKT_DECLARE_M2T_MRHS(0)
+FKT_DECLARE_M2T_MRHS(1)
+FKT_DECLARE_M2T_MRHS(2)
+FKT_DECLARE_M2T_MRHS(3)
+FKT_DECLARE_M2T_MRHS(4)
+FKT_DECLARE_M2T_MRHS(5)
+FKT_DECLARE_M2T_MRHS(6)
+#undef FKT_DECLARE_M2T_MRHS
+// s2m of one column into the given moment buffer (gather included)
+hipError_t launch_s2m_column(const DevPlan& a, const DevWork& wk, const void* x, int nrhs, int col, int prec,
+                             hipStream_t s);
 // y = K~ x for nrhs (a multiple of 32) FP32 columns
 hipError_t launch_mvm_mrhs(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, const float* x, float* y, int nrhs,
                            hipStream_t s);

@@ -1,0 +1,233 @@
+// Far field of a group of 32 right-hand sides on the matrix cores (FP32
+// plans), one object per kernel kind (FKT_M2T_KIND, set when compiling).
+//
+// For a (target, far node) pair the multipole-to-target step is a dot
+// product of the pair's basis vector b (entries Y_kh(r^) (s/|r|)^j F_kj(|r|),
+// the same factors as the one-column kernel) with the node's moments, so
+// for 32 columns it is a (pairs x rank) by (rank x 32) product. One wave owns
+// a 64-target block and walks its packed far jobs (64 pairs, <= MAXN nodes,
+// lanes grouped by node): each lane generates its pair's basis entries in
+// emission order and writes them, split into bf16 high and low parts, into
+// an LDS chunk laid out as MFMA A fragments; every 64 entries the chunk is
+// multiplied by each job node's moments (bf16 high/low B fragments prepared
+// once per group) with v_mfma_f32_16x16x32_bf16, three products per tile
+// (hi*hi + hi*lo + lo*hi: about 16 bits of mantissa), rows of other nodes
+// masked to zero. Pair rows are then added into the block's per-target LDS
+// sums, which are written once per (target, column).
+#include <hip/hip_runtime.h>
+
+#include "fkt_kernels.h"
+#include "fkt_mrhs.h"
+
+#ifndef FKT_M2T_KIND
+#error "compile with -DFKT_M2T_KIND=<fkt_kernel_kind value>"
+#endif
+#define FKT_CAT2(a, b) a##b
+#define FKT_CAT(a, b) FKT_CAT2(a, b)
+
+namespace fkt {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kKC = 64;  // basis entries per LDS chunk: two MFMA k-steps of 32
+
+template <int D, int P, int KIND>
+__global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const bf8* __restrict__ Bhi,
+                                                    const bf8* __restrict__ Blo, int KS, float* __restrict__ zf)
+{
+    constexpr int R = cbinom(P + D, D);
+    constexpr int RP = (R + kKC - 1) / kKC * kKC;
+    constexpr int NF = f_off(P, P + 1);
+    constexpr int MAXN = m2t_max_job_nodes(D, P, (int)sizeof(float));
+    __shared__ bf8 Ahi[4][2][kWave];  // [row tile][k-step in chunk][fragment lane]
+    __shared__ bf8 Alo[4][2][kWave];
+    __shared__ float Zb[kWave][kMrCols + 1];
+    const int blk = blockIdx.x, lane = threadIdx.x, r16 = lane & 15;
+    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
+    for (int c = 0; c <= kMrCols; ++c) Zb[lane][c] = 0.f;
+    double tx[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
+
+    const int j0 = a.job_off[blk], j1 = a.job_off[blk + 1];
+    for (int j = j0; j < j1; ++j) {
+        const int n0 = a.job_noff[j], nn = a.job_noff[j + 1] - n0;
+        const unsigned pw = a.job_pairs[(size_t)j * kWave + lane];
+        const bool valid = pw != 0xffffu;
+        const int lt = pw & 63, ni = valid ? (int)(pw >> 6) : 0;
+        uint64_t nodemask[MAXN];
+#pragma unroll
+        for (int k = 0; k < MAXN; ++k) nodemask[k] = __ballot(valid && ni == k);
+        const int slot = a.job_nodes[n0 + ni];
+        double txl[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) txl[i] = __shfl(tx[i], lt, kWave);
+
+        // geometry and radial factors of this lane's pair (FP64), as in k_m2t
+        double r[D], r2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            r[i] = valid ? txl[i] - a.slot_ctr[(size_t)slot * D + i] : (i == 0 ? 1.0 : 0.0);
+            r2 = fma(r[i], r[i], r2);
+        }
+        const double ir = rsqrt_pos(r2);
+        const double rr = r2 * ir;
+        float x[D], rho2[D + 1];
+        rho2[0] = 0.f;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            x[i] = (float)(r[i] * ir);
+            rho2[i + 1] = rho2[i] + x[i] * x[i];
+        }
+        rho2[D] = 1.f;
+        float rad[NF];
+        {
+            double Dm[P + 1];
+            radial_derivs<KIND, P>(a, rr, Dm);
+            double um[P + 1];
+            um[0] = Dm[0];
+            double rp = 1.0;
+#pragma unroll
+            for (int m = 1; m <= P; ++m) {
+                rp *= rr;
+                um[m] = Dm[m] * rp;
+            }
+            const double v = a.slot_scale[slot] * ir;
+            double vp[P + 1];
+            vp[0] = 1.0;
+#pragma unroll
+            for (int jp = 1; jp <= P; ++jp) vp[jp] = vp[jp - 1] * v;
+            auto radial_k = [&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                auto radial_j = [&](auto jc) {
+                    constexpr int jj = decltype(jc)::value;
+                    constexpr int jv = k + 2 * jj;
+                    double f = (jv == 0) ? um[0] : 0.0;
+                    auto term = [&](auto mc) {
+                        constexpr int m = decltype(mc)::value + 1;
+                        constexpr double c = cx_tbar(D, k, jv, m);
+                        f = fma(um[m], c, f);
+                    };
+                    static_for<0, jv>(term);
+                    rad[f_off(P, k) + jj] = valid ? (float)(vp[jv] * f) : 0.f;
+                };
+                static_for<0, nj_of(P, k)>(radial_j);
+            };
+            static_for<0, P + 1>(radial_k);
+        }
+
+        f4 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+        // contract the chunk holding entries [kbase, kbase + 64) with every node
+        auto flush = [&](int kbase) {
+            __syncthreads();
+            const int ks0 = kbase / 32;
+#pragma unroll
+            for (int k = 0; k < MAXN; ++k) {
+                if (k >= nn) break;
+                const uint64_t nm = nodemask[k];
+                const int sl = a.job_nodes[n0 + k];
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const size_t fb = ((size_t)sl * KS + ks0 + ks) * 2 * kWave;
+                    const bf8 bh0 = Bhi[fb + lane], bh1 = Bhi[fb + kWave + lane];
+                    const bf8 bl0 = Blo[fb + lane], bl1 = Blo[fb + kWave + lane];
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt) {
+                        if (((nm >> (16 * rt)) & 0xffffull) == 0) continue;
+                        const bool mine = (nm >> (16 * rt + r16)) & 1ull;
+                        const bf8 z = {};
+                        const bf8 ah = mine ? Ahi[rt][ks][lane] : z;
+                        const bf8 al = mine ? Alo[rt][ks][lane] : z;
+                        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, acc[rt][0], 0, 0, 0);
+                        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, acc[rt][0], 0, 0, 0);
+                        acc[rt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, acc[rt][0], 0, 0, 0);
+                        acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, acc[rt][1], 0, 0, 0);
+                        acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, acc[rt][1], 0, 0, 0);
+                        acc[rt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, acc[rt][1], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        // entry idx of this lane's row goes to fragment lane (lane % 16) + 16 g,
+        // element q, of row tile lane / 16, with g = (idx % 32) / 8, q = idx % 8
+        __bf16* hrow = (__bf16*)&Ahi[lane >> 4][0][0];
+        __bf16* lrow = (__bf16*)&Alo[lane >> 4][0][0];
+        auto put = [&](int idx, float bv) {
+            const int c = idx % kKC, ks = c / 32, g = (c % 32) / 8, q = c % 8;
+            const __bf16 h = (__bf16)bv;
+            const __bf16 l = (__bf16)(bv - (float)h);
+            const int o = (ks * kWave + r16 + 16 * g) * 8 + q;
+            hrow[o] = h;
+            lrow[o] = l;
+            if (c == kKC - 1) flush(idx - (kKC - 1));
+        };
+        int off = 0;
+        auto emit = [&](auto kc, float yv) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int nj = nj_of(P, k);
+            auto one = [&](auto jc) {
+                constexpr int jj = decltype(jc)::value;
+                put(off + jj, yv * rad[f_off(P, k) + jj]);
+            };
+            static_for<0, nj>(one);
+            off += nj;
+        };
+        harmonics<D, P, false, float>(x, rho2, (const float*)nullptr, emit);
+        auto pad = [&](auto ic) {
+            constexpr int idx = R + decltype(ic)::value;
+            put(idx, 0.f);
+        };
+        static_for<0, RP - R>(pad);
+
+        // pair rows into the block's per-target sums
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * rt + 4 * (lane >> 4) + q;
+                    const unsigned prow = (unsigned)__shfl((int)pw, row, kWave);
+                    if (prow != 0xffffu) atomicAdd(&Zb[prow & 63][16 * ct + r16], acc[rt][ct][q]);
+                }
+    }
+    __syncthreads();
+    if (lane < cnt)
+        for (int c = 0; c < kMrCols; ++c) zf[(size_t)c * a.n + tb + lane] = Zb[lane][c];
+}
+
+template <int D, int P = 0>
+bool launch_d(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
+{
+    if constexpr (P > PMax<D>::value) {
+        return false;
+    } else {
+        if (a.p == P) {
+            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks), dim3(kWave), 0, s, a,
+                               (const bf8*)mr.bhi, (const bf8*)mr.blo, mr.ks, (float*)mr.zf);
+            return true;
+        }
+        return launch_d<D, P + 1>(a, mr, s);
+    }
+}
+
+}  // namespace
+
+bool FKT_CAT(launch_m2t_mrhs_kind, FKT_M2T_KIND)(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
+{
+    switch (a.d) {
+    case 3: return launch_d<3>(a, mr, s);
+    case 4: return launch_d<4>(a, mr, s);
+    case 5: return launch_d<5>(a, mr, s);
+    default: return false;
+    }
+}
+
+}  // namespace fkt

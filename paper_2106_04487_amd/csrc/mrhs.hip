@@ -41,6 +41,47 @@ __global__ __launch_bounds__(256) void k_mr_gather(int npad, const int* __restri
     for (int c = 0; c < kMrCols; ++c) XT[(size_t)c * npad + p] = (TC)(xr ? xr[c] : 0.f);
 }
 
+// B fragments of the moments: for node slot s, k-step t (32 entries) and
+// column tile ct, lane l holds entries k = 32 t + 8 (l / 16) + q, q < 8, of
+// column 16 ct + l % 16, split into bf16 high and low parts (0 past rank)
+__global__ __launch_bounds__(256) void k_mom_frag(int nslots, int R, int KS, const float* __restrict__ mom,
+                                                  bf8* __restrict__ bhi, bf8* __restrict__ blo)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)nslots * KS * 2 * kWave;
+    if (g >= total) return;
+    const int lane = (int)(g % kWave);
+    const int ct = (int)((g / kWave) % 2);
+    const int t = (int)((g / (2 * kWave)) % KS);
+    const int64_t sl = g / (2 * (int64_t)kWave * KS);
+    const int col = 16 * ct + (lane & 15);
+    const float* mc = mom + ((size_t)col * nslots + sl) * R;
+    bf8 h, l;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int k = 32 * t + 8 * (lane >> 4) + q;
+        const float v = k < R ? mc[k] : 0.f;
+        h[q] = (__bf16)v;
+        l[q] = (__bf16)(v - (float)h[q]);
+    }
+    bhi[g] = h;
+    blo[g] = l;
+}
+
+bool launch_m2t_mrhs(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
+{
+    switch (a.kind) {
+    case 0: return launch_m2t_mrhs_kind0(a, mr, s);
+    case 1: return launch_m2t_mrhs_kind1(a, mr, s);
+    case 2: return launch_m2t_mrhs_kind2(a, mr, s);
+    case 3: return launch_m2t_mrhs_kind3(a, mr, s);
+    case 4: return launch_m2t_mrhs_kind4(a, mr, s);
+    case 5: return launch_m2t_mrhs_kind5(a, mr, s);
+    case 6: return launch_m2t_mrhs_kind6(a, mr, s);
+    default: return false;
+    }
+}
+
 template <int D, int KIND, typename TC>
 __global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevMrhs mr, const TC* __restrict__ XT,
                                                      const float* __restrict__ zf, float* __restrict__ y, int nrhs,
@@ -181,12 +222,29 @@ hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, co
     TC* XT = (TC*)mr.xt;
     float* zf = (float*)mr.zf;
     for (int col0 = 0; col0 < nrhs; col0 += kMrCols) {
-        // far field of each column into zf[c] (the gather clears it)
-        for (int c = 0; c < kMrCols; ++c) {
-            DevWork w = wk;
-            w.zacc = zf + (size_t)c * a.n;
-            hipError_t e = launch_far_column(a, w, x, nrhs, col0 + c, 1, s);
-            if (e != hipSuccess) return e;
+        if (mr.mom && a.nslots > 0) {
+            // far field of the group on the matrix cores: moments of each
+            // column, B fragments, then one MFMA multipole-to-target pass that
+            // writes zf for all 32 columns
+            for (int c = 0; c < kMrCols; ++c) {
+                DevWork w = wk;
+                w.zacc = zf + (size_t)c * a.n;
+                w.mom = (float*)mr.mom + (size_t)c * a.nslots * a.rank;
+                hipError_t e = launch_s2m_column(a, w, x, nrhs, col0 + c, 1, s);
+                if (e != hipSuccess) return e;
+            }
+            const int64_t nf = (int64_t)a.nslots * mr.ks * 2 * kWave;
+            hipLaunchKernelGGL(k_mom_frag, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, a.nslots, a.rank,
+                               mr.ks, (const float*)mr.mom, (bf8*)mr.bhi, (bf8*)mr.blo);
+            if (!launch_m2t_mrhs(a, mr, s)) return hipErrorInvalidValue;
+        } else {
+            // far field of each column into zf[c] (the gather clears it)
+            for (int c = 0; c < kMrCols; ++c) {
+                DevWork w = wk;
+                w.zacc = zf + (size_t)c * a.n;
+                hipError_t e = launch_far_column(a, w, x, nrhs, col0 + c, 1, s);
+                if (e != hipSuccess) return e;
+            }
         }
         hipLaunchKernelGGL((k_mr_gather<TC>), dim3((mr.npad + 255) / 256), dim3(256), 0, s, mr.npad, mr.src, a.perm, x,
                            nrhs, col0, XT);

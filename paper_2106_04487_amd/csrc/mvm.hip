@@ -147,6 +147,24 @@ bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
 
 void near_consts_f32(const DevPlan& a, float& c0, float& c1) { near_consts<float>(a, c0, c1); }
 
+hipError_t launch_s2m_column(const DevPlan& a, const DevWork& wk, const void* xv, int nrhs, int col, int prec,
+                             hipStream_t s)
+{
+    if (prec != 1) return hipErrorInvalidValue;
+    const float* x = (const float*)xv;
+    float* src = (float*)wk.src;
+    float* zacc = (float*)wk.zacc;
+    const dim3 gg((a.n + 255) / 256), gb(256);
+    switch (a.d) {
+    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (a.nslots > 0 && !launch_s2m(a, wk, 1, s)) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* xv, int nrhs, int col, int prec,
                              hipStream_t s)
 {
