@@ -90,7 +90,8 @@ def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmu
 def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM
     on the d = 4 mixture: no preconditioner, block-Jacobi, and the learned
-    per-leaf spectral filter after train_steps Adam steps (batch 8)."""
+    per-leaf spectral filter after train_steps Adam steps (batch 8), judged by
+    block-Jacobi on 200 CG iterations (reverted to block-Jacobi if worse)."""
     spec = W.WORKLOADS["gmm4_n200k_gp"]
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
     y = W.gp_targets(X, spec["lengthscale"], spec["sigma2"], spec["nfeat"], spec["rhs_seed"])
@@ -126,12 +127,12 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     F.fkt_learn_params(plan, sig2)  # leaf spectra (host eigendecompositions)
     spectra_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    l0, l1 = F.fkt_learn_train(plan, sig2, steps=train_steps, batch=8, lr=3e-3, seed=1)
+    l0, l1, accepted = F.fkt_learn_train(plan, sig2, steps=train_steps, batch=8, lr=3e-3, seed=1, judge_iters=200)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     solve("learned", "learned")
     out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
-                           "train_loss_first": l0, "train_loss_last": l1})
+                           "train_loss_first": l0, "train_loss_last": l1, "kept_after_block_jacobi_judge": accepted})
     plan.close()
     return out
 

@@ -274,9 +274,14 @@ fkt_status fkt_learn_loss_grad(fkt_plan_t p, double sigma2, const double *v, int
  * batch of `batch` Gaussian vectors drawn on the device (SplitMix64 counter
  * hash + Box-Muller, keyed by seed and step). loss_first / loss_last (host,
  * may be NULL) receive the loss of the first and of the last step's batch
- * (before that step's update). Synchronises the plan's stream. */
+ * (before that step's update). With judge_iters > 0, block-Jacobi judges the
+ * result: judge_iters CG iterations on one Gaussian right-hand side with each
+ * preconditioner, and if the learned filter ends with the larger residual its
+ * last layer is zeroed (the filter is then block-Jacobi exactly); accepted
+ * (host, may be NULL) receives 1 if the trained weights were kept, else 0.
+ * Synchronises the plan's stream. */
 fkt_status fkt_learn_train(fkt_plan_t p, double sigma2, int steps, int batch, double lr, uint64_t seed,
-                           double *loss_first, double *loss_last);
+                           double *loss_first, double *loss_last, int judge_iters, int *accepted);
 
 #ifdef __cplusplus
 }

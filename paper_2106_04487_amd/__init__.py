@@ -107,7 +107,8 @@ _lib.fkt_learn_loss_grad.restype = ctypes.c_int
 _lib.fkt_learn_loss_grad.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]
 _lib.fkt_learn_train.restype = ctypes.c_int
 _lib.fkt_learn_train.argtypes = [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
-                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)]
 
 
 def _check(status: int):
@@ -396,14 +397,17 @@ def fkt_learn_loss_grad(plan: Plan, sigma2: float, v):
     return loss.value, grad
 
 
-def fkt_learn_train(plan: Plan, sigma2: float, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 1):
-    """Adam steps on device-drawn Gaussian batches; returns (loss of the
-    first step, loss of the last step)."""
+def fkt_learn_train(plan: Plan, sigma2: float, steps: int, batch: int = 8, lr: float = 1e-3, seed: int = 1,
+                    judge_iters: int = 0):
+    """Adam steps on device-drawn Gaussian batches; with judge_iters > 0
+    block-Jacobi judges the result (see fkt.h). Returns (loss of the first
+    step, loss of the last step, accepted)."""
     l0 = ctypes.c_double(float("nan"))
     l1 = ctypes.c_double(float("nan"))
+    acc = ctypes.c_int(1)
     _check(_lib.fkt_learn_train(plan.handle, float(sigma2), int(steps), int(batch), float(lr), int(seed),
-                                ctypes.byref(l0), ctypes.byref(l1)))
-    return l0.value, l1.value
+                                ctypes.byref(l0), ctypes.byref(l1), int(judge_iters), ctypes.byref(acc)))
+    return l0.value, l1.value, bool(acc.value)
 
 
 def fkt_destroy(plan: Plan):

@@ -269,6 +269,20 @@ static fkt_status upload_plan(fkt_plan_t P)
         // bf16 high/low B fragments (rank padded to a multiple of 64)
         const int64_t ns = (int64_t)L.slot_node.size(), R = P->tab.rank;
         P->mr.ks = (int)((R + 63) / 64 * 2);
+        {
+            fkt::JobSet J;
+            fkt::pack_far_jobs(L, fkt::kMrJobNodes, J);
+            std::string err;
+            if (!fkt::check_jobs(L, J.job_off, J.job_noff, J.job_nodes, J.job_pairs, J.max_nodes, err))
+                return fail(FKT_EINVAL, "internal error: " + err);
+#define FKT_UP3(vec, dst) \
+    if ((e = P->upload(vec, &dst)) != hipSuccess) return hip_fail(e, "many-RHS job upload")
+            FKT_UP3(J.job_off, P->mr.job_off);
+            FKT_UP3(J.job_noff, P->mr.job_noff);
+            FKT_UP3(J.job_nodes, P->mr.job_nodes);
+            FKT_UP3(J.job_pairs, P->mr.job_pairs);
+#undef FKT_UP3
+        }
         if (ns > 0) {
             if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * ns * R, &P->mr.mom)) != hipSuccess)
                 return hip_fail(e, "many-RHS moments");
@@ -614,17 +628,53 @@ fkt_status fkt_learn_loss_grad(fkt_plan_t P, double sigma2, const double* v, int
 }
 
 fkt_status fkt_learn_train(fkt_plan_t P, double sigma2, int steps, int batch, double lr, uint64_t seed,
-                           double* loss_first, double* loss_last)
+                           double* loss_first, double* loss_last, int judge_iters, int* accepted)
 {
     if (steps < 0) return fail(FKT_EINVAL, "steps must be >= 0");
     if (batch < 1 || batch > 64) return fail(FKT_EINVAL, "batch must be in [1, 64]");
     if (!(lr > 0.0) || !std::isfinite(lr)) return fail(FKT_EINVAL, "lr must be > 0");
+    if (judge_iters < 0) return fail(FKT_EINVAL, "judge_iters must be >= 0");
     DeviceScope ds(P ? P->opt.device : 0);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
     fkt_status st = learn_entry(P, sigma2);
     if (st != FKT_OK) return st;
     st = fkt::learn_train(P, P->learn, (int)P->opt.prec, sigma2, steps, batch, lr, seed, loss_first, loss_last);
-    return st == FKT_OK ? FKT_OK : fail(st, "learned preconditioner training");
+    if (st != FKT_OK) return fail(st, "learned preconditioner training");
+    if (accepted) *accepted = 1;
+    if (judge_iters == 0) return FKT_OK;
+    // block-Jacobi judges: judge_iters CG iterations on a Gaussian right-hand
+    // side with each preconditioner; if the learned filter ends with the
+    // larger residual, its last layer is zeroed, which is block-Jacobi exactly
+    const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
+    void *b = nullptr, *x = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&b, es * P->n)) != hipSuccess || (e = hipMalloc(&x, es * P->n)) != hipSuccess) {
+        if (b) (void)hipFree(b);
+        return hip_fail(e, "judge buffers");
+    }
+    double rr[2] = {0.0, 0.0};
+    if ((e = fkt::learn_randn(P->learn, b, P->n, P->opt.prec == FKT_F32, seed ^ 0x4A554447ull)) != hipSuccess)
+        st = hip_fail(e, "judge right-hand side");
+    for (int pc = 1; pc <= 2 && st == FKT_OK; ++pc) {
+        if ((e = hipMemsetAsync(x, 0, es * P->n, P->stream)) != hipSuccess) {
+            st = hip_fail(e, "judge initial guess");
+            break;
+        }
+        int it = 0;
+        const fkt_status s2 = fkt_cg_solve(P, sigma2, b, x, 1, 1e-300, judge_iters, pc, &it, &rr[pc - 1]);
+        if (s2 != FKT_OK && s2 != FKT_ENOTCONV) st = s2;
+    }
+    (void)hipFree(b);
+    (void)hipFree(x);
+    if (st != FKT_OK) return st;
+    if (!(rr[1] < rr[0])) {
+        std::vector<float> w(fkt::kLearnParams);
+        if ((e = fkt::learn_params(P->learn, w.data(), false)) != hipSuccess) return hip_fail(e, "judge reset");
+        for (int i = fkt::kLearnParams - fkt::kLearnHidden - 1; i < fkt::kLearnParams; ++i) w[i] = 0.f;
+        if ((e = fkt::learn_params(P->learn, w.data(), true)) != hipSuccess) return hip_fail(e, "judge reset");
+        if (accepted) *accepted = 0;
+    }
+    return FKT_OK;
 }
 
 struct fkt_graph_s {

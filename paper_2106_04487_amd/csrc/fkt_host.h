@@ -40,6 +40,17 @@ struct Tree {
     bool leaf(int64_t b) const { return kid0[b] < 0 && kid1[b] < 0; }
 };
 
+// Far pairs of the 64-target blocks packed into 64-lane jobs: every
+// (target, far node) pair of a block gets a lane; a job holds the pairs of at
+// most max_nodes nodes, lanes grouped by node.
+struct JobSet {
+    std::vector<int32_t> job_off;     // [nblocks + 1] jobs of each block
+    std::vector<int32_t> job_noff;    // [njobs + 1] into job_nodes
+    std::vector<int32_t> job_nodes;   // far-node slots of each job
+    std::vector<uint16_t> job_pairs;  // [njobs][64]: lane | node index << 6 (0xffff: empty)
+    int max_nodes = 0;
+};
+
 // Near/far interaction lists per 64-target block, with lane masks: bit i of
 // a mask is set when target (block begin + i) has that entry in its own
 // near or far set (paper eq. accparam, per target). The far lists drive the
@@ -85,9 +96,15 @@ void build_tree(const double* X, int64_t n, int d, int leaf_size, int max_depth,
 // of X), concatenated in instance order; no interaction crosses instances.
 void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int leaf_size, int max_depth, Tree& T);
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
+// pack L's far lists (far_off / far_slot / far_mask) into jobs
+void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J);
+
 void build_tables(int d, int p, Tables& tab);
 // Bounds of every index the kernels derive from the lists (false + err).
 bool check_lists(const Tree& T, const Lists& L, std::string& err);
+bool check_jobs(const Lists& L, const std::vector<int32_t>& job_off, const std::vector<int32_t>& job_noff,
+                const std::vector<int32_t>& job_nodes, const std::vector<uint16_t>& job_pairs, int max_nodes,
+                std::string& err);
 
 // K(r) for a kernel (K(0) = 0 for the singular 1/r), FP64, host side.
 double kernel_value(const fkt_kernel& k, double r);

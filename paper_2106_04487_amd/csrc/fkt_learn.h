@@ -25,6 +25,8 @@ void learn_destroy(LearnState* L);
 hipError_t learn_update_spectra(LearnState* L, const LeafSpectra& S);
 hipError_t learn_params(LearnState* L, float* host, bool set);
 hipError_t learn_grad(LearnState* L, float* host);
+// x (device, n, FP32 or FP64) <- N(0, 1) draws keyed by key; synchronises
+hipError_t learn_randn(LearnState* L, void* x, int64_t n, bool f32, uint64_t key);
 hipError_t learn_prepare_filter(LearnState* L);
 hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s);
 fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, const double* v, int B, double* loss);

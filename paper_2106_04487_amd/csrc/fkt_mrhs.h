@@ -11,7 +11,8 @@
 
 namespace fkt {
 
-constexpr int kMrCols = 32;  // columns per group
+constexpr int kMrCols = 32;      // columns per group
+constexpr int kMrJobNodes = 4;   // far nodes per 64-lane job of the matrix-core far field
 
 struct DevMrhs {
     int npad = 0;                     // leaves padded to multiples of 32 points
@@ -29,6 +30,10 @@ struct DevMrhs {
     void* bhi = nullptr;              // [nslots][ks][2][64] bf16 x 8 MFMA B fragments, high part
     void* blo = nullptr;              //   and low part (m - hi)
     int ks = 0;                       // 32-entry k-steps per node (rank padded to a multiple of 64)
+    const int* job_off = nullptr;     // far jobs per block with up to kMrJobNodes nodes (see Lists)
+    const int* job_noff = nullptr;
+    const int* job_nodes = nullptr;
+    const uint16_t* job_pairs = nullptr;
 };
 
 // far field of one column (gather clearing wk.zacc, s2m, m2t into wk.zacc)

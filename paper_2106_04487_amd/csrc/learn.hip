@@ -661,6 +661,21 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
     return FKT_OK;
 }
 
+hipError_t learn_randn(LearnState* L, void* x, int64_t n, bool f32, uint64_t key)
+{
+    double* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, sizeof(double) * (n ? n : 1));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_randn, dim3(blocks_of(n)), dim3(kT), 0, L->s, n, key, tmp);
+    if (f32)
+        hipLaunchKernelGGL((k_cvt<float>), dim3(blocks_of(n)), dim3(kT), 0, L->s, n, (const double*)tmp, (float*)x);
+    else
+        (void)hipMemcpyAsync(x, tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, L->s);
+    e = hipStreamSynchronize(L->s);
+    (void)hipFree(tmp);
+    return e;
+}
+
 hipError_t learn_grad(LearnState* L, float* host)
 {
     hipError_t e = hipStreamSynchronize(L->s);

@@ -5,8 +5,8 @@
 // product of the pair's basis vector b (entries Y_kh(r^) (s/|r|)^j F_kj(|r|),
 // the same factors as the one-column kernel) with the node's moments, so
 // for 32 columns it is a (pairs x rank) by (rank x 32) product. One wave owns
-// a 64-target block and walks its packed far jobs (64 pairs, <= MAXN nodes,
-// lanes grouped by node): each lane generates its pair's basis entries in
+// a 64-target block and walks its far jobs (64 pairs of up to kMrJobNodes
+// nodes, lanes grouped by node): each lane generates its pair's basis entries in
 // emission order and writes them, split into bf16 high and low parts, into
 // an LDS chunk laid out as MFMA A fragments; every 64 entries the chunk is
 // multiplied by each job node's moments (bf16 high/low B fragments prepared
@@ -34,13 +34,12 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int kKC = 64;  // basis entries per LDS chunk: two MFMA k-steps of 32
 
 template <int D, int P, int KIND>
-__global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const bf8* __restrict__ Bhi,
+__global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMrhs mr, const bf8* __restrict__ Bhi,
                                                     const bf8* __restrict__ Blo, int KS, float* __restrict__ zf)
 {
     constexpr int R = cbinom(P + D, D);
     constexpr int RP = (R + kKC - 1) / kKC * kKC;
     constexpr int NF = f_off(P, P + 1);
-    constexpr int MAXN = m2t_max_job_nodes(D, P, (int)sizeof(float));
     __shared__ bf8 Ahi[4][2][kWave];  // [row tile][k-step in chunk][fragment lane]
     __shared__ bf8 Alo[4][2][kWave];
     __shared__ float Zb[kWave][kMrCols + 1];
@@ -51,16 +50,13 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const bf8* 
 #pragma unroll
     for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
 
-    const int j0 = a.job_off[blk], j1 = a.job_off[blk + 1];
+    const int j0 = mr.job_off[blk], j1 = mr.job_off[blk + 1];
     for (int j = j0; j < j1; ++j) {
-        const int n0 = a.job_noff[j], nn = a.job_noff[j + 1] - n0;
-        const unsigned pw = a.job_pairs[(size_t)j * kWave + lane];
+        const int n0 = mr.job_noff[j], nn = mr.job_noff[j + 1] - n0;
+        const unsigned pw = mr.job_pairs[(size_t)j * kWave + lane];
         const bool valid = pw != 0xffffu;
         const int lt = pw & 63, ni = valid ? (int)(pw >> 6) : 0;
-        uint64_t nodemask[MAXN];
-#pragma unroll
-        for (int k = 0; k < MAXN; ++k) nodemask[k] = __ballot(valid && ni == k);
-        const int slot = a.job_nodes[n0 + ni];
+        const int slot = mr.job_nodes[n0 + ni];
         double txl[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) txl[i] = __shfl(tx[i], lt, kWave);
@@ -127,11 +123,10 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const bf8* 
         auto flush = [&](int kbase) {
             __syncthreads();
             const int ks0 = kbase / 32;
-#pragma unroll
-            for (int k = 0; k < MAXN; ++k) {
-                if (k >= nn) break;
-                const uint64_t nm = nodemask[k];
-                const int sl = a.job_nodes[n0 + k];
+#pragma unroll 1
+            for (int k = 0; k < nn; ++k) {
+                const uint64_t nm = __ballot(valid && ni == k);
+                const int sl = mr.job_nodes[n0 + k];
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     const size_t fb = ((size_t)sl * KS + ks0 + ks) * 2 * kWave;
@@ -156,16 +151,18 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const bf8* 
             __syncthreads();
         };
         // entry idx of this lane's row goes to fragment lane (lane % 16) + 16 g,
-        // element q, of row tile lane / 16, with g = (idx % 32) / 8, q = idx % 8
-        __bf16* hrow = (__bf16*)&Ahi[lane >> 4][0][0];
-        __bf16* lrow = (__bf16*)&Alo[lane >> 4][0][0];
+        // element q, of row tile lane / 16, with g = (idx % 32) / 8, q = idx % 8;
+        // eight consecutive entries are collected and stored as one vector
+        bf8 hv, lv;
         auto put = [&](int idx, float bv) {
             const int c = idx % kKC, ks = c / 32, g = (c % 32) / 8, q = c % 8;
             const __bf16 h = (__bf16)bv;
-            const __bf16 l = (__bf16)(bv - (float)h);
-            const int o = (ks * kWave + r16 + 16 * g) * 8 + q;
-            hrow[o] = h;
-            lrow[o] = l;
+            hv[q] = h;
+            lv[q] = (__bf16)(bv - (float)h);
+            if (q == 7) {
+                Ahi[lane >> 4][ks][r16 + 16 * g] = hv;
+                Alo[lane >> 4][ks][r16 + 16 * g] = lv;
+            }
             if (c == kKC - 1) flush(idx - (kKC - 1));
         };
         int off = 0;
@@ -210,7 +207,7 @@ bool launch_d(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
         return false;
     } else {
         if (a.p == P) {
-            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks), dim3(kWave), 0, s, a,
+            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks), dim3(kWave), 0, s, a, mr,
                                (const bf8*)mr.bhi, (const bf8*)mr.blo, mr.ks, (float*)mr.zf);
             return true;
         }

@@ -223,6 +223,45 @@ void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int
 
 // ------------------------------------------------------------- partition
 
+// Pack each block's far pairs into jobs of 64 lanes, in list order (so a
+// node's lanes are adjacent), starting a new job when 64 pairs or max_nodes
+// distinct nodes are reached.
+void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J)
+{
+    const int64_t nb = (int64_t)L.blk_begin.size();
+    J = JobSet();
+    J.max_nodes = max_nodes;
+    J.job_off.assign(nb + 1, 0);
+    J.job_noff.assign(1, 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        int in_job = kBlock, nodes_in_job = max_nodes;  // forces a new job
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) {
+            uint64_t m = L.far_mask[e];
+            bool node_open = false;
+            while (m) {
+                if (in_job == kBlock || (!node_open && nodes_in_job == max_nodes)) {
+                    J.job_pairs.resize(J.job_pairs.size() + kBlock, (uint16_t)0xffff);
+                    J.job_noff.push_back(J.job_noff.back());
+                    in_job = 0;
+                    nodes_in_job = 0;
+                    node_open = false;
+                }
+                if (!node_open) {
+                    J.job_nodes.push_back(L.far_slot[e]);
+                    J.job_noff.back() += 1;
+                    ++nodes_in_job;
+                    node_open = true;
+                }
+                const int lane = __builtin_ctzll(m);
+                m &= m - 1;
+                J.job_pairs[J.job_pairs.size() - kBlock + in_job] = (uint16_t)(lane | ((nodes_in_job - 1) << 6));
+                ++in_job;
+            }
+        }
+        J.job_off[q + 1] = (int32_t)(J.job_noff.size() - 1);
+    }
+}
+
 namespace {
 struct BlockLists {
     std::vector<int32_t> near_node, far_node;
@@ -324,38 +363,14 @@ void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_p
         }
     }
 
-    // Pack each block's far pairs into jobs of 64 lanes, in list order (so a
-    // node's lanes are adjacent), starting a new job when 64 pairs or
-    // max_job_nodes distinct nodes are reached.
-    L.max_job_nodes = max_job_nodes;
-    L.job_off.assign(nb + 1, 0);
-    L.job_noff.assign(1, 0);
-    for (int64_t q = 0; q < nb; ++q) {
-        int in_job = kBlock, nodes_in_job = max_job_nodes;  // forces a new job
-        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) {
-            uint64_t m = L.far_mask[e];
-            bool node_open = false;
-            while (m) {
-                if (in_job == kBlock || (!node_open && nodes_in_job == max_job_nodes)) {
-                    L.job_pairs.resize(L.job_pairs.size() + kBlock, (uint16_t)0xffff);
-                    L.job_noff.push_back(L.job_noff.back());
-                    in_job = 0;
-                    nodes_in_job = 0;
-                    node_open = false;
-                }
-                if (!node_open) {
-                    L.job_nodes.push_back(L.far_slot[e]);
-                    L.job_noff.back() += 1;
-                    ++nodes_in_job;
-                    node_open = true;
-                }
-                const int lane = __builtin_ctzll(m);
-                m &= m - 1;
-                L.job_pairs[L.job_pairs.size() - kBlock + in_job] = (uint16_t)(lane | ((nodes_in_job - 1) << 6));
-                ++in_job;
-            }
-        }
-        L.job_off[q + 1] = (int32_t)(L.job_noff.size() - 1);
+    {
+        JobSet J;
+        pack_far_jobs(L, max_job_nodes, J);
+        L.max_job_nodes = max_job_nodes;
+        L.job_off = std::move(J.job_off);
+        L.job_noff = std::move(J.job_noff);
+        L.job_nodes = std::move(J.job_nodes);
+        L.job_pairs = std::move(J.job_pairs);
     }
     far_lane = (int64_t)(L.job_noff.size() - 1) * kBlock;
 
@@ -588,7 +603,6 @@ bool build_block_jacobi(const Tree& T, const fkt_kernel& k, double sigma2, std::
 bool check_lists(const Tree& T, const Lists& L, std::string& err)
 {
     const int64_t n = T.n, nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
-    const int64_t njobs = (int64_t)L.job_noff.size() - 1;
     auto bad = [&](const std::string& what, int64_t i) {
         err = "plan check: " + what + " at " + std::to_string(i);
         return false;
@@ -617,27 +631,7 @@ bool check_lists(const Tree& T, const Lists& L, std::string& err)
     for (size_t e = 0; e < L.near_beg.size(); ++e)
         if (L.near_beg[e] < 0 || L.near_beg[e] > L.near_end[e] || L.near_end[e] > n) return bad("near entry", (int64_t)e);
     // far-field jobs
-    if ((int64_t)L.job_off.size() != nb + 1 || L.job_off[0] != 0 || L.job_off[nb] != njobs)
-        return bad("job offsets", 0);
-    if (L.job_noff[0] != 0 || L.job_noff[njobs] != (int64_t)L.job_nodes.size() ||
-        (int64_t)L.job_pairs.size() != njobs * kBlock)
-        return bad("job arrays", 0);
-    for (int64_t q = 0; q < nb; ++q) {
-        if (L.job_off[q + 1] < L.job_off[q]) return bad("job offsets", q);
-        for (int64_t j = L.job_off[q]; j < L.job_off[q + 1]; ++j) {
-            const int nn = L.job_noff[j + 1] - L.job_noff[j];
-            if (nn < 1 || nn > L.max_job_nodes) return bad("job node count", j);
-            for (int k = 0; k < nn; ++k) {
-                const int32_t sl = L.job_nodes[L.job_noff[j] + k];
-                if (sl < 0 || sl >= ns) return bad("job node slot", j);
-            }
-            for (int lane = 0; lane < kBlock; ++lane) {
-                const uint16_t pw = L.job_pairs[(size_t)j * kBlock + lane];
-                if (pw == 0xffffu) continue;
-                if ((pw & 63) >= L.blk_count[q] || (pw >> 6) >= nn) return bad("job pair", j);
-            }
-        }
-    }
+    if (!check_jobs(L, L.job_off, L.job_noff, L.job_nodes, L.job_pairs, L.max_job_nodes, err)) return false;
     if ((int64_t)L.slot_ctr.size() != ns * T.d || (int64_t)L.slot_scale.size() != ns) return bad("slot arrays", 0);
     // s2m units and partial sums
     for (size_t u = 0; u < L.unit_slot.size(); ++u) {
@@ -651,6 +645,50 @@ bool check_lists(const Tree& T, const Lists& L, std::string& err)
     if (L.red_off.size() != L.red_slot.size() + 1 || L.red_off.back() != L.npartials) return bad("partial lists", 0);
     for (size_t r = 0; r < L.red_slot.size(); ++r)
         if (L.red_slot[r] < 0 || L.red_slot[r] >= ns || L.red_off[r + 1] < L.red_off[r]) return bad("partial list", (int64_t)r);
+    return true;
+}
+
+bool check_jobs(const Lists& L, const std::vector<int32_t>& job_off, const std::vector<int32_t>& job_noff,
+                const std::vector<int32_t>& job_nodes, const std::vector<uint16_t>& job_pairs, int max_nodes,
+                std::string& err)
+{
+    const int64_t nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
+    const int64_t njobs = (int64_t)job_noff.size() - 1;
+    struct {
+        const std::vector<int32_t>& job_off;
+        const std::vector<int32_t>& job_noff;
+        const std::vector<int32_t>& job_nodes;
+        const std::vector<uint16_t>& job_pairs;
+        int max_nodes;
+    } J{job_off, job_noff, job_nodes, job_pairs, max_nodes};
+    auto bad = [&](const std::string& what, int64_t i) {
+        err = "plan check: " + what + " at " + std::to_string(i);
+        return false;
+    };
+    if ((int64_t)J.job_off.size() != nb + 1 || J.job_off[0] != 0 || J.job_off[nb] != njobs)
+        return bad("job offsets", 0);
+    if (J.job_noff[0] != 0 || J.job_noff[njobs] != (int64_t)J.job_nodes.size() ||
+        (int64_t)J.job_pairs.size() != njobs * kBlock)
+        return bad("job arrays", 0);
+    for (int64_t q = 0; q < nb; ++q) {
+        if (J.job_off[q + 1] < J.job_off[q]) return bad("job offsets", q);
+        for (int64_t j = J.job_off[q]; j < J.job_off[q + 1]; ++j) {
+            const int nn = J.job_noff[j + 1] - J.job_noff[j];
+            if (nn < 1 || nn > J.max_nodes) return bad("job node count", j);
+            for (int k = 0; k < nn; ++k) {
+                const int32_t sl = J.job_nodes[J.job_noff[j] + k];
+                if (sl < 0 || sl >= ns) return bad("job node slot", j);
+            }
+            int prev = 0;
+            for (int lane = 0; lane < kBlock; ++lane) {
+                const uint16_t pw = J.job_pairs[(size_t)j * kBlock + lane];
+                if (pw == 0xffffu) continue;
+                if ((pw & 63) >= L.blk_count[q] || (pw >> 6) >= nn || (int)(pw >> 6) < prev)
+                    return bad("job pair", j);
+                prev = pw >> 6;  // lanes grouped by node, in node order
+            }
+        }
+    }
     return true;
 }
 

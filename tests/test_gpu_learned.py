@@ -85,9 +85,34 @@ def test_training_lowers_loss_and_cg_iterations(F):
     its = {}
     _, its["none"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="none")
     _, its["block_jacobi"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="block_jacobi")
-    l0, l1 = F.fkt_learn_train(plan, sig2, steps=40, batch=8, lr=3e-3, seed=7)
+    l0, l1, _ = F.fkt_learn_train(plan, sig2, steps=40, batch=8, lr=3e-3, seed=7)
     _, its["learned"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond="learned")
     print(f"training loss {l0:.4f} -> {l1:.4f}; CG iterations {its}")
     assert l1 < l0
     assert its["learned"] < its["none"]
+    plan.close()
+
+
+def test_block_jacobi_judges_the_trained_filter(F):
+    """With the judge on, the kept filter is never worse than block-Jacobi on
+    the judge's run; if it was rejected, the filter is block-Jacobi exactly."""
+    import torch
+    n, sig2 = 6000, 1e-2
+    X = _gp_points(n, 68)
+    plan = F.fkt_plan(X, "matern52", 128, 5, theta=0.4, lengthscale=0.3)
+    # a large step size makes a poor filter likely; the judge must catch it
+    l0, l1, accepted = F.fkt_learn_train(plan, sig2, steps=30, batch=4, lr=3e-2, seed=9, judge_iters=60)
+    p = LR.unpack(F.fkt_learn_params(plan, sig2).astype(np.float64))
+    b = torch.as_tensor(W.normal_rhs(n, 1, 69)[:, 0], device="cuda")
+    res = {}
+    for pc in ("block_jacobi", "learned"):
+        try:
+            _, it, rr = F.fkt_cg_solve(plan, sig2, b, rtol=1e-30, maxit=60, precond=pc)
+        except F.FktError as e:
+            it, rr = e.iters, e.relres
+        res[pc] = rr
+    print(f"judge: accepted {accepted}, loss {l0:.3f} -> {l1:.3f}, 60-iteration residuals {res}")
+    if not accepted:
+        assert np.all(p["w3"] == 0.0) and p["b3"] == 0.0
+        assert abs(res["learned"] - res["block_jacobi"]) <= 1e-6 * res["block_jacobi"] + 1e-300
     plan.close()
