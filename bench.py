@@ -146,7 +146,7 @@ def _sync_time(torch, fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
-def batch_leg(F, torch, reps, theta, err_per_inst):
+def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
     """Batched uneven instances: 256 sets in d = 3 with log-uniform sizes in
     [1e3, 1e5], rational quadratic kernel, 4 RHS, FP32: one forest plan
     (eager launches and one HIP graph) against per-instance plans and
@@ -159,11 +159,13 @@ def batch_leg(F, torch, reps, theta, err_per_inst):
     x64 = W.normal_rhs(n, spec["nrhs"], spec["rhs_seed"])
     kw = dict(lengthscale=spec["lengthscale"], alpha=spec["alpha"])
     p = spec["order"]
-    t0 = time.perf_counter()
-    leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [64, 128, 256, 512], nrhs=spec["nrhs"], reps=2,
-                                     theta=theta, prec="f32", batch=True, **kw)
-    tune_s = time.perf_counter() - t0
-    print(f"bench: batch autotune {tune} -> leaf {leaf} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    tune = None
+    if leaf <= 0:
+        t0 = time.perf_counter()
+        leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [64, 128, 256, 512], nrhs=spec["nrhs"],
+                                         reps=2, theta=theta, prec="f32", batch=True, **kw)
+        tune_s = time.perf_counter() - t0
+        print(f"bench: batch autotune {tune} -> leaf {leaf} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
     x = torch.as_tensor(x64, dtype=torch.float32, device="cuda").contiguous()
     y = torch.empty_like(x)
     t0 = time.perf_counter()
@@ -178,20 +180,22 @@ def batch_leg(F, torch, reps, theta, err_per_inst):
     g.close()
     plan.close()
     # per-instance plans, one fkt_mvm each
-    t0 = time.perf_counter()
-    plans = [F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
-             for i in range(len(sizes))]
-    plans_s = time.perf_counter() - t0
-    xs = [x[off[i]:off[i + 1]] for i in range(len(sizes))]
-    ys = [y[off[i]:off[i + 1]] for i in range(len(sizes))]
+    per_ms = plans_s = None
+    if per_instance:
+        t0 = time.perf_counter()
+        plans = [F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
+                 for i in range(len(sizes))]
+        plans_s = time.perf_counter() - t0
+        xs = [x[off[i]:off[i + 1]] for i in range(len(sizes))]
+        ys = [y[off[i]:off[i + 1]] for i in range(len(sizes))]
 
-    def per_instance():
-        for q, xi, yi in zip(plans, xs, ys):
-            F.fkt_mvm(q, xi, yi)
-    per_instance()
-    per_ms = _sync_time(torch, per_instance, reps)
-    for q in plans:
-        q.close()
+        def per_instance_mvms():
+            for q, xi, yi in zip(plans, xs, ys):
+                F.fkt_mvm(q, xi, yi)
+        per_instance_mvms()
+        per_ms = _sync_time(torch, per_instance_mvms, reps)
+        for q in plans:
+            q.close()
     # error against the dense FP64 sum on sampled targets of a few instances
     errs = []
     for i in W.subsample(len(sizes), 8, 3005):
@@ -204,15 +208,19 @@ def batch_leg(F, torch, reps, theta, err_per_inst):
            "size_min": int(sizes.min()), "size_max": int(sizes.max()), "nrhs": spec["nrhs"], "dtype": "f32",
            "theta": theta, "p": p, "leaf": leaf, "autotune_ms": tune, "batched_graph_ms": graph_ms,
            "batched_eager_ms": eager_ms, "per_instance_ms": per_ms,
-           "batched_graph_mpoints_per_s": n / graph_ms / 1e3, "speedup_graph_vs_per_instance": per_ms / graph_ms,
+           "batched_graph_mpoints_per_s": n / graph_ms / 1e3,
+           "speedup_graph_vs_per_instance": per_ms / graph_ms if per_ms else None,
            "plan_seconds_batched": plan_s, "plan_seconds_per_instance_total": plans_s,
            "rel_err_vs_dense_max_of_8_instances": max(errs)}
     print(f"bench: batch {len(sizes)} instances n={n}: graph {graph_ms:.2f} ms, eager {eager_ms:.2f} ms, "
-          f"per-instance {per_ms:.2f} ms; err {max(errs):.2e}", file=sys.stderr, flush=True)
+          f"per-instance {per_ms} ms; err {max(errs):.2e}", file=sys.stderr, flush=True)
     return out
 
 
-def mrhs_leg(F, torch, reps, theta, err_targets):
+MRHS_MODES = {"columns_f32": None, "mfma_f32": "f32", "mfma_bf16": "bf16"}
+
+
+def mrhs_leg(F, torch, reps, theta, err_targets, modes=tuple(MRHS_MODES)):
     """Mixed precision, many RHS: 500k points of a 10-component mixture in
     d = 5, Gaussian length scale 0.2, p = 8, 32 RHS, FP32 plan: column by
     column against the matrix-core near field in FP32 and in bf16."""
@@ -222,18 +230,22 @@ def mrhs_leg(F, torch, reps, theta, err_targets):
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
     x64 = W.normal_rhs(n, spec["nrhs"], spec["rhs_seed"])
     x = torch.as_tensor(x64, dtype=torch.float32, device="cuda").contiguous()
-    tg = W.subsample(n, err_targets, 3007)
-    zd = oracle.dense_mvm(X, x64, spec["kernel"], targets=tg, lengthscale=spec["lengthscale"])
+    tg = W.subsample(n, err_targets, 3007) if err_targets > 0 else None
+    zd = oracle.dense_mvm(X, x64, spec["kernel"], targets=tg, lengthscale=spec["lengthscale"]) if tg is not None \
+        else None
     out = {"workload": f"gmm5_n{n}_gauss_32rhs", "n": n, "d": 5, "p": spec["order"], "theta": theta, "nrhs": 32}
-    for name, mr in (("columns_f32", None), ("mfma_f32", "f32"), ("mfma_bf16", "bf16")):
+    for name in modes:
+        mr = MRHS_MODES[name]
         plan = F.fkt_plan(X, spec["kernel"], 256, spec["order"], theta=theta, prec="f32", mrhs=mr,
                           lengthscale=spec["lengthscale"])
         y = F.fkt_mvm(plan, x)
         ms = _sync_time(torch, lambda: F.fkt_mvm(plan, x, y), reps)
-        z = y.double().cpu().numpy()[tg]
-        err = float(np.linalg.norm(z - zd) / np.linalg.norm(zd))
+        err = None
+        if zd is not None:
+            z = y.double().cpu().numpy()[tg]
+            err = float(np.linalg.norm(z - zd) / np.linalg.norm(zd))
         out[name] = {"ms_per_mvm_32rhs": ms, "mpoints_rhs_per_s": n * 32 / ms / 1e3, "rel_err_vs_dense_fp64": err}
-        print(f"bench: mrhs {name}: {ms:.1f} ms per 32-column MVM, err {err:.2e}", file=sys.stderr, flush=True)
+        print(f"bench: mrhs {name}: {ms:.1f} ms per 32-column MVM, err {err}", file=sys.stderr, flush=True)
         plan.close()
     return out
 
@@ -260,8 +272,13 @@ def main():
                     help="points of the GP solves (the d = 4 mixture workload at 200k takes minutes); 0 skips them")
     ap.add_argument("--gp-maxit", type=int, default=3000)
     ap.add_argument("--gp-train-steps", type=int, default=100)
-    ap.add_argument("--batch-theta", type=float, default=0.35)
+    ap.add_argument("--batch-theta", type=float, default=0.3)
+    ap.add_argument("--batch-leaf", type=int, default=0, help="0: the library's autotuner picks it")
+    ap.add_argument("--batch-no-per-instance", action="store_true")
     ap.add_argument("--mrhs-theta", type=float, default=0.4)
+    ap.add_argument("--mrhs-modes", default=",".join(MRHS_MODES))
+    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp"],
+                    help="run one secondary leg alone and print its JSON (the default runs the headline line)")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -271,6 +288,17 @@ def main():
 
     import torch
     import paper_2106_04487_amd as F
+
+    if a.leg != "all":
+        if a.leg == "many_rhs":
+            out = mrhs_leg(F, torch, a.steps, a.mrhs_theta, a.err_targets, tuple(a.mrhs_modes.split(",")))
+        elif a.leg == "batched":
+            out = batch_leg(F, torch, a.steps, a.batch_theta, max(a.err_targets // 10, 20), a.batch_leaf,
+                            not a.batch_no_per_instance)
+        else:
+            out = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
+        print(json.dumps(out))
+        return
 
     X = W.uniform_cube(a.n, 3, 1002)
     x64 = W.normal_rhs(a.n, 1, 2002)[:, 0]
@@ -306,8 +334,9 @@ def main():
 
     batch = mrhs = None
     if not a.no_variants:
-        batch = batch_leg(F, torch, 3, a.batch_theta, min(200, max(a.err_targets // 10, 50)))
-        mrhs = mrhs_leg(F, torch, 2, a.mrhs_theta, min(a.err_targets, 500))
+        batch = batch_leg(F, torch, 3, a.batch_theta, min(200, max(a.err_targets // 10, 50)), a.batch_leaf,
+                          not a.batch_no_per_instance)
+        mrhs = mrhs_leg(F, torch, 2, a.mrhs_theta, min(a.err_targets, 500), tuple(a.mrhs_modes.split(",")))
 
     cpu = None
     if a.cpu_seconds > 0:
