@@ -253,20 +253,21 @@ __device__ __forceinline__ double exp_nonpos(double x)
 // |f| <= ln2/512, so e^x = 2^(n >> 8) 2^((n & 255)/256) e^f, with e^f by its
 // Taylor polynomial to degree 4 (truncation < 4e-17 relative). n is read from
 // the low word of x 256/ln2 + 1.5 2^52, whose rounding is the rounding of n.
-// x is clamped at -1100, where e^x is already zero in FP64.
+// f takes one FMA with ln2/256 rounded to FP64: its error, at most
+// |n| 2^-62 <= 369 |x| 2^-62, changes e^x by a relative 8e-17 |x|, i.e. by at
+// most 8e-17 e^x |x| <= 3e-17 absolute. x is clamped at -1100, where e^x is
+// already zero in FP64.
 constexpr int kExpTabLen = 256;
 __device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab)
 {
     constexpr double kShift = 6755399441055744.0;               // 1.5 * 2^52
     constexpr double kInvL = 369.3299304675746;                 // 256 / ln2
-    constexpr double kLHi = 0x1.62e42ff000000p-9;               // ln2/256 to 32 bits: k * kLHi exact
-    constexpr double kLLo = -1.6409824502660487e-13;            // ln2/256 - kLHi
+    constexpr double kL = 0x1.62e42ff000000p-9 + -1.6409824502660487e-13;  // ln2/256 to FP64
     x = fmax(x, -1100.0);
     const double kn = fma(x, kInvL, kShift);
     const int n = __double2loint(kn);
     const double k = kn - kShift;
-    double f = fma(k, -kLHi, x);
-    f = fma(k, -kLLo, f);
+    const double f = fma(k, -kL, x);
     double q = fma(f, 4.16666666666666666667e-02, 1.66666666666666666667e-01);
     q = fma(q, f, 0.5);
     q = fma(q, f, 1.0);
