@@ -8,7 +8,7 @@
 // a 64-target block and walks its far jobs (64 pairs of up to kMrJobNodes
 // nodes, lanes grouped by node): each lane generates its pair's basis entries in
 // emission order and writes them, split into bf16 high and low parts, into
-// an LDS chunk laid out as MFMA A fragments; every 64 entries the chunk is
+// an LDS chunk laid out as MFMA A fragments; every 32 entries the chunk is
 // multiplied by each job node's moments (bf16 high/low B fragments prepared
 // once per group) with v_mfma_f32_16x16x32_bf16, three products per tile
 // (hi*hi + hi*lo + lo*hi: about 16 bits of mantissa), rows of other nodes
@@ -31,7 +31,8 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int kKC = 64;  // basis entries per LDS chunk: two MFMA k-steps of 32
+constexpr int kKC = 32;         // basis entries per LDS chunk (16 KB of LDS with the sums)
+constexpr int kKS = kKC / 32;    // MFMA k-steps of 32 per chunk
 
 template <int D, int P, int KIND>
 __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMrhs mr, const bf8* __restrict__ Bhi,
@@ -40,8 +41,8 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
     constexpr int R = cbinom(P + D, D);
     constexpr int RP = (R + kKC - 1) / kKC * kKC;
     constexpr int NF = f_off(P, P + 1);
-    __shared__ bf8 Ahi[4][2][kWave];  // [row tile][k-step in chunk][fragment lane]
-    __shared__ bf8 Alo[4][2][kWave];
+    __shared__ bf8 Ahi[4][kKS][kWave];  // [row tile][k-step in chunk][fragment lane]
+    __shared__ bf8 Alo[4][kKS][kWave];
     __shared__ float Zb[kWave][kMrCols + 1];
     const int blk = blockIdx.x, lane = threadIdx.x, r16 = lane & 15;
     const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
@@ -56,7 +57,9 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
         const unsigned pw = mr.job_pairs[(size_t)j * kWave + lane];
         const bool valid = pw != 0xffffu;
         const int lt = pw & 63, ni = valid ? (int)(pw >> 6) : 0;
-        const int slot = mr.job_nodes[n0 + ni];
+        // lane k < nn holds the slot of job node k, read back with readlane
+        const int jslot = mr.job_nodes[n0 + min(lane, nn - 1)];
+        const int slot = __shfl(jslot, ni, kWave);
         double txl[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) txl[i] = __shfl(tx[i], lt, kWave);
@@ -119,16 +122,16 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
-        // contract the chunk holding entries [kbase, kbase + 64) with every node
+        // contract the chunk holding entries [kbase, kbase + kKC) with every node
         auto flush = [&](int kbase) {
             __syncthreads();
             const int ks0 = kbase / 32;
 #pragma unroll 1
             for (int k = 0; k < nn; ++k) {
                 const uint64_t nm = __ballot(valid && ni == k);
-                const int sl = mr.job_nodes[n0 + k];
+                const int sl = __builtin_amdgcn_readlane(jslot, k);
 #pragma unroll
-                for (int ks = 0; ks < 2; ++ks) {
+                for (int ks = 0; ks < kKS; ++ks) {
                     const size_t fb = ((size_t)sl * KS + ks0 + ks) * 2 * kWave;
                     const bf8 bh0 = Bhi[fb + lane], bh1 = Bhi[fb + kWave + lane];
                     const bf8 bl0 = Blo[fb + lane], bl1 = Blo[fb + kWave + lane];
