@@ -131,6 +131,7 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     solve("learned", "learned")
+    out["learned"]["fallback_to_block_jacobi_at"] = plan.info()["cg_fallback_iter"]
     out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
                            "train_loss_first": l0, "train_loss_last": l1, "kept_after_block_jacobi_judge": accepted})
     plan.close()

@@ -140,7 +140,13 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  *   maxit     iteration cap, >= 1.
  *   precond   0 none, 1 block-Jacobi (per-leaf dense Cholesky of
  *             K_ll + sigma2 I), 2 the learned per-leaf spectral filter
- *             (fkt_learn_*, current weights; block-Jacobi until trained).
+ *             (fkt_learn_*, current weights; block-Jacobi while its output
+ *             layer is zero: initially, or after the judge rejected a filter).
+ *             With a trained filter, block-Jacobi is also the fallback: once the residual
+ *             exceeds 10 times its best so far, or sets no new best for 250
+ *             iterations, CG restarts from the best iterate with block-Jacobi
+ *             (one extra fkt_mvm; iterations keep counting; the switch is
+ *             reported in fkt_plan_stats.cg_fallback_iter).
  *   iters     host, receives the iteration count (may be NULL).
  *   relres    host, receives max over columns of the final relative
  *             residual (may be NULL).
@@ -173,6 +179,9 @@ typedef struct {
     int64_t far_lane_pairs;   /* expansions incl. masked-off lanes             */
     int64_t s2m_terms;        /* sum_b |b| over nodes with far sets            */
     double plan_seconds;      /* host wall time of fkt_plan                    */
+    int64_t cg_fallback_iter; /* iteration at which the last fkt_cg_solve fell
+                                 back from the learned filter to block-Jacobi,
+                                 -1 if it did not (or no solve has run)        */
 } fkt_plan_stats;
 
 fkt_status fkt_plan_info(fkt_plan_t p, fkt_plan_stats *s);

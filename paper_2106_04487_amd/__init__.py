@@ -64,7 +64,8 @@ _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes
 
 
 class _Stats(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int64) for f in _STAT_FIELDS] + [("plan_seconds", ctypes.c_double)]
+    _fields_ = [(f, ctypes.c_int64) for f in _STAT_FIELDS] + [("plan_seconds", ctypes.c_double),
+                                                               ("cg_fallback_iter", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -149,6 +150,7 @@ class Plan:
         _check(_lib.fkt_plan_info(self.handle, ctypes.byref(s)))
         out = {f: int(getattr(s, f)) for f in _STAT_FIELDS}
         out["plan_seconds"] = float(s.plan_seconds)
+        out["cg_fallback_iter"] = int(s.cg_fallback_iter)
         return out
 
     def perm(self) -> np.ndarray:

@@ -134,20 +134,29 @@ fkt_status cg_set_error(fkt_status st, const std::string& msg);
 
 namespace fkt {
 
+// Safeguard of the learned preconditioner (when fallback_at is given): PCG
+// with it falls back to block-Jacobi, restarted from the best iterate so far,
+// once the residual has grown past kFallbackGrow times its best or has set no
+// new best for kFallbackStall iterations.
+constexpr double kFallbackGrow = 10.0;
+constexpr int kFallbackStall = 250;
+
 template <typename T>
 static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const T* b_in, T* x_io, int nrhs, double rtol,
-                           int maxit, int precond, int* iters, double* relres)
+                           int maxit, int precond, int* iters, double* relres, int64_t* fallback_at)
 {
     const int64_t n = v.n, m = n * nrhs;
     hipStream_t s = v.stream;
     Buf buf;
-    double *b, *x, *r, *z, *p, *q, *part, *coef;
+    double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr;
     T *op_in, *op_out;
     hipError_t e;
     if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &z)) ||
         (e = buf.get(m, &p)) || (e = buf.get(m, &q)) || (e = buf.get((size_t)kDotBlocks * nrhs, &part)) ||
-        (e = buf.get(3 * nrhs, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)))
+        (e = buf.get(3 * nrhs, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)) ||
+        (precond == 2 && fallback_at && (e = buf.get(m, &xbest))))
         return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "cg work buffers");
+    if (fallback_at) *fallback_at = -1;
 
     std::vector<double> hpart((size_t)kDotBlocks * nrhs), hcoef(3 * nrhs);
     auto dots = [&](const double* a1, const double* a2, std::vector<double>& out) -> bool {
@@ -184,15 +193,21 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 
     hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, b_in, b);
     hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const T*)x_io, x);
-    fkt_status st = apply(x, q);
-    if (st != FKT_OK) return st;
-    hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
-    if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
-    if (hipMemcpyAsync(p, z, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return cg_set_error(FKT_EDEVICE, "cg copy");
-
     std::vector<double> bb, rr, rz, pq, rz_new;
-    if (!dots(b, b, bb) || !dots(r, r, rr) || !dots(r, z, rz)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+    // r = b - A x, z = M r, p = z, rz = (r, z), rr = (r, r)
+    auto start = [&]() -> fkt_status {
+        fkt_status st0 = apply(x, q);
+        if (st0 != FKT_OK) return st0;
+        hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
+        if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
+        if (hipMemcpyAsync(p, z, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return cg_set_error(FKT_EDEVICE, "cg copy");
+        if (!dots(r, r, rr) || !dots(r, z, rz)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        return FKT_OK;
+    };
+    if (!dots(b, b, bb)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+    fkt_status st = start();
+    if (st != FKT_OK) return st;
     auto worst = [&](const std::vector<double>& rv) {
         double w = 0.0;
         for (int c2 = 0; c2 < nrhs; ++c2) {
@@ -203,7 +218,21 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     };
     int it = 0;
     double res = worst(rr);
+    double best = res;
+    int it_best = 0;
+    if (xbest && hipMemcpyAsync(xbest, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return cg_set_error(FKT_EDEVICE, "cg copy");
     while (res > rtol && it < maxit) {
+        if (xbest && precond == 2 && (res > kFallbackGrow * best || it - it_best >= kFallbackStall)) {
+            // block-Jacobi from the best iterate (one extra operator application)
+            precond = 1;
+            if (fallback_at) *fallback_at = it;
+            if (hipMemcpyAsync(x, xbest, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return cg_set_error(FKT_EDEVICE, "cg copy");
+            if ((st = start()) != FKT_OK) return st;
+            res = worst(rr);
+            continue;
+        }
         st = apply(p, q);
         if (st != FKT_OK) return st;
         if (!dots(p, q, pq)) return cg_set_error(FKT_EDEVICE, "cg reduction");
@@ -227,6 +256,12 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         rz = rz_new;
         ++it;
         res = worst(rr);
+        if (xbest && precond == 2 && res < best) {
+            best = res;
+            it_best = it;
+            if (hipMemcpyAsync(xbest, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return cg_set_error(FKT_EDEVICE, "cg copy");
+        }
     }
     hipLaunchKernelGGL((k_from_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, x, x_io);
     if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
@@ -237,15 +272,28 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 }
 
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
-                         double rtol, int maxit, int precond, int* iters, double* relres)
+                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at)
 {
     if (precond < 0 || precond > 2 || (precond == 2 && !v.learn))
         return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
+    if (precond == 2) {
+        // a zero output layer (initial weights, or a filter the judge
+        // rejected) is block-Jacobi exactly: run it as such
+        std::vector<float> prm(kLearnParams);
+        if (learn_params(v.learn, prm.data(), false) != hipSuccess)
+            return cg_set_error(FKT_EDEVICE, "learned preconditioner weights");
+        constexpr int kOut = kLearnFeatures * kLearnHidden + kLearnHidden + kLearnHidden * kLearnHidden + kLearnHidden;
+        bool zero = true;
+        for (int i = kOut; i < kLearnParams; ++i) zero = zero && prm[i] == 0.0f;
+        if (zero) precond = 1;
+    }
     if (precond == 2 && learn_prepare_filter(v.learn) != hipSuccess)
         return cg_set_error(FKT_EDEVICE, "learned preconditioner forward pass");
     if (v.prec == 1)
-        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters, relres);
-    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters, relres);
+        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters, relres,
+                               fallback_at);
+    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters, relres,
+                            fallback_at);
 }
 
 }  // namespace fkt

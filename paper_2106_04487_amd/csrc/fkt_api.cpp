@@ -50,7 +50,7 @@ struct DeviceScope {
 namespace fkt {
 fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
-                         double rtol, int maxit, int precond, int* iters, double* relres);
+                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at);
 }  // namespace fkt
 
 struct fkt_plan_s {
@@ -368,6 +368,7 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
         st.depth = std::max<int64_t>(st.depth, P->T.level[b]);
     }
     st.rank = P->tab.rank;
+    st.cg_fallback_iter = -1;
     if (opt.device >= 0) {
         s = upload_plan(P);
         if (s != FKT_OK) {
@@ -532,8 +533,10 @@ static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
     return FKT_OK;
 }
 
-fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
-                        int precond, int* iters, double* relres)
+// fkt_cg_solve without (fallback_at NULL) or with the learned filter's
+// block-Jacobi fallback; the judge runs the filter on its own.
+static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
+                           int precond, int* iters, double* relres, int64_t* fallback_at)
 {
     if (!P) return fail(FKT_EINVAL, "plan is NULL");
     if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_cg_solve");
@@ -549,13 +552,14 @@ fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int
         const fkt_status st = ensure_learn(P, sigma2);
         if (st != FKT_OK) return st;
     }
-    if (precond == 1 && P->st.nleaves > 0) {
+    // block-Jacobi serves precond 1 and is the fallback of precond 2
+    if (precond >= 1 && P->st.nleaves > 0) {
         int64_t big = 0;
         for (int64_t b = 0; b < P->T.nnodes(); ++b)
             if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
         if (big > 4096) return fail(FKT_EUNSUPPORTED, "block-Jacobi needs leaves of at most 4096 points");
     }
-    if (precond == 1 && P->bj_sigma2 != sigma2) {
+    if (precond >= 1 && P->bj_sigma2 != sigma2) {
         std::vector<int32_t> lb, lc;
         std::vector<int64_t> off;
         std::vector<double> inv;
@@ -586,7 +590,13 @@ fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int
     }
     fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream, P->dp.perm, P->bj_nleaf,
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off, P->bj_inv, P->learn};
-    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres);
+    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at);
+}
+
+fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
+                        int precond, int* iters, double* relres)
+{
+    return cg_entry(P, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, P ? &P->st.cg_fallback_iter : nullptr);
 }
 
 static fkt_status learn_entry(fkt_plan_t P, double sigma2)
@@ -661,7 +671,7 @@ fkt_status fkt_learn_train(fkt_plan_t P, double sigma2, int steps, int batch, do
             break;
         }
         int it = 0;
-        const fkt_status s2 = fkt_cg_solve(P, sigma2, b, x, 1, 1e-300, judge_iters, pc, &it, &rr[pc - 1]);
+        const fkt_status s2 = cg_entry(P, sigma2, b, x, 1, 1e-300, judge_iters, pc, &it, &rr[pc - 1], nullptr);
         if (s2 != FKT_OK && s2 != FKT_ENOTCONV) st = s2;
     }
     (void)hipFree(b);

@@ -116,3 +116,39 @@ def test_block_jacobi_judges_the_trained_filter(F):
         assert np.all(p["w3"] == 0.0) and p["b3"] == 0.0
         assert abs(res["learned"] - res["block_jacobi"]) <= 1e-6 * res["block_jacobi"] + 1e-300
     plan.close()
+
+
+def test_learned_solve_falls_back_to_block_jacobi(F):
+    """On an ill-conditioned system (length scale 0.3) the residual of PCG
+    rises well above its best within a few dozen iterations; with a trained
+    filter (non-zero output layer) the solve then restarts from its best
+    iterate with block-Jacobi. A zero output layer is block-Jacobi exactly and
+    runs as such, without the fallback."""
+    import torch
+    n, sig2 = 6000, 1e-2
+    X = _gp_points(n, 68)
+    plan = F.fkt_plan(X, "matern52", 128, 5, theta=0.4, lengthscale=0.3)
+    b = torch.as_tensor(W.normal_rhs(n, 1, 69)[:, 0], device="cuda")
+    res = {}
+    for pc in ("block_jacobi", "learned"):
+        with pytest.raises(F.FktError) as ei:
+            F.fkt_cg_solve(plan, sig2, b, rtol=1e-30, maxit=100, precond=pc)
+        res[pc] = ei.value.relres
+        assert plan.info()["cg_fallback_iter"] == -1
+    assert abs(res["learned"] - res["block_jacobi"]) <= 1e-6 * res["block_jacobi"]  # atomics: run-to-run rounding
+    rng = np.random.default_rng(72)
+    P = LR.unpack(np.zeros(LR.NPARAMS))
+    P["W1"] = rng.normal(0.0, 1.0, P["W1"].shape)
+    P["b1"] = rng.normal(0.0, 0.5, P["b1"].shape)
+    P["W2"] = rng.normal(0.0, 0.1, P["W2"].shape)
+    P["w3"] = rng.normal(0.0, 0.01, P["w3"].shape)
+    F.fkt_learn_params(plan, sig2, LR.pack(P).astype(np.float32))
+    with pytest.raises(F.FktError) as ei:
+        F.fkt_cg_solve(plan, sig2, b, rtol=1e-30, maxit=100, precond="learned")
+    e = ei.value
+    fb = plan.info()["cg_fallback_iter"]
+    print(f"100 iterations: block-Jacobi relres {res['block_jacobi']:.3e}; perturbed filter fell back at {fb}, "
+          f"relres {e.relres:.3e}")
+    assert e.status == 5 and e.iters == 100
+    assert 0 <= fb < 100 and np.isfinite(e.relres)
+    plan.close()
