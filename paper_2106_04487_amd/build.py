@@ -48,6 +48,10 @@ def _jobs():
     for kind in range(7):
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "stage_m2t.hip"),
                      "-o", os.path.join(BUILD, f"stage_m2t_{kind}.o")])
+    # many-RHS source-to-multipole on the matrix cores, one object per dimension
+    for d in (3, 4, 5):
+        jobs.append([*dev, f"-DFKT_S2M_D={d}", "-c", os.path.join(CSRC, "s2m_mrhs.hip"),
+                     "-o", os.path.join(BUILD, f"s2m_mrhs_d{d}.o")])
     # many-RHS multipole-to-target on the matrix cores, one object per kernel kind
     for kind in range(7):
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "m2t_mrhs.hip"),

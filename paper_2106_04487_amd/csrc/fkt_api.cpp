@@ -286,6 +286,11 @@ static fkt_status upload_plan(fkt_plan_t P)
         if (ns > 0) {
             if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * ns * R, &P->mr.mom)) != hipSuccess)
                 return hip_fail(e, "many-RHS moments");
+            P->mr.npart = L.npartials;
+            if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * P->n, &P->mr.x32)) != hipSuccess ||
+                (e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * (size_t)std::max<int64_t>(L.npartials, 1) * R,
+                              &P->mr.part32)) != hipSuccess)
+                return hip_fail(e, "many-RHS moment work buffers");
             const size_t fb = (size_t)ns * P->mr.ks * 2 * 64 * 16;
             if ((e = P->alloc(fb, &P->mr.bhi)) != hipSuccess || (e = P->alloc(fb, &P->mr.blo)) != hipSuccess)
                 return hip_fail(e, "many-RHS moment fragments");

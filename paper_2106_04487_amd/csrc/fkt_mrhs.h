@@ -26,7 +26,10 @@ struct DevMrhs {
     void* zf = nullptr;               // [32][n] far field of the group, FP32, tree order
     bool bf16 = false;
     // far field of the group on the matrix cores
-    void* mom = nullptr;              // [32][nslots][rank] FP32 moments (one s2m per column)
+    void* mom = nullptr;              // [32][nslots][rank] FP32 moments
+    void* x32 = nullptr;              // [n][32] FP32 weights of the group in tree order
+    void* part32 = nullptr;           // [32][npart][rank] partial moments of split nodes
+    int64_t npart = 0;
     void* bhi = nullptr;              // [nslots][ks][2][64] bf16 x 8 MFMA B fragments, high part
     void* blo = nullptr;              //   and low part (m - hi)
     int ks = 0;                       // 32-entry k-steps per node (rank padded to a multiple of 64)
@@ -50,6 +53,10 @@ FKT_DECLARE_M2T_MRHS(4)
 FKT_DECLARE_M2T_MRHS(5)
 FKT_DECLARE_M2T_MRHS(6)
 #undef FKT_DECLARE_M2T_MRHS
+// moments of the 32 columns of the group (x32 gathered) into mom, per dimension
+bool launch_s2m_mrhs_d3(const DevPlan& a, const DevMrhs& mr, hipStream_t s);
+bool launch_s2m_mrhs_d4(const DevPlan& a, const DevMrhs& mr, hipStream_t s);
+bool launch_s2m_mrhs_d5(const DevPlan& a, const DevMrhs& mr, hipStream_t s);
 // s2m of one column into the given moment buffer (gather included)
 hipError_t launch_s2m_column(const DevPlan& a, const DevWork& wk, const void* x, int nrhs, int col, int prec,
                              hipStream_t s);

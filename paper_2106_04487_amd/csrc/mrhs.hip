@@ -41,6 +41,18 @@ __global__ __launch_bounds__(256) void k_mr_gather(int npad, const int* __restri
     for (int c = 0; c < kMrCols; ++c) XT[(size_t)c * npad + p] = (TC)(xr ? xr[c] : 0.f);
 }
 
+// X32[i][c] = x[perm[i]][col0 + c]: the group's weights in tree order
+__global__ __launch_bounds__(256) void k_mr_xgather(int n, const int64_t* __restrict__ perm,
+                                                    const float* __restrict__ x, int nrhs, int col0,
+                                                    float* __restrict__ X32)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)n * kMrCols) return;
+    const int64_t i = g / kMrCols;
+    const int c = (int)(g % kMrCols);
+    X32[g] = x[perm[i] * nrhs + col0 + c];
+}
+
 // B fragments of the moments: for node slot s, k-step t (32 entries) and
 // column tile ct, lane l holds entries k = 32 t + 8 (l / 16) + q, q < 8, of
 // column 16 ct + l % 16, split into bf16 high and low parts (0 past rank)
@@ -223,16 +235,20 @@ hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, co
     float* zf = (float*)mr.zf;
     for (int col0 = 0; col0 < nrhs; col0 += kMrCols) {
         if (mr.mom && a.nslots > 0) {
-            // far field of the group on the matrix cores: moments of each
-            // column, B fragments, then one MFMA multipole-to-target pass that
-            // writes zf for all 32 columns
-            for (int c = 0; c < kMrCols; ++c) {
-                DevWork w = wk;
-                w.zacc = zf + (size_t)c * a.n;
-                w.mom = (float*)mr.mom + (size_t)c * a.nslots * a.rank;
-                hipError_t e = launch_s2m_column(a, w, x, nrhs, col0 + c, 1, s);
-                if (e != hipSuccess) return e;
+            // far field of the group on the matrix cores: moments of the 32
+            // columns (MFMA s2m), B fragments, then one MFMA multipole-to-
+            // target pass that writes zf for all 32 columns
+            const int64_t nx = (int64_t)a.n * kMrCols;
+            hipLaunchKernelGGL(k_mr_xgather, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, a.n, a.perm, x,
+                               nrhs, col0, (float*)mr.x32);
+            bool ok_s2m = false;
+            switch (a.d) {
+            case 3: ok_s2m = launch_s2m_mrhs_d3(a, mr, s); break;
+            case 4: ok_s2m = launch_s2m_mrhs_d4(a, mr, s); break;
+            case 5: ok_s2m = launch_s2m_mrhs_d5(a, mr, s); break;
+            default: break;
             }
+            if (!ok_s2m) return hipErrorInvalidValue;
             const int64_t nf = (int64_t)a.nslots * mr.ks * 2 * kWave;
             hipLaunchKernelGGL(k_mom_frag, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, a.nslots, a.rank,
                                mr.ks, (const float*)mr.mom, (bf8*)mr.bhi, (bf8*)mr.blo);
