@@ -87,6 +87,21 @@ def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmu
             "rel_err_vs_dense": rel_err, "stages_ms": stages, "plan": info}
 
 
+def nsweep_leg(F, torch, steps, err_targets, kernel="matern32", prec="f64"):
+    """The headline settings (uniform cube, leaf 256, p = 6, the kernel's
+    theta) at N from 1e4 to 1e6: time per MVM against N shows the
+    O(N log N) growth of the method."""
+    out = []
+    for n in (10_000, 31_623, 100_000, 316_228, 1_000_000):
+        X = W.uniform_cube(n, 3, 1002)
+        x64 = W.normal_rhs(n, 1, 2002)[:, 0]
+        r = run_variant(F, torch, X, x64, kernel, prec, DEFAULT_THETA[kernel], 256, 6, steps, 3, min(err_targets, n))
+        info = r.pop("plan")
+        r.update({"n": n, "near_pairs": info["near_pairs"], "far_pairs": info["far_pairs"]})
+        out.append(r)
+    return out
+
+
 def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM
     on the d = 4 mixture: no preconditioner, block-Jacobi, and the learned
@@ -262,8 +277,9 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--order", type=int, default=6)
-    ap.add_argument("--err-targets", type=int, default=2000,
-                    help="targets sampled (seed 3002) for the error against the dense FP64 sum; 0 skips")
+    ap.add_argument("--err-targets", type=int, default=10000,
+                    help="targets sampled (seed 3002) for the error against the dense FP64 sum (the headline "
+                         "line; the secondary legs use at most 1000); 0 skips")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="time budget of the CPU-oracle baseline sample; 0 skips")
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
@@ -278,7 +294,7 @@ def main():
     ap.add_argument("--batch-no-per-instance", action="store_true")
     ap.add_argument("--mrhs-theta", type=float, default=0.4)
     ap.add_argument("--mrhs-modes", default=",".join(MRHS_MODES))
-    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp"],
+    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp", "nsweep"],
                     help="run one secondary leg alone and print its JSON (the default runs the headline line)")
     a = ap.parse_args()
 
@@ -292,10 +308,12 @@ def main():
 
     if a.leg != "all":
         if a.leg == "many_rhs":
-            out = mrhs_leg(F, torch, a.steps, a.mrhs_theta, a.err_targets, tuple(a.mrhs_modes.split(",")))
+            out = mrhs_leg(F, torch, a.steps, a.mrhs_theta, min(a.err_targets, 1000), tuple(a.mrhs_modes.split(",")))
         elif a.leg == "batched":
             out = batch_leg(F, torch, a.steps, a.batch_theta, max(a.err_targets // 10, 20), a.batch_leaf,
                             not a.batch_no_per_instance)
+        elif a.leg == "nsweep":
+            out = nsweep_leg(F, torch, a.steps, a.err_targets, a.kernel, a.prec)
         else:
             out = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
         print(json.dumps(out))
