@@ -45,7 +45,7 @@ NEAR_FLOPS_PER_PAIR = {"laplace": 12, "matern32": 16}
 # HBM bytes per near-field launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors of a plain copy) of the current near kernel, from the
 # counter profile under profiles/; empty until re-measured after a change.
-NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.376e9}
+NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.375e9}
 
 
 def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True):

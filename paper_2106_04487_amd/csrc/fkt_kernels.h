@@ -256,9 +256,11 @@ __device__ __forceinline__ double exp_nonpos(double x)
 // f takes one FMA with ln2/256 rounded to FP64: its error, at most
 // |n| 2^-62 <= 369 |x| 2^-62, changes e^x by a relative 8e-17 |x|, i.e. by at
 // most 8e-17 e^x |x| <= 3e-17 absolute. x is clamped at -1100, where e^x is
-// already zero in FP64.
+// already zero in FP64. exp_tab_scaled applies scale() to the polynomial
+// value before the table entry, so a factor such as 1 + a costs one FMA.
 constexpr int kExpTabLen = 256;
-__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab)
+template <class Scale>
+__device__ __forceinline__ double exp_tab_scaled(double x, const double* __restrict__ tab, Scale scale)
 {
     constexpr double kShift = 6755399441055744.0;               // 1.5 * 2^52
     constexpr double kInvL = 369.3299304675746;                 // 256 / ln2
@@ -272,7 +274,16 @@ __device__ __forceinline__ double exp_tab(double x, const double* __restrict__ t
     q = fma(q, f, 0.5);
     q = fma(q, f, 1.0);
     q = fma(q, f, 1.0);
-    return __builtin_ldexp(tab[n & (kExpTabLen - 1)] * q, n >> 8);
+    return __builtin_ldexp(tab[n & (kExpTabLen - 1)] * scale(q), n >> 8);
+}
+__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab)
+{
+    return exp_tab_scaled(x, tab, [](double q) { return q; });
+}
+// (1 + a) e^x: the factor enters the polynomial value as one FMA, q + q a
+__device__ __forceinline__ double exp_tab_1p(double x, double a, const double* __restrict__ tab)
+{
+    return exp_tab_scaled(x, tab, [a](double q) { return fma(q, a, q); });
 }
 
 // c sqrt(d2) for d2 > 0: estimate y of 1/sqrt(d2), g = d2 y, then one Newton
@@ -651,7 +662,7 @@ template <> struct NearKernel<FKT_MATERN32, double> {
     static __device__ __forceinline__ double eval(double d2, double c0, double, const double* tab)
     {
         const double ar = scaled_sqrt_pos(d2, c0);
-        return (1.0 + ar) * exp_tab(-ar, tab);
+        return exp_tab_1p(-ar, ar, tab);
     }
 };
 template <> struct NearKernel<FKT_MATERN52, double> {
