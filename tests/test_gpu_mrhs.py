@@ -1,7 +1,7 @@
 """Many right-hand sides on the matrix cores (FP32 plans, groups of 32
-columns): the near field by MFMA in FP32 or bf16, the far field column by
-column. Checked against the oracle's Algorithm 1 (FP64) and against the
-same plan's column-at-a-time FP32 path."""
+columns): the near field by MFMA in FP32 or bf16, the moments by FP32 MFMA
+and the far field by bf16 x3 MFMA. Checked against the oracle's Algorithm 1
+(FP64) and against the same plan's column-at-a-time FP32 path."""
 import numpy as np
 import pytest
 
@@ -77,3 +77,30 @@ def test_mrhs_needs_fp32_plan(F):
     X = W.uniform_cube(500, 3, 79)
     with pytest.raises(F.FktError):
         F.fkt_plan(X, "gaussian", 64, 4, theta=0.5, prec="f64", mrhs="bf16", lengthscale=0.1)
+
+
+def test_mrhs_split_nodes_match_column_path(F):
+    """Nodes with a far set and more than 1024 points are split over several
+    moment work units whose partial moments are summed afterwards; the
+    matrix-core moments of 32 columns must agree with the column-at-a-time
+    path there too (which the oracle checks elsewhere)."""
+    n, theta = 60000, 0.5
+    X = W.uniform_cube(n, 3, 80)
+    x = W.normal_rhs(n, 32, 81)
+    # the case has such nodes: far from some target whose walk reaches them
+    T = oracle.Tree(X, 128)
+    big = [b for b in range(T.nnodes) if T.end[b] - T.start[b] > 1024 and T.parent[b] >= 0]
+    far_somewhere = False
+    for b in big:
+        pb = T.parent[b]
+        d2b = np.sum((X - T.ctr[b]) ** 2, axis=1)
+        d2p = np.sum((X - T.ctr[pb]) ** 2, axis=1)
+        if np.any((T.rho2[b] < theta * theta * d2b) & ~(T.rho2[pb] < theta * theta * d2p)):
+            far_somewhere = True
+            break
+    assert far_somewhere
+    zcol = _run(F, X, x, "gaussian", dict(lengthscale=0.1), 128, 4, theta, None)
+    zf32 = _run(F, X, x, "gaussian", dict(lengthscale=0.1), 128, 4, theta, "f32")
+    rel = np.linalg.norm(zf32 - zcol) / np.linalg.norm(zcol)
+    print(f"split nodes: mrhs f32 vs columns {rel:.2e}")
+    assert rel <= 1e-5
