@@ -608,6 +608,13 @@ bool check_lists(const Tree& T, const Lists& L, std::string& err)
         return false;
     };
     if ((int64_t)L.blk_count.size() != nb) return bad("block arrays", 0);
+    // list offsets are 32-bit on the device
+    constexpr int64_t kMax32 = 0x7fffffff;
+    if ((int64_t)L.near_tgt.size() > kMax32 || (int64_t)L.far_slot.size() > kMax32 ||
+        (int64_t)L.job_nodes.size() > kMax32 || (int64_t)L.job_noff.size() > kMax32 || L.npartials > kMax32) {
+        err = "plan check: more list entries than 32-bit offsets hold (too many points for one plan)";
+        return false;
+    }
     for (int64_t q = 0; q < nb; ++q)
         if (L.blk_count[q] < 1 || L.blk_count[q] > kBlock || L.blk_begin[q] < 0 || L.blk_begin[q] + L.blk_count[q] > n)
             return bad("block range", q);
