@@ -106,7 +106,8 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM
     on the d = 4 mixture: no preconditioner, block-Jacobi, and the learned
     per-leaf spectral filter after train_steps Adam steps (batch 8), judged by
-    block-Jacobi on 200 CG iterations (reverted to block-Jacobi if worse)."""
+    block-Jacobi on 200 CG iterations (reverted to block-Jacobi if worse);
+    then the same three with the MVM in FP32 (mixed precision)."""
     spec = W.WORKLOADS["gmm4_n200k_gp"]
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
     y = W.gp_targets(X, spec["lengthscale"], spec["sigma2"], spec["nfeat"], spec["rhs_seed"])
@@ -120,10 +121,11 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
            "plan_seconds": plan_s}
 
     def solve(name, pc):
+        rhs = b if plan.prec == "f64" else b.float()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            x, it, rr = F.fkt_cg_solve(plan, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
+            x, it, rr = F.fkt_cg_solve(plan, sig2, rhs, rtol=rtol, maxit=maxit, precond=pc)
             ok = True
         except F.FktError as e:
             if e.status != 5:
@@ -149,6 +151,17 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     out["learned"]["fallback_to_block_jacobi_at"] = plan.info()["cg_fallback_iter"]
     out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
                            "train_loss_first": l0, "train_loss_last": l1, "kept_after_block_jacobi_judge": accepted})
+    params = F.fkt_learn_params(plan, sig2)
+    plan.close()
+
+    # mixed precision: the same solves with the MVM in FP32 (CG vectors,
+    # scalars and preconditioners stay FP64; the learned weights carry over)
+    t0 = time.perf_counter()
+    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, prec="f32", lengthscale=lengthscale)
+    out["f32_plan_seconds"] = time.perf_counter() - t0
+    F.fkt_learn_params(plan, sig2, params)
+    for name in ("none", "block_jacobi", "learned"):
+        solve("f32_mvm_" + name, name)
     plan.close()
     return out
 
