@@ -152,3 +152,28 @@ def test_learned_solve_falls_back_to_block_jacobi(F):
     assert e.status == 5 and e.iters == 100
     assert 0 <= fb < 100 and np.isfinite(e.relres)
     plan.close()
+
+
+def test_mixed_precision_cg_reaches_tolerance(F):
+    """CG with the MVM in FP32 (vectors, scalars and the preconditioners in
+    FP64) still reaches relative residual 1e-6, and its solution agrees with
+    the FP64 plan's to the FP32 operator's accuracy."""
+    import torch
+    n, sig2 = 5000, 1e-2
+    X = _gp_points(n, 73)
+    y = W.gp_targets(X, 0.1, sig2, 512, 74)
+    sol = {}
+    for prec in ("f64", "f32"):
+        plan = F.fkt_plan(X, "matern52", 128, 6, theta=0.35, prec=prec, lengthscale=0.1)
+        b = torch.as_tensor(y, device="cuda", dtype=torch.float64 if prec == "f64" else torch.float32)
+        for pc in ("none", "block_jacobi"):
+            x, it, rr = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond=pc)
+            assert rr <= 1e-6
+            sol[(prec, pc)] = (x.double().cpu().numpy(), it)
+        plan.close()
+    for pc in ("none", "block_jacobi"):
+        x64, it64 = sol[("f64", pc)]
+        x32, it32 = sol[("f32", pc)]
+        rel = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+        print(f"{pc}: iterations f64 {it64}, f32 MVM {it32}; solutions differ by {rel:.2e}")
+        assert rel <= 1e-4
