@@ -121,11 +121,11 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
            "plan_seconds": plan_s}
 
     def solve(name, pc):
-        rhs = b if plan.prec == "f64" else b.float()
+        # FP32 plans: FP32 MVMs with FP64 b and solution (fkt_cg_solve64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            x, it, rr = F.fkt_cg_solve(plan, sig2, rhs, rtol=rtol, maxit=maxit, precond=pc)
+            x, it, rr = F.fkt_cg_solve64(plan, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
             ok = True
         except F.FktError as e:
             if e.status != 5:
@@ -152,7 +152,7 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
                            "train_loss_first": l0, "train_loss_last": l1, "kept_after_block_jacobi_judge": accepted})
     params = F.fkt_learn_params(plan, sig2)
-    plan.close()
+    plan64 = plan
 
     # mixed precision: the same solves with the MVM in FP32 (CG vectors,
     # scalars and preconditioners stay FP64; the learned weights carry over)
@@ -162,7 +162,25 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     F.fkt_learn_params(plan, sig2, params)
     for name in ("none", "block_jacobi", "learned"):
         solve("f32_mvm_" + name, name)
+    # FP32 CG corrections to FP64 residuals: rtol under the FP64 operator
+    for name in ("none", "block_jacobi", "learned"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            x, it, outer, rr = F.fkt_cg_solve_refined(plan64, plan, sig2, b, rtol=rtol, maxit=maxit, precond=name)
+            ok = True
+        except F.FktError as e:
+            if e.status != 5:
+                raise
+            it, outer, rr, ok = e.iters, e.outer, e.relres, False
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out["refined_" + name] = {"iterations_f32": it, "fp64_steps": outer, "relres": rr, "converged": ok,
+                                  "seconds": sec}
+        print(f"bench: gp solve n={n} refined precond={name}: {it} FP32 iterations, {outer} FP64 steps, "
+              f"{sec:.2f} s, relres {rr:.2e}", file=sys.stderr, flush=True)
     plan.close()
+    plan64.close()
     return out
 
 
@@ -249,6 +267,84 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
 MRHS_MODES = {"columns_f32": None, "mfma_f32": "f32", "mfma_bf16": "bf16"}
 
 
+def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0):
+    """Solves (K~ + sigma2 I) x = b on the first ninst instances of the
+    batched workload (rational quadratic, d = 3): one CG call on the forest
+    plan (every instance its own CG system, all advanced by one MVM per
+    iteration) with the MVM in FP64 and in FP32, against plain FP64 CG on one
+    plan per instance, one instance after another. Reports the worst
+    per-instance relative residual of each batched solve (against the FP64
+    operator) and its speedup over the per-instance solves."""
+    spec = W.WORKLOADS["batch256_rq"]
+    sizes = W.instance_sizes(spec["ninst"], spec["nmin"], spec["nmax"], spec["size_seed"])[:ninst]
+    X, off = W.batched_instances(sizes, spec["d"], spec["pts_seed"])
+    n = X.shape[0]
+    b64 = W.normal_rhs(n, 1, spec["rhs_seed"])[:, 0]
+    kw = dict(lengthscale=spec["lengthscale"], alpha=spec["alpha"])
+    leaf, p = 128, spec["order"]
+    out = {"workload": f"batch{ninst}_rq_d3_n{n}", "instances": ninst, "n_total": n, "sigma2": sig2, "rtol": rtol,
+           "maxit": maxit, "theta": theta, "p": p, "leaf": leaf}
+
+    def cg(plan, b, pc, solve=F.fkt_cg_solve):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            x, it, rr = solve(plan, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
+        except F.FktError as e:
+            if e.status != 5:
+                raise
+            x, it, rr = e.x, e.iters, e.relres
+        torch.cuda.synchronize()
+        return x, it, rr, time.perf_counter() - t0
+
+    its, secs = [], 0.0
+    for i in range(ninst):
+        plan = F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, **kw)
+        bi = torch.as_tensor(b64[off[i]:off[i + 1]], device="cuda")
+        _, it, _, sec = cg(plan, bi, "none")
+        its.append(it)
+        secs += sec
+        plan.close()
+    out["per_instance_f64_none"] = {"seconds": secs, "iterations_max": max(its), "iterations_sum": int(sum(its))}
+    print(f"bench: batched solve, per-instance FP64 plain CG: {secs:.2f} s, iterations max {max(its)}",
+          file=sys.stderr, flush=True)
+    # true residuals of every solution against the FP64 operator
+    plan64 = F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta, prec="f64", **kw)
+    b = torch.as_tensor(b64, device="cuda")
+    bh = b64
+    for prec in ("f64", "f32"):
+        plan = plan64 if prec == "f64" else F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta,
+                                                               prec=prec, **kw)
+        # FP32 plans: FP32 MVMs, FP64 b, CG vectors and solution (fkt_cg_solve64)
+        for pc in ("none", "block_jacobi"):
+            x, it, rr, sec = cg(plan, b, pc, solve=F.fkt_cg_solve64)
+            x = x.double()
+            r = (b - F.fkt_mvm(plan64, x) - sig2 * x).cpu().numpy()
+            worst = max(float(np.linalg.norm(r[off[i]:off[i + 1]]) / np.linalg.norm(bh[off[i]:off[i + 1]]))
+                        for i in range(ninst))
+            out[f"batched_{prec}_{pc}"] = {"seconds": sec, "iterations": it, "relres": rr,
+                                           "relres_worst_instance": worst, "speedup_vs_per_instance_f64": secs / sec}
+            print(f"bench: batched solve {prec} {pc}: {sec:.2f} s, {it} iterations, relres {rr:.2e}, "
+                  f"worst instance {worst:.2e}", file=sys.stderr, flush=True)
+        if plan is not plan64:
+            plan32 = plan
+    # FP32 CG corrections to FP64 residuals: every instance to rtol under the
+    # FP64 operator
+    for pc in ("none", "block_jacobi"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, outer, rr = F.fkt_cg_solve_refined(plan64, plan32, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[f"batched_refined_{pc}"] = {"seconds": sec, "iterations_f32": it, "fp64_steps": outer, "relres": rr,
+                                        "speedup_vs_per_instance_f64": secs / sec}
+        print(f"bench: batched solve refined {pc}: {sec:.2f} s, {it} FP32 iterations, {outer} FP64 steps, "
+              f"relres {rr:.2e}", file=sys.stderr, flush=True)
+    plan32.close()
+    plan64.close()
+    return out
+
+
 def mrhs_leg(F, torch, reps, theta, err_targets, modes=tuple(MRHS_MODES)):
     """Mixed precision, many RHS: 500k points of a 10-component mixture in
     d = 5, Gaussian length scale 0.2, p = 8, 32 RHS, FP32 plan: column by
@@ -307,7 +403,7 @@ def main():
     ap.add_argument("--batch-no-per-instance", action="store_true")
     ap.add_argument("--mrhs-theta", type=float, default=0.4)
     ap.add_argument("--mrhs-modes", default=",".join(MRHS_MODES))
-    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp", "nsweep"],
+    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp", "nsweep", "batched_solve"],
                     help="run one secondary leg alone and print its JSON (the default runs the headline line)")
     a = ap.parse_args()
 
@@ -325,6 +421,8 @@ def main():
         elif a.leg == "batched":
             out = batch_leg(F, torch, a.steps, a.batch_theta, max(a.err_targets // 10, 20), a.batch_leaf,
                             not a.batch_no_per_instance)
+        elif a.leg == "batched_solve":
+            out = batch_solve_leg(F, torch, 32, a.batch_theta)
         elif a.leg == "nsweep":
             out = nsweep_leg(F, torch, a.steps, a.err_targets, a.kernel, a.prec)
         else:

@@ -136,7 +136,12 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  *   b         device, n x nrhs (plan precision element type).
  *   x         device, n x nrhs; on entry the initial guess, on exit the
  *             solution (the last iterate if not converged).
- *   rtol      stop when ||b - A x||_2 <= rtol ||b||_2 for every column.
+ *   rtol      stop when ||b - A x||_2 <= rtol ||b||_2 for every system.
+ *             A system is one column of one instance: for a batched plan
+ *             (fkt_plan_batch) the operator is block diagonal, so every
+ *             instance and column runs its own CG recurrences (its own step
+ *             lengths and stopping test, norms over the instance's rows);
+ *             a system that has converged is frozen while the others go on.
  *   maxit     iteration cap, >= 1.
  *   precond   0 none, 1 block-Jacobi (per-leaf dense Cholesky of
  *             K_ll + sigma2 I), 2 the learned per-leaf spectral filter
@@ -147,8 +152,9 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  *             iterations, CG restarts from the best iterate with block-Jacobi
  *             (one extra fkt_mvm; iterations keep counting; the switch is
  *             reported in fkt_plan_stats.cg_fallback_iter).
- *   iters     host, receives the iteration count (may be NULL).
- *   relres    host, receives max over columns of the final relative
+ *   iters     host, receives the iteration count (of the slowest system;
+ *             may be NULL).
+ *   relres    host, receives max over systems of the final relative
  *             residual (may be NULL).
  * Synchronises the plan's stream (it reads residual norms on the host).
  * Errors: as fkt_mvm, FKT_EUNSUPPORTED for an unknown precond, FKT_ENOTCONV
@@ -156,6 +162,45 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  */
 fkt_status fkt_cg_solve(fkt_plan_t p, double sigma2, const void *b, void *x, int nrhs, double rtol, int maxit,
                         int precond, int *iters, double *relres);
+
+/*
+ * fkt_cg_solve64 -- fkt_cg_solve with b and x in FP64 (device, n x nrhs
+ * doubles) whatever the plan's precision. On an FP32 plan this is the
+ * mixed-precision solve: the MVMs run in FP32, while b, the CG vectors, the
+ * preconditioners and the returned solution stay FP64, so the solution is
+ * not rounded to FP32 on the way out. On an FP64 plan it is fkt_cg_solve.
+ * Arguments, errors and synchronisation as fkt_cg_solve.
+ */
+fkt_status fkt_cg_solve64(fkt_plan_t p, double sigma2, const double *b, double *x, int nrhs, double rtol, int maxit,
+                          int precond, int *iters, double *relres);
+
+/*
+ * fkt_cg_solve_refined -- solve (K~ + sigma2 I) x = b to rtol against the
+ * FP64 operator while the CG iterations run on the FP32 one (mixed-precision
+ * iterative refinement), for the posterior-mean system of the paper's
+ * Gaussian-process regression (eq. gp_posterior). CG on an FP32 operator
+ * alone stops at that operator's own error (about 1e-5 relative), so the
+ * residual is taken in FP64 and the FP32 solves only supply corrections:
+ *   r = b - (K~64 + sigma2 I) x;  solve (K~32 + sigma2 I) d = r by CG from
+ *   d = 0 (fkt_cg_solve64 on lo, precond as fkt_cg_solve, tolerance
+ *   min(0.5, rtol / (2 max_j relres_j)));  x += d;  repeat,
+ * at most 10 times, until every system's relative residual is <= rtol.
+ *   p       FP64 plan; its stream runs the residuals.
+ *   lo      FP32 plan over the same points (same instances, kernel, order
+ *           and device; only n, d, device and instance offsets are checked).
+ *   b, x    device, n x nrhs doubles; x on entry the initial guess, on exit
+ *           the solution (the last iterate if not converged).
+ *   maxit   cap on the FP32 CG iterations over all steps, >= 1.
+ *   iters   host, total FP32 CG iterations (may be NULL).
+ *   outer   host, refinement steps taken, each one FP64 fkt_mvm (may be NULL;
+ *           one more FP64 fkt_mvm computes the first residual).
+ *   relres  host, max over systems of the final FP64 relative residual (may
+ *           be NULL).
+ * Errors: as fkt_cg_solve; FKT_EINVAL if the plans' precisions or shapes do
+ * not pair up; FKT_ENOTCONV when maxit or the step cap is reached first.
+ */
+fkt_status fkt_cg_solve_refined(fkt_plan_t p, fkt_plan_t lo, double sigma2, const double *b, double *x, int nrhs,
+                                double rtol, int maxit, int precond, int *iters, int *outer, double *relres);
 
 /* Release the plan and its device memory (NULL is a no-op). Waits for the
  * plan's stream first. */

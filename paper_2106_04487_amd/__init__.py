@@ -8,6 +8,8 @@ Entry points mirror the C ABI (include/fkt.h):
     fkt_plan(points, kernel, leaf_size, order, ...) -> Plan
     fkt_mvm(plan, x, y=None) -> y
     fkt_cg_solve(plan, sigma2, b, x0=None, ...) -> (x, iters, relres)
+    fkt_cg_solve64(plan, sigma2, b, x0=None, ...) -> (x, iters, relres), FP64 b and x
+    fkt_cg_solve_refined(plan64, plan32, sigma2, b, x0=None, ...) -> (x, iters, outer, relres)
     fkt_destroy(plan)
 """
 from __future__ import annotations
@@ -36,7 +38,9 @@ PRECISIONS = {"f64": 0, "f32": 1}
 STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "FKT_EUNSUPPORTED",
           5: "FKT_ENOTCONV"}
 
-EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_destroy", "fkt_last_error",
+EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_cg_solve64", "fkt_cg_solve_refined",
+            "fkt_destroy",
+            "fkt_last_error",
             "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
             "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
@@ -78,6 +82,12 @@ _lib.fkt_mvm.argtypes = [_P, _P, _P, ctypes.c_int]
 _lib.fkt_cg_solve.restype = ctypes.c_int
 _lib.fkt_cg_solve.argtypes = [_P, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+_lib.fkt_cg_solve64.restype = ctypes.c_int
+_lib.fkt_cg_solve64.argtypes = _lib.fkt_cg_solve.argtypes
+_lib.fkt_cg_solve_refined.restype = ctypes.c_int
+_lib.fkt_cg_solve_refined.argtypes = [_P, _P, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_double)]
 _lib.fkt_destroy.argtypes = [_P]
 _lib.fkt_last_error.restype = ctypes.c_char_p
 _lib.fkt_plan_info.restype = ctypes.c_int
@@ -318,11 +328,11 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     return Plan(h, n, d, prec, device, sh)
 
 
-def _device_matrix(plan: Plan, t, name):
+def _device_matrix(plan: Plan, t, name, f64=False):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a torch tensor on the GPU")
-    want = torch.float32 if plan.prec == "f32" else torch.float64
+    want = torch.float32 if plan.prec == "f32" and not f64 else torch.float64
     if t.dtype != want:
         raise TypeError(f"{name} must be {want} for a {plan.prec} plan")
     if t.shape[0] != plan.n or t.dim() not in (1, 2):
@@ -348,25 +358,56 @@ PRECONDS = {"none": 0, "block_jacobi": 1, "learned": 2}
 
 
 def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,
-                 precond=0):
+                 precond=0, _f64=False):
     """Solve (K~ + sigma2 I) x = b by CG. precond: 0/"none", 1/"block_jacobi",
     2/"learned". Returns (x, iters, relres); if maxit is reached raises
     FktError(FKT_ENOTCONV) carrying .x, .iters, .relres."""
     precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
     import torch
-    b = _device_matrix(plan, b, "b")
-    x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0").clone()
+    b = _device_matrix(plan, b, "b", _f64)
+    x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0", _f64).clone()
     nrhs = 1 if b.dim() == 1 else b.shape[1]
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
-    st = _lib.fkt_cg_solve(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol), int(maxit),
-                           int(precond), ctypes.byref(it), ctypes.byref(rr))
+    fn = _lib.fkt_cg_solve64 if _f64 else _lib.fkt_cg_solve
+    st = fn(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol), int(maxit), int(precond),
+            ctypes.byref(it), ctypes.byref(rr))
     if st == 5:  # FKT_ENOTCONV: x holds the last iterate
         err = FktError(st, _lib.fkt_last_error().decode())
         err.x, err.iters, err.relres = x, it.value, rr.value
         raise err
     _check(st)
     return x, it.value, rr.value
+
+
+def fkt_cg_solve64(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,
+                   precond=0):
+    """fkt_cg_solve with FP64 b and x for any plan: on an FP32 plan the MVMs
+    run in FP32 and the solution is returned in FP64 (mixed precision)."""
+    return fkt_cg_solve(plan, sigma2, b, x0, rtol=rtol, maxit=maxit, precond=precond, _f64=True)
+
+
+def fkt_cg_solve_refined(plan: Plan, lo: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6,
+                         maxit: int = 1000, precond=0):
+    """Mixed-precision iterative refinement: FP64 residuals on plan, FP32 CG
+    corrections on lo (an FP32 plan over the same points). b, x: FP64.
+    Returns (x, iters, outer, relres) with relres the FP64 relative residual;
+    raises FktError(FKT_ENOTCONV) carrying .x, .iters, .outer, .relres."""
+    precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
+    import torch
+    b = _device_matrix(plan, b, "b")
+    x = torch.zeros_like(b) if x0 is None else _device_matrix(plan, x0, "x0").clone()
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    it, ot, rr = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _lib.fkt_cg_solve_refined(plan.handle, lo.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs,
+                                   float(rtol), int(maxit), int(precond), ctypes.byref(it), ctypes.byref(ot),
+                                   ctypes.byref(rr))
+    if st == 5:
+        err = FktError(st, _lib.fkt_last_error().decode())
+        err.x, err.iters, err.outer, err.relres = x, it.value, ot.value, rr.value
+        raise err
+    _check(st)
+    return x, it.value, ot.value, rr.value
 
 
 def fkt_learn_nparams() -> int:

@@ -18,6 +18,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDotBlocks = 512;
+constexpr int kRefineSteps = 10;  // iterative refinement: outer steps at most
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_to_f64(int64_t m, const T* __restrict__ a, double* __restrict__ b)
@@ -42,14 +43,22 @@ __global__ __launch_bounds__(kThreads) void k_add_shift(int64_t m, const T* __re
     if (i < m) q[i] = (double)kp[i] + sigma2 * p[i];
 }
 
-// partial[blk][c] = sum over rows i in block-stride of a[i][c] * b[i][c]
-__global__ __launch_bounds__(kThreads) void k_dot_partial(int64_t n, int nrhs, const double* __restrict__ a,
-                                                          const double* __restrict__ b, double* __restrict__ partial)
+// Systems: the rows of segment s (rows [seg_off[s], seg_off[s + 1]): one
+// instance of a batched plan, or all rows) and column c form system
+// s * nrhs + c, with its own CG scalars.
+// partial[s][blk][c] = sum over the rows of segment s in block-stride of a[i][c] * b[i][c]
+// (bps blocks per segment: block blockIdx.x is block blockIdx.x % bps of
+// segment blockIdx.x / bps)
+__global__ __launch_bounds__(kThreads) void k_dot_partial(int nrhs, int bps, const int64_t* __restrict__ seg_off,
+                                                          const double* __restrict__ a, const double* __restrict__ b,
+                                                          double* __restrict__ partial)
 {
     __shared__ double sh[kThreads];
+    const int seg = blockIdx.x / bps, blk = blockIdx.x % bps;
+    const int64_t r0 = seg_off[seg], r1 = seg_off[seg + 1];
     for (int c = 0; c < nrhs; ++c) {
         double s = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        for (int64_t i = r0 + (int64_t)blk * kThreads + threadIdx.x; i < r1; i += (int64_t)bps * kThreads)
             s += a[i * nrhs + c] * b[i * nrhs + c];
         sh[threadIdx.x] = s;
         __syncthreads();
@@ -57,25 +66,42 @@ __global__ __launch_bounds__(kThreads) void k_dot_partial(int64_t n, int nrhs, c
             if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0) partial[blockIdx.x * nrhs + c] = sh[0];
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nrhs + c] = sh[0];
         __syncthreads();
     }
 }
 
-// y[i][c] += alpha[c] * x[i][c]
-__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, int nrhs, const double* __restrict__ alpha,
-                                                   const double* __restrict__ x, double* __restrict__ y)
+// x[i] += d[i]
+__global__ __launch_bounds__(kThreads) void k_axpy1(int64_t m, const double* __restrict__ d, double* __restrict__ x)
 {
-    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (g < n * nrhs) y[g] += alpha[g % nrhs] * x[g];
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < m) x[i] += d[i];
 }
 
-// p[i][c] = r[i][c] + beta[c] * p[i][c]
-__global__ __launch_bounds__(kThreads) void k_xpby(int64_t n, int nrhs, const double* __restrict__ r,
-                                                   const double* __restrict__ beta, double* __restrict__ p)
+// system of element g = i * nrhs + c (row_seg: segment of each row, or NULL
+// for one segment)
+__device__ __forceinline__ int64_t system_of(int64_t g, int nrhs, const int* __restrict__ row_seg)
+{
+    const int c = (int)(g % nrhs);
+    return row_seg ? (int64_t)row_seg[g / nrhs] * nrhs + c : c;
+}
+
+// y[i][c] += alpha[system] * x[i][c]
+__global__ __launch_bounds__(kThreads) void k_axpy(int64_t n, int nrhs, const int* __restrict__ row_seg,
+                                                   const double* __restrict__ alpha, const double* __restrict__ x,
+                                                   double* __restrict__ y)
 {
     const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (g < n * nrhs) p[g] = r[g] + beta[g % nrhs] * p[g];
+    if (g < n * nrhs) y[g] += alpha[system_of(g, nrhs, row_seg)] * x[g];
+}
+
+// p[i][c] = r[i][c] + beta[system] * p[i][c]
+__global__ __launch_bounds__(kThreads) void k_xpby(int64_t n, int nrhs, const int* __restrict__ row_seg,
+                                                   const double* __restrict__ r, const double* __restrict__ beta,
+                                                   double* __restrict__ p)
+{
+    const int64_t g = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (g < n * nrhs) p[g] = r[g] + beta[system_of(g, nrhs, row_seg)] * p[g];
 }
 
 // r = b - q
@@ -141,32 +167,43 @@ namespace fkt {
 constexpr double kFallbackGrow = 10.0;
 constexpr int kFallbackStall = 250;
 
-template <typename T>
-static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const T* b_in, T* x_io, int nrhs, double rtol,
+// T: element type of the MVM (the plan's precision); TI: element type of b
+// and x at the boundary (T, or double for a mixed-precision solve on an FP32
+// plan, whose iterate then never passes through FP32)
+template <typename T, typename TI>
+static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const TI* b_in, TI* x_io, int nrhs, double rtol,
                            int maxit, int precond, int* iters, double* relres, int64_t* fallback_at)
 {
     const int64_t n = v.n, m = n * nrhs;
+    // systems: (instance, column) pairs, each with its own CG scalars; a
+    // converged system is frozen (alpha = beta = 0) while the others go on
+    const int nseg = v.nseg, nsys = nseg * nrhs;
+    const int bps = std::max(8, kDotBlocks / nseg);  // dot blocks per instance
     hipStream_t s = v.stream;
     Buf buf;
     double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr;
     T *op_in, *op_out;
     hipError_t e;
     if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &z)) ||
-        (e = buf.get(m, &p)) || (e = buf.get(m, &q)) || (e = buf.get((size_t)kDotBlocks * nrhs, &part)) ||
-        (e = buf.get(3 * nrhs, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)) ||
+        (e = buf.get(m, &p)) || (e = buf.get(m, &q)) || (e = buf.get((size_t)nseg * bps * nrhs, &part)) ||
+        (e = buf.get((size_t)3 * nsys, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)) ||
         (precond == 2 && fallback_at && (e = buf.get(m, &xbest))))
         return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "cg work buffers");
     if (fallback_at) *fallback_at = -1;
 
-    std::vector<double> hpart((size_t)kDotBlocks * nrhs), hcoef(3 * nrhs);
+    std::vector<double> hpart((size_t)nseg * bps * nrhs), hcoef((size_t)3 * nsys);
+    // out[seg * nrhs + c] = (a1, a2) over the rows of instance seg, column c
     auto dots = [&](const double* a1, const double* a2, std::vector<double>& out) -> bool {
-        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(kThreads), 0, s, n, nrhs, a1, a2, part);
+        hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)(nseg * bps)), dim3(kThreads), 0, s, nrhs, bps, v.seg_off, a1,
+                           a2, part);
         if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
             return false;
         if (hipStreamSynchronize(s) != hipSuccess) return false;
-        out.assign(nrhs, 0.0);
-        for (int k = 0; k < kDotBlocks; ++k)
-            for (int c2 = 0; c2 < nrhs; ++c2) out[c2] += hpart[(size_t)k * nrhs + c2];
+        out.assign(nsys, 0.0);
+        for (int g = 0; g < nseg; ++g)
+            for (int k = 0; k < bps; ++k)
+                for (int c2 = 0; c2 < nrhs; ++c2)
+                    out[(size_t)g * nrhs + c2] += hpart[((size_t)g * bps + k) * nrhs + c2];
         return true;
     };
     auto apply = [&](const double* in, double* out) -> fkt_status {
@@ -191,8 +228,8 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         return hipMemcpyAsync(out, in, sizeof(double) * m, hipMemcpyDeviceToDevice, s) == hipSuccess;
     };
 
-    hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, b_in, b);
-    hipLaunchKernelGGL((k_to_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const T*)x_io, x);
+    hipLaunchKernelGGL((k_to_f64<TI>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, b_in, b);
+    hipLaunchKernelGGL((k_to_f64<TI>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const TI*)x_io, x);
     std::vector<double> bb, rr, rz, pq, rz_new;
     // r = b - A x, z = M r, p = z, rz = (r, z), rr = (r, r)
     auto start = [&]() -> fkt_status {
@@ -208,12 +245,13 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     if (!dots(b, b, bb)) return cg_set_error(FKT_EDEVICE, "cg reduction");
     fkt_status st = start();
     if (st != FKT_OK) return st;
+    auto relres_of = [&](const std::vector<double>& rv, int j) {
+        const double den = bb[j] > 0.0 ? std::sqrt(bb[j]) : 1.0;
+        return std::sqrt(std::max(rv[j], 0.0)) / den;
+    };
     auto worst = [&](const std::vector<double>& rv) {
         double w = 0.0;
-        for (int c2 = 0; c2 < nrhs; ++c2) {
-            const double den = bb[c2] > 0.0 ? std::sqrt(bb[c2]) : 1.0;
-            w = std::max(w, std::sqrt(std::max(rv[c2], 0.0)) / den);
-        }
+        for (int j = 0; j < nsys; ++j) w = std::max(w, relres_of(rv, j));
         return w;
     };
     int it = 0;
@@ -238,21 +276,23 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         if (!dots(p, q, pq)) return cg_set_error(FKT_EDEVICE, "cg reduction");
         // coef = [alpha | -alpha | beta]; host slots are rewritten only after
         // a stream synchronisation (inside dots) has retired the copy.
-        for (int c2 = 0; c2 < nrhs; ++c2) {
-            hcoef[c2] = (pq[c2] != 0.0) ? rz[c2] / pq[c2] : 0.0;
-            hcoef[nrhs + c2] = -hcoef[c2];
+        std::vector<char> frozen(nsys);
+        for (int j = 0; j < nsys; ++j) {
+            frozen[j] = relres_of(rr, j) <= rtol;
+            hcoef[j] = (!frozen[j] && pq[j] != 0.0) ? rz[j] / pq[j] : 0.0;
+            hcoef[nsys + j] = -hcoef[j];
         }
-        if (hipMemcpyAsync(coef, hcoef.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s) != hipSuccess)
+        if (hipMemcpyAsync(coef, hcoef.data(), sizeof(double) * 2 * nsys, hipMemcpyHostToDevice, s) != hipSuccess)
             return cg_set_error(FKT_EDEVICE, "cg copy");
-        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef, p, x);
-        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, coef + nrhs, q, r);
+        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, v.row_seg, coef, p, x);
+        hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, v.row_seg, coef + nsys, q, r);
         if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
         if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
-        for (int c2 = 0; c2 < nrhs; ++c2) hcoef[2 * nrhs + c2] = rz[c2] != 0.0 ? rz_new[c2] / rz[c2] : 0.0;
-        if (hipMemcpyAsync(coef + 2 * nrhs, hcoef.data() + 2 * nrhs, sizeof(double) * nrhs, hipMemcpyHostToDevice, s) !=
+        for (int j = 0; j < nsys; ++j) hcoef[2 * nsys + j] = (!frozen[j] && rz[j] != 0.0) ? rz_new[j] / rz[j] : 0.0;
+        if (hipMemcpyAsync(coef + 2 * nsys, hcoef.data() + 2 * nsys, sizeof(double) * nsys, hipMemcpyHostToDevice, s) !=
             hipSuccess)
             return cg_set_error(FKT_EDEVICE, "cg copy");
-        hipLaunchKernelGGL(k_xpby, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, z, coef + 2 * nrhs, p);
+        hipLaunchKernelGGL(k_xpby, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, v.row_seg, z, coef + 2 * nsys, p);
         rz = rz_new;
         ++it;
         res = worst(rr);
@@ -263,7 +303,7 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
                 return cg_set_error(FKT_EDEVICE, "cg copy");
         }
     }
-    hipLaunchKernelGGL((k_from_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, x, x_io);
+    hipLaunchKernelGGL((k_from_f64<TI>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, x, x_io);
     if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
     if (iters) *iters = it;
     if (relres) *relres = res;
@@ -272,7 +312,8 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 }
 
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
-                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at)
+                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
+                         bool io64)
 {
     if (precond < 0 || precond > 2 || (precond == 2 && !v.learn))
         return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
@@ -289,11 +330,83 @@ fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const
     }
     if (precond == 2 && learn_prepare_filter(v.learn) != hipSuccess)
         return cg_set_error(FKT_EDEVICE, "learned preconditioner forward pass");
+    if (v.prec == 1 && io64)
+        return cg_typed<float, double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters,
+                                       relres, fallback_at);
     if (v.prec == 1)
-        return cg_typed<float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters, relres,
-                               fallback_at);
-    return cg_typed<double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters, relres,
-                            fallback_at);
+        return cg_typed<float, float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters,
+                                      relres, fallback_at);
+    return cg_typed<double, double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters,
+                                    relres, fallback_at);
+}
+
+// Mixed-precision iterative refinement: residuals r = b - (K~ + sigma2 I) x
+// of the FP64 plan P (view v), corrections from CG on the FP32 plan through
+// inner(r, d, inner_rtol, maxit_left, &its), which solves for d from a zero
+// start. The inner tolerance is what the next step needs: half of rtol over
+// the current worst relative residual (at most 0.5), so the first solve goes
+// to about rtol and the later ones only remove the FP32 operator's error.
+fkt_status cg_refine_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const double* b, double* x, int nrhs,
+                          double rtol, int maxit, const CgInner& inner, int* iters, int* outer, double* relres)
+{
+    const int64_t n = v.n, m = n * nrhs;
+    const int nseg = v.nseg, nsys = nseg * nrhs;
+    const int bps = std::max(8, kDotBlocks / nseg);
+    hipStream_t s = v.stream;
+    Buf buf;
+    double *r, *d, *q, *part;
+    hipError_t e;
+    if ((e = buf.get(m, &r)) || (e = buf.get(m, &d)) || (e = buf.get(m, &q)) ||
+        (e = buf.get((size_t)nseg * bps * nrhs, &part)))
+        return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "refinement work buffers");
+    std::vector<double> hpart((size_t)nseg * bps * nrhs), bb, rr;
+    auto dots = [&](const double* a1, std::vector<double>& out) -> bool {
+        hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)(nseg * bps)), dim3(kThreads), 0, s, nrhs, bps, v.seg_off, a1,
+                           a1, part);
+        if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        out.assign(nsys, 0.0);
+        for (int g = 0; g < nseg; ++g)
+            for (int k = 0; k < bps; ++k)
+                for (int c2 = 0; c2 < nrhs; ++c2)
+                    out[(size_t)g * nrhs + c2] += hpart[((size_t)g * bps + k) * nrhs + c2];
+        return true;
+    };
+    // r = b - (K~ x + sigma2 x) in FP64; returns the worst relative residual
+    auto residual = [&](double* worst) -> fkt_status {
+        const fkt_status st0 = fkt_mvm(P, x, q, nrhs);
+        if (st0 != FKT_OK) return st0;
+        hipLaunchKernelGGL((k_add_shift<double>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, q, x, sigma2, q);
+        hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
+        if (!dots(r, rr)) return cg_set_error(FKT_EDEVICE, "refinement reduction");
+        double w = 0.0;
+        for (int j = 0; j < nsys; ++j)
+            w = std::max(w, std::sqrt(std::max(rr[j], 0.0)) / (bb[j] > 0.0 ? std::sqrt(bb[j]) : 1.0));
+        *worst = w;
+        return FKT_OK;
+    };
+    if (!dots(b, bb)) return cg_set_error(FKT_EDEVICE, "refinement reduction");
+    double res = 0.0;
+    fkt_status st = residual(&res);
+    if (st != FKT_OK) return st;
+    int its = 0, steps = 0;
+    while (res > rtol && its < maxit && steps < kRefineSteps) {
+        if (hipMemsetAsync(d, 0, sizeof(double) * m, s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "memset");
+        if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "refinement sync");
+        int it = 0;
+        st = inner(r, d, std::min(0.5, 0.5 * rtol / res), maxit - its, &it);
+        its += it;
+        ++steps;
+        if (st != FKT_OK && st != FKT_ENOTCONV) return st;
+        hipLaunchKernelGGL(k_axpy1, dim3(grid_of(m)), dim3(kThreads), 0, s, m, d, x);
+        if ((st = residual(&res)) != FKT_OK) return st;
+    }
+    if (iters) *iters = its;
+    if (outer) *outer = steps;
+    if (relres) *relres = res;
+    if (res > rtol) return cg_set_error(FKT_ENOTCONV, "refinement stopped before rtol");
+    return FKT_OK;
 }
 
 }  // namespace fkt

@@ -50,7 +50,10 @@ struct DeviceScope {
 namespace fkt {
 fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
-                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at);
+                         double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
+                         bool io64);
+fkt_status cg_refine_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const double* b, double* x, int nrhs,
+                          double rtol, int maxit, const CgInner& inner, int* iters, int* outer, double* relres);
 }  // namespace fkt
 
 struct fkt_plan_s {
@@ -68,6 +71,11 @@ struct fkt_plan_s {
     fkt::DevPlan dp{};
     fkt::DevWork wk{};
     fkt::DevMrhs mr{};   // many-RHS layout (opt.mrhs != 0)
+    // CG systems: one per instance (row ranges in user order), row -> instance
+    // (NULL for one instance)
+    int cg_nseg = 1;
+    const int64_t* cg_seg_off = nullptr;
+    const int32_t* cg_row_seg = nullptr;
     struct Ev7 { hipEvent_t e[7]; };
     std::vector<Ev7> prof;   // events of profiled column passes not yet summed
     double prof_ms[5] = {0, 0, 0, 0, 0};
@@ -187,6 +195,18 @@ static fkt_status upload_plan(fkt_plan_t P)
         FKT_UP(p32, a.pts32);
     }
     FKT_UP(T.perm, a.perm);
+    {
+        // instances own the contiguous user-order rows [inst_begin[i], inst_begin[i + 1])
+        const size_t ni = T.inst_begin.size() - 1;
+        P->cg_nseg = (int)ni;
+        FKT_UP(T.inst_begin, P->cg_seg_off);
+        if (ni > 1) {
+            std::vector<int32_t> rs((size_t)P->n);
+            for (size_t i = 0; i < ni; ++i)
+                std::fill(rs.begin() + T.inst_begin[i], rs.begin() + T.inst_begin[i + 1], (int32_t)i);
+            FKT_UP(rs, P->cg_row_seg);
+        }
+    }
     FKT_UP(L.blk_begin, a.blk_begin);
     FKT_UP(L.blk_count, a.blk_count);
     FKT_UP(L.near_tgt, a.near_tgt);
@@ -541,7 +561,7 @@ static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
 // fkt_cg_solve without (fallback_at NULL) or with the learned filter's
 // block-Jacobi fallback; the judge runs the filter on its own.
 static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
-                           int precond, int* iters, double* relres, int64_t* fallback_at)
+                           int precond, int* iters, double* relres, int64_t* fallback_at, bool io64 = false)
 {
     if (!P) return fail(FKT_EINVAL, "plan is NULL");
     if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_cg_solve");
@@ -593,15 +613,50 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
         for (int32_t c : lc) P->bj_maxleaf = std::max(P->bj_maxleaf, (int)c);
         P->bj_sigma2 = sigma2;
     }
-    fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream, P->dp.perm, P->bj_nleaf,
-                      P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off, P->bj_inv, P->learn};
-    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at);
+    fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
+                      P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
+                      P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
+    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at, io64);
 }
 
 fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
                         int precond, int* iters, double* relres)
 {
     return cg_entry(P, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, P ? &P->st.cg_fallback_iter : nullptr);
+}
+
+fkt_status fkt_cg_solve64(fkt_plan_t P, double sigma2, const double* b, double* x, int nrhs, double rtol, int maxit,
+                          int precond, int* iters, double* relres)
+{
+    return cg_entry(P, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, P ? &P->st.cg_fallback_iter : nullptr,
+                    true);
+}
+
+fkt_status fkt_cg_solve_refined(fkt_plan_t P, fkt_plan_t Q, double sigma2, const double* b, double* x, int nrhs,
+                                double rtol, int maxit, int precond, int* iters, int* outer, double* relres)
+{
+    if (!P || !Q) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device || !Q->on_device) return fail(FKT_EDEVICE, "host-only plans cannot run fkt_cg_solve_refined");
+    if (P->opt.prec != FKT_F64 || Q->opt.prec != FKT_F32)
+        return fail(FKT_EINVAL, "fkt_cg_solve_refined takes an FP64 plan and an FP32 plan");
+    if (P->n != Q->n || P->d != Q->d || P->opt.device != Q->opt.device || P->T.inst_begin != Q->T.inst_begin)
+        return fail(FKT_EINVAL, "the two plans must cover the same points, instances and device");
+    if (!b || !x) return fail(FKT_EINVAL, "b or x is NULL");
+    if (nrhs < 1 || nrhs > 64) return fail(FKT_EINVAL, "nrhs must be in [1, 64]");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be >= 0");
+    if (!(rtol > 0.0)) return fail(FKT_EINVAL, "rtol must be > 0");
+    if (maxit < 1) return fail(FKT_EINVAL, "maxit must be >= 1");
+    if (precond < 0 || precond > 2) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    const fkt::CgInner inner = [&](const double* r, double* d, double inner_rtol, int left, int* it) {
+        double rr = 0.0;
+        return cg_entry(Q, sigma2, r, d, nrhs, inner_rtol, left, precond, it, &rr, &Q->st.cg_fallback_iter, true);
+    };
+    fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
+                      P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
+                      P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
+    return fkt::cg_refine_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, inner, iters, outer, relres);
 }
 
 static fkt_status learn_entry(fkt_plan_t P, double sigma2)

@@ -72,6 +72,83 @@ def test_graph_replays_match_eager(F, prec, mrhs, nrhs):
     plan.close()
 
 
+@pytest.mark.parametrize("prec,true_tol", [("f64", 1e-5), ("f32", 1e-4), ("mixed", 1e-4)])
+@pytest.mark.parametrize("precond", ["none", "block_jacobi"])
+def test_batch_cg_solves_every_instance(F, prec, true_tol, precond):
+    """The operator of a batched plan is block diagonal: each instance (and
+    column) is its own CG system. Every instance must meet rtol on its own
+    rows (checked against the oracle's operator), and the batched solve must
+    take no more iterations than the slowest instance solved alone ("mixed":
+    FP32 plan, FP64 b and x through fkt_cg_solve64). The
+    operator is made accurate (theta 0.35, p 6) so that CG's recurrences
+    hold for K~, which is symmetric only up to the expansion error."""
+    import torch
+    sizes = [1500, 1, 64, 3000, 0, 777]
+    X, off = W.batched_instances(sizes, 3, 930)
+    leaf, p, theta, sig2, rtol = 64, 6, 0.35, 0.1, 1e-6
+    b = W.normal_rhs(X.shape[0], 2, 931)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    pprec = "f64" if prec == "f64" else "f32"
+    solve = F.fkt_cg_solve64 if prec == "mixed" else F.fkt_cg_solve
+    plan = F.fkt_plan_batch((X, off), "ratquad", leaf, p, theta=theta, prec=pprec, **KW)
+    xb, itb, rrb = solve(plan, sig2, torch.as_tensor(b, dtype=dt, device="cuda"), rtol=rtol, maxit=2000,
+                         precond=precond)
+    plan.close()
+    xb = xb.double().cpu().numpy()
+    assert rrb <= rtol
+    its = []
+    for i in range(len(sizes)):
+        a0, a1 = off[i], off[i + 1]
+        if a1 == a0:
+            continue
+        Xi, bi, xi = X[a0:a1], b[a0:a1], xb[a0:a1]
+        Kx = oracle.fkt_alg1(oracle.Tree(Xi, leaf), xi, "ratquad", theta, p, **OKW)
+        res = np.linalg.norm(bi - Kx - sig2 * xi, axis=0) / np.linalg.norm(bi, axis=0)
+        assert res.max() <= true_tol, (i, sizes[i], res)
+        pi = F.fkt_plan(Xi, "ratquad", leaf, p, theta=theta, prec=pprec, **KW)
+        xs, it, _ = solve(pi, sig2, torch.as_tensor(bi, dtype=dt, device="cuda"), rtol=rtol, maxit=2000,
+                          precond=precond)
+        pi.close()
+        its.append(it)
+        xs = xs.double().cpu().numpy()
+        e = np.linalg.norm(xi - xs) / np.linalg.norm(xs)
+        assert e <= 100 * true_tol, (i, sizes[i], e)
+    print("batched iterations", itb, "per instance", its)
+    assert itb <= max(its) + 2 + max(its) // 20
+
+
+def test_batch_refined_solve_meets_fp64_residual(F):
+    """Iterative refinement on a batched plan: FP32 CG corrections, FP64
+    residuals. Every instance meets 1e-6 under the oracle's operator (the
+    same truncation as the FP64 plan), where FP32 CG alone stops near the
+    FP32 operator's error."""
+    import torch
+    sizes = [1500, 1, 64, 3000, 0, 777]
+    X, off = W.batched_instances(sizes, 3, 930)
+    leaf, p, theta, sig2, rtol = 64, 6, 0.35, 0.1, 1e-6
+    b = W.normal_rhs(X.shape[0], 2, 931)
+    p64 = F.fkt_plan_batch((X, off), "ratquad", leaf, p, theta=theta, prec="f64", **KW)
+    p32 = F.fkt_plan_batch((X, off), "ratquad", leaf, p, theta=theta, prec="f32", **KW)
+    bt = torch.as_tensor(b, device="cuda")
+    x, it, outer, rr = F.fkt_cg_solve_refined(p64, p32, sig2, bt, rtol=rtol, maxit=2000, precond="block_jacobi")
+    print(f"refined: {it} FP32 iterations, {outer} steps, FP64 relres {rr:.2e}")
+    assert rr <= rtol and 1 <= outer <= 10
+    x = x.cpu().numpy()
+    for i in range(len(sizes)):
+        a0, a1 = off[i], off[i + 1]
+        if a1 == a0:
+            continue
+        Xi, bi, xi = X[a0:a1], b[a0:a1], x[a0:a1]
+        Kx = oracle.fkt_alg1(oracle.Tree(Xi, leaf), xi, "ratquad", theta, p, **OKW)
+        res = np.linalg.norm(bi - Kx - sig2 * xi, axis=0) / np.linalg.norm(bi, axis=0)
+        assert res.max() <= 1.1 * rtol, (i, sizes[i], res)
+    # the second plan must be the FP32 one
+    with pytest.raises(F.FktError):
+        F.fkt_cg_solve_refined(p64, p64, sig2, bt)
+    p64.close()
+    p32.close()
+
+
 def test_autotuner_picks_a_candidate(F):
     X, off = W.batched_instances([3000, 500, 8000], 3, 920)
     best, ms = F.fkt_autotune_leaf((X, off), "ratquad", 4, [32, 64, 128, 256], nrhs=4, reps=2, theta=0.5,

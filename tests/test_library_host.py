@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     src = open(os.path.join(ROOT, "include", "fkt.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fkt_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fkt_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol():
