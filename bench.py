@@ -267,7 +267,7 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
 MRHS_MODES = {"columns_f32": None, "mfma_f32": "f32", "mfma_bf16": "bf16"}
 
 
-def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0):
+def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0, pcs=("none", "block_jacobi")):
     """Solves (K~ + sigma2 I) x = b on the first ninst instances of the
     batched workload (rational quadratic, d = 3): one CG call on the forest
     plan (every instance its own CG system, all advanced by one MVM per
@@ -316,7 +316,7 @@ def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0):
         plan = plan64 if prec == "f64" else F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta,
                                                                prec=prec, **kw)
         # FP32 plans: FP32 MVMs, FP64 b, CG vectors and solution (fkt_cg_solve64)
-        for pc in ("none", "block_jacobi"):
+        for pc in pcs:
             x, it, rr, sec = cg(plan, b, pc, solve=F.fkt_cg_solve64)
             x = x.double()
             r = (b - F.fkt_mvm(plan64, x) - sig2 * x).cpu().numpy()
@@ -462,10 +462,11 @@ def main():
         # the workload's length scale 0.3, and 0.1 where per-leaf preconditioning has something to act on
         gp = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
 
-    batch = mrhs = None
+    batch = mrhs = bsolve = None
     if not a.no_variants:
         batch = batch_leg(F, torch, 3, a.batch_theta, min(200, max(a.err_targets // 10, 50)), a.batch_leaf,
                           not a.batch_no_per_instance)
+        bsolve = batch_solve_leg(F, torch, 32, a.batch_theta, pcs=("none",))
         mrhs = mrhs_leg(F, torch, 2, a.mrhs_theta, min(a.err_targets, 500), tuple(a.mrhs_modes.split(",")))
 
     cpu = None
@@ -503,6 +504,7 @@ def main():
         "variants": variants,
         "gp_solve": gp,
         "batched_instances": batch,
+        "batched_solve": bsolve,
         "many_rhs": mrhs,
     }
     print(json.dumps(out))
