@@ -113,6 +113,31 @@ def test_invalid_arguments():
     assert "host-only" in F.last_error()
 
 
+def test_solve_entry_points_reject_host_plans():
+    """The FP64-in/out and refinement solves check their plans before any
+    device work: NULL plans are invalid, host-only plans cannot solve."""
+    EINVAL, EDEVICE = 1, 3
+    X = W.uniform_cube(100, 3, 5)
+    p = F.fkt_plan(X, "gaussian", 16, 4, device=None)
+    q = F.fkt_plan(X, "gaussian", 16, 4, device=None, prec="f32")
+    lib = ctypes.CDLL(F.LIB_PATH)
+    P, D, I = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    lib.fkt_cg_solve64.restype = I
+    lib.fkt_cg_solve64.argtypes = [P, D, P, P, I, D, I, I, P, P]
+    lib.fkt_cg_solve_refined.restype = I
+    lib.fkt_cg_solve_refined.argtypes = [P, P, D, P, P, I, D, I, I, P, P, P]
+    b = (ctypes.c_double * 100)()
+    x = (ctypes.c_double * 100)()
+    ab, ax = ctypes.addressof(b), ctypes.addressof(x)
+    assert lib.fkt_cg_solve64(p.handle, 0.1, ab, ax, 1, 1e-6, 10, 0, None, None) == EDEVICE
+    assert "host-only" in F.last_error()
+    assert lib.fkt_cg_solve_refined(None, q.handle, 0.1, ab, ax, 1, 1e-6, 10, 0, None, None, None) == EINVAL
+    assert lib.fkt_cg_solve_refined(p.handle, q.handle, 0.1, ab, ax, 1, 1e-6, 10, 0, None, None, None) == EDEVICE
+    assert "host-only" in F.last_error()
+    p.close()
+    q.close()
+
+
 def test_duplicate_points_hit_depth_cap():
     X = np.repeat(W.uniform_cube(3, 3, 4), 200, axis=0)
     p = F.fkt_plan(X, "gaussian", 8, 2, lengthscale=0.3, device=None, max_depth=20)
