@@ -162,7 +162,8 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
     F.fkt_learn_params(plan, sig2, params)
     for name in ("none", "block_jacobi", "learned"):
         solve("f32_mvm_" + name, name)
-    # FP32 CG corrections to FP64 residuals: rtol under the FP64 operator
+    # FP32 CG with the residual replaced by the FP64 one: rtol under the
+    # FP64 operator
     for name in ("none", "block_jacobi", "learned"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -175,9 +176,9 @@ def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
             it, outer, rr, ok = e.iters, e.outer, e.relres, False
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
-        out["refined_" + name] = {"iterations_f32": it, "fp64_steps": outer, "relres": rr, "converged": ok,
+        out["refined_" + name] = {"iterations_f32": it, "fp64_replacements": outer, "relres": rr, "converged": ok,
                                   "seconds": sec}
-        print(f"bench: gp solve n={n} refined precond={name}: {it} FP32 iterations, {outer} FP64 steps, "
+        print(f"bench: gp solve n={n} refined precond={name}: {it} FP32 iterations, {outer} FP64 replacements, "
               f"{sec:.2f} s, relres {rr:.2e}", file=sys.stderr, flush=True)
     plan.close()
     plan64.close()
@@ -328,17 +329,17 @@ def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0, pcs
                   f"worst instance {worst:.2e}", file=sys.stderr, flush=True)
         if plan is not plan64:
             plan32 = plan
-    # FP32 CG corrections to FP64 residuals: every instance to rtol under the
-    # FP64 operator
+    # FP32 CG with the residual replaced by the FP64 one: every instance to
+    # rtol under the FP64 operator
     for pc in ("none", "block_jacobi"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, it, outer, rr = F.fkt_cg_solve_refined(plan64, plan32, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
-        out[f"batched_refined_{pc}"] = {"seconds": sec, "iterations_f32": it, "fp64_steps": outer, "relres": rr,
+        out[f"batched_refined_{pc}"] = {"seconds": sec, "iterations_f32": it, "fp64_replacements": outer, "relres": rr,
                                         "speedup_vs_per_instance_f64": secs / sec}
-        print(f"bench: batched solve refined {pc}: {sec:.2f} s, {it} FP32 iterations, {outer} FP64 steps, "
+        print(f"bench: batched solve refined {pc}: {sec:.2f} s, {it} FP32 iterations, {outer} FP64 replacements, "
               f"relres {rr:.2e}", file=sys.stderr, flush=True)
     plan32.close()
     plan64.close()

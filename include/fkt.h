@@ -177,27 +177,27 @@ fkt_status fkt_cg_solve64(fkt_plan_t p, double sigma2, const double *b, double *
 /*
  * fkt_cg_solve_refined -- solve (K~ + sigma2 I) x = b to rtol against the
  * FP64 operator while the CG iterations run on the FP32 one (mixed-precision
- * iterative refinement), for the posterior-mean system of the paper's
- * Gaussian-process regression (eq. gp_posterior). CG on an FP32 operator
- * alone stops at that operator's own error (about 1e-5 relative), so the
- * residual is taken in FP64 and the FP32 solves only supply corrections:
- *   r = b - (K~64 + sigma2 I) x;  solve (K~32 + sigma2 I) d = r by CG from
- *   d = 0 (fkt_cg_solve64 on lo, precond as fkt_cg_solve, tolerance
- *   min(0.5, rtol / (2 max_j relres_j)));  x += d;  repeat,
- * at most 10 times, until every system's relative residual is <= rtol.
- *   p       FP64 plan; its stream runs the residuals.
+ * CG with residual replacement), for the posterior-mean system of the
+ * paper's Gaussian-process regression (eq. gp_posterior). CG on an FP32
+ * operator alone stops at that operator's own error (about 1e-5 relative).
+ * Here CG runs on lo (fkt_cg_solve64: FP32 MVMs, FP64 vectors), and each time
+ * its worst residual has dropped tenfold since the last replacement, or has
+ * reached rtol, the residual is replaced by r = b - (K~64 + sigma2 I) x from
+ * the FP64 plan; the search direction is kept. It stops only when every
+ * system's replaced (true FP64) residual is <= rtol.
+ *   p       FP64 plan; its stream runs the replacement MVMs.
  *   lo      FP32 plan over the same points (same instances, kernel, order
  *           and device; only n, d, device and instance offsets are checked).
+ *           The preconditioner (precond as fkt_cg_solve) is lo's.
  *   b, x    device, n x nrhs doubles; x on entry the initial guess, on exit
  *           the solution (the last iterate if not converged).
- *   maxit   cap on the FP32 CG iterations over all steps, >= 1.
- *   iters   host, total FP32 CG iterations (may be NULL).
- *   outer   host, refinement steps taken, each one FP64 fkt_mvm (may be NULL;
- *           one more FP64 fkt_mvm computes the first residual).
- *   relres  host, max over systems of the final FP64 relative residual (may
- *           be NULL).
+ *   maxit   cap on the CG iterations, >= 1.
+ *   iters   host, CG iterations (one FP32 fkt_mvm each; may be NULL).
+ *   outer   host, residual replacements (one FP64 fkt_mvm each; may be NULL).
+ *   relres  host, max over systems of the final relative residual, the FP64
+ *           one on success (may be NULL).
  * Errors: as fkt_cg_solve; FKT_EINVAL if the plans' precisions or shapes do
- * not pair up; FKT_ENOTCONV when maxit or the step cap is reached first.
+ * not pair up; FKT_ENOTCONV when maxit is reached first.
  */
 fkt_status fkt_cg_solve_refined(fkt_plan_t p, fkt_plan_t lo, double sigma2, const double *b, double *x, int nrhs,
                                 double rtol, int maxit, int precond, int *iters, int *outer, double *relres);

@@ -389,10 +389,11 @@ def fkt_cg_solve64(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6,
 
 def fkt_cg_solve_refined(plan: Plan, lo: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6,
                          maxit: int = 1000, precond=0):
-    """Mixed-precision iterative refinement: FP64 residuals on plan, FP32 CG
-    corrections on lo (an FP32 plan over the same points). b, x: FP64.
-    Returns (x, iters, outer, relres) with relres the FP64 relative residual;
-    raises FktError(FKT_ENOTCONV) carrying .x, .iters, .outer, .relres."""
+    """Mixed-precision CG: FP32 MVMs on lo (an FP32 plan over the same
+    points), residual replaced by plan's FP64 one after every tenfold drop.
+    b, x: FP64. Returns (x, iters, outer = replacements, relres) with relres
+    the FP64 relative residual; raises FktError(FKT_ENOTCONV) carrying .x,
+    .iters, .outer, .relres."""
     precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
     import torch
     b = _device_matrix(plan, b, "b")

@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDotBlocks = 512;
-constexpr int kRefineSteps = 10;  // iterative refinement: outer steps at most
+constexpr double kReplaceDrop = 0.1;  // residual replacement after each drop by this factor
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_to_f64(int64_t m, const T* __restrict__ a, double* __restrict__ b)
@@ -69,13 +69,6 @@ __global__ __launch_bounds__(kThreads) void k_dot_partial(int nrhs, int bps, con
         if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nrhs + c] = sh[0];
         __syncthreads();
     }
-}
-
-// x[i] += d[i]
-__global__ __launch_bounds__(kThreads) void k_axpy1(int64_t m, const double* __restrict__ d, double* __restrict__ x)
-{
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < m) x[i] += d[i];
 }
 
 // system of element g = i * nrhs + c (row_seg: segment of each row, or NULL
@@ -172,7 +165,8 @@ constexpr int kFallbackStall = 250;
 // plan, whose iterate then never passes through FP32)
 template <typename T, typename TI>
 static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const TI* b_in, TI* x_io, int nrhs, double rtol,
-                           int maxit, int precond, int* iters, double* relres, int64_t* fallback_at)
+                           int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
+                           fkt_plan_t P64 = nullptr, const CgPlanView* v64 = nullptr, int* replaced = nullptr)
 {
     const int64_t n = v.n, m = n * nrhs;
     // systems: (instance, column) pairs, each with its own CG scalars; a
@@ -181,13 +175,13 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     const int bps = std::max(8, kDotBlocks / nseg);  // dot blocks per instance
     hipStream_t s = v.stream;
     Buf buf;
-    double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr;
+    double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr, *q64 = nullptr;
     T *op_in, *op_out;
     hipError_t e;
     if ((e = buf.get(m, &b)) || (e = buf.get(m, &x)) || (e = buf.get(m, &r)) || (e = buf.get(m, &z)) ||
         (e = buf.get(m, &p)) || (e = buf.get(m, &q)) || (e = buf.get((size_t)nseg * bps * nrhs, &part)) ||
         (e = buf.get((size_t)3 * nsys, &coef)) || (e = buf.get(m, &op_in)) || (e = buf.get(m, &op_out)) ||
-        (precond == 2 && fallback_at && (e = buf.get(m, &xbest))))
+        (precond == 2 && fallback_at && (e = buf.get(m, &xbest))) || (P64 && (e = buf.get(m, &q64))))
         return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "cg work buffers");
     if (fallback_at) *fallback_at = -1;
 
@@ -256,6 +250,8 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     };
     int it = 0;
     double res = worst(rr);
+    double res_replaced = res;  // worst residual at the last replacement
+    if (replaced) *replaced = 0;
     double best = res;
     int it_best = 0;
     if (xbest && hipMemcpyAsync(xbest, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -288,6 +284,20 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         hipLaunchKernelGGL(k_axpy, dim3(grid_of(m)), dim3(kThreads), 0, s, n, nrhs, v.row_seg, coef + nsys, q, r);
         if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
         if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        if (P64 && (worst(rr) <= rtol || worst(rr) <= kReplaceDrop * res_replaced)) {
+            // residual replacement: r = b - (K~64 + sigma2 I) x on the FP64
+            // plan's stream (this stream is idle after the reductions)
+            st = fkt_mvm(P64, x, q64, nrhs);
+            if (st != FKT_OK) return st;
+            hipLaunchKernelGGL((k_add_shift<double>), dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, q64, x,
+                               sigma2, q64);
+            hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, b, q64, r);
+            if (hipStreamSynchronize(v64->stream) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
+            if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
+            if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+            res_replaced = worst(rr);
+            if (replaced) ++*replaced;
+        }
         for (int j = 0; j < nsys; ++j) hcoef[2 * nsys + j] = (!frozen[j] && rz[j] != 0.0) ? rz_new[j] / rz[j] : 0.0;
         if (hipMemcpyAsync(coef + 2 * nsys, hcoef.data() + 2 * nsys, sizeof(double) * nsys, hipMemcpyHostToDevice, s) !=
             hipSuccess)
@@ -313,7 +323,7 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
-                         bool io64)
+                         bool io64, fkt_plan_t P64, const CgPlanView* v64, int* replaced)
 {
     if (precond < 0 || precond > 2 || (precond == 2 && !v.learn))
         return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
@@ -332,81 +342,12 @@ fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const
         return cg_set_error(FKT_EDEVICE, "learned preconditioner forward pass");
     if (v.prec == 1 && io64)
         return cg_typed<float, double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters,
-                                       relres, fallback_at);
+                                       relres, fallback_at, P64, v64, replaced);
     if (v.prec == 1)
         return cg_typed<float, float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters,
                                       relres, fallback_at);
     return cg_typed<double, double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters,
                                     relres, fallback_at);
-}
-
-// Mixed-precision iterative refinement: residuals r = b - (K~ + sigma2 I) x
-// of the FP64 plan P (view v), corrections from CG on the FP32 plan through
-// inner(r, d, inner_rtol, maxit_left, &its), which solves for d from a zero
-// start. The inner tolerance is what the next step needs: half of rtol over
-// the current worst relative residual (at most 0.5), so the first solve goes
-// to about rtol and the later ones only remove the FP32 operator's error.
-fkt_status cg_refine_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const double* b, double* x, int nrhs,
-                          double rtol, int maxit, const CgInner& inner, int* iters, int* outer, double* relres)
-{
-    const int64_t n = v.n, m = n * nrhs;
-    const int nseg = v.nseg, nsys = nseg * nrhs;
-    const int bps = std::max(8, kDotBlocks / nseg);
-    hipStream_t s = v.stream;
-    Buf buf;
-    double *r, *d, *q, *part;
-    hipError_t e;
-    if ((e = buf.get(m, &r)) || (e = buf.get(m, &d)) || (e = buf.get(m, &q)) ||
-        (e = buf.get((size_t)nseg * bps * nrhs, &part)))
-        return cg_set_error(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE, "refinement work buffers");
-    std::vector<double> hpart((size_t)nseg * bps * nrhs), bb, rr;
-    auto dots = [&](const double* a1, std::vector<double>& out) -> bool {
-        hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)(nseg * bps)), dim3(kThreads), 0, s, nrhs, bps, v.seg_off, a1,
-                           a1, part);
-        if (hipMemcpyAsync(hpart.data(), part, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s) != hipSuccess)
-            return false;
-        if (hipStreamSynchronize(s) != hipSuccess) return false;
-        out.assign(nsys, 0.0);
-        for (int g = 0; g < nseg; ++g)
-            for (int k = 0; k < bps; ++k)
-                for (int c2 = 0; c2 < nrhs; ++c2)
-                    out[(size_t)g * nrhs + c2] += hpart[((size_t)g * bps + k) * nrhs + c2];
-        return true;
-    };
-    // r = b - (K~ x + sigma2 x) in FP64; returns the worst relative residual
-    auto residual = [&](double* worst) -> fkt_status {
-        const fkt_status st0 = fkt_mvm(P, x, q, nrhs);
-        if (st0 != FKT_OK) return st0;
-        hipLaunchKernelGGL((k_add_shift<double>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, q, x, sigma2, q);
-        hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
-        if (!dots(r, rr)) return cg_set_error(FKT_EDEVICE, "refinement reduction");
-        double w = 0.0;
-        for (int j = 0; j < nsys; ++j)
-            w = std::max(w, std::sqrt(std::max(rr[j], 0.0)) / (bb[j] > 0.0 ? std::sqrt(bb[j]) : 1.0));
-        *worst = w;
-        return FKT_OK;
-    };
-    if (!dots(b, bb)) return cg_set_error(FKT_EDEVICE, "refinement reduction");
-    double res = 0.0;
-    fkt_status st = residual(&res);
-    if (st != FKT_OK) return st;
-    int its = 0, steps = 0;
-    while (res > rtol && its < maxit && steps < kRefineSteps) {
-        if (hipMemsetAsync(d, 0, sizeof(double) * m, s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "memset");
-        if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "refinement sync");
-        int it = 0;
-        st = inner(r, d, std::min(0.5, 0.5 * rtol / res), maxit - its, &it);
-        its += it;
-        ++steps;
-        if (st != FKT_OK && st != FKT_ENOTCONV) return st;
-        hipLaunchKernelGGL(k_axpy1, dim3(grid_of(m)), dim3(kThreads), 0, s, m, d, x);
-        if ((st = residual(&res)) != FKT_OK) return st;
-    }
-    if (iters) *iters = its;
-    if (outer) *outer = steps;
-    if (relres) *relres = res;
-    if (res > rtol) return cg_set_error(FKT_ENOTCONV, "refinement stopped before rtol");
-    return FKT_OK;
 }
 
 }  // namespace fkt

@@ -51,9 +51,8 @@ namespace fkt {
 fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st, msg); }
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
-                         bool io64);
-fkt_status cg_refine_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const double* b, double* x, int nrhs,
-                          double rtol, int maxit, const CgInner& inner, int* iters, int* outer, double* relres);
+                         bool io64, fkt_plan_t P64 = nullptr, const CgPlanView* v64 = nullptr,
+                         int* replaced = nullptr);
 }  // namespace fkt
 
 struct fkt_plan_s {
@@ -561,7 +560,8 @@ static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
 // fkt_cg_solve without (fallback_at NULL) or with the learned filter's
 // block-Jacobi fallback; the judge runs the filter on its own.
 static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
-                           int precond, int* iters, double* relres, int64_t* fallback_at, bool io64 = false)
+                           int precond, int* iters, double* relres, int64_t* fallback_at, bool io64 = false,
+                           fkt_plan_t P64 = nullptr, const fkt::CgPlanView* v64 = nullptr, int* replaced = nullptr)
 {
     if (!P) return fail(FKT_EINVAL, "plan is NULL");
     if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_cg_solve");
@@ -616,7 +616,8 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
     fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
                       P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
-    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at, io64);
+    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at, io64, P64,
+                              v64, replaced);
 }
 
 fkt_status fkt_cg_solve(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
@@ -649,14 +650,12 @@ fkt_status fkt_cg_solve_refined(fkt_plan_t P, fkt_plan_t Q, double sigma2, const
     if (precond < 0 || precond > 2) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
-    const fkt::CgInner inner = [&](const double* r, double* d, double inner_rtol, int left, int* it) {
-        double rr = 0.0;
-        return cg_entry(Q, sigma2, r, d, nrhs, inner_rtol, left, precond, it, &rr, &Q->st.cg_fallback_iter, true);
-    };
     fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
                       P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
-    return fkt::cg_refine_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, inner, iters, outer, relres);
+    // CG on the FP32 plan with its residual replaced by the FP64 one
+    return cg_entry(Q, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, &Q->st.cg_fallback_iter, true, P, &v,
+                    outer);
 }
 
 static fkt_status learn_entry(fkt_plan_t P, double sigma2)

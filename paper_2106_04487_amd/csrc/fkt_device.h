@@ -4,7 +4,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <functional>
 
 #include "../../include/fkt.h"
 
@@ -89,10 +88,6 @@ struct CgPlanView {
     const int64_t* seg_off;  // device [nseg + 1]: instance rows [seg_off[i], seg_off[i + 1]) (user order)
     const int32_t* row_seg;  // device [n]: instance of each row (NULL when nseg = 1)
 };
-
-// inner solve of iterative refinement: d from a zero start, to inner_rtol,
-// at most maxit iterations (count in *iters)
-typedef std::function<fkt_status(const double* r, double* d, double inner_rtol, int maxit, int* iters)> CgInner;
 
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,
                              int prec, hipStream_t s, bool overlap, hipEvent_t* ev);

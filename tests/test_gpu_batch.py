@@ -118,8 +118,8 @@ def test_batch_cg_solves_every_instance(F, prec, true_tol, precond):
 
 
 def test_batch_refined_solve_meets_fp64_residual(F):
-    """Iterative refinement on a batched plan: FP32 CG corrections, FP64
-    residuals. Every instance meets 1e-6 under the oracle's operator (the
+    """Mixed-precision CG on a batched plan: FP32 MVMs, residual replaced by
+    the FP64 plan's. Every instance meets 1e-6 under the oracle's operator (the
     same truncation as the FP64 plan), where FP32 CG alone stops near the
     FP32 operator's error."""
     import torch
@@ -131,8 +131,8 @@ def test_batch_refined_solve_meets_fp64_residual(F):
     p32 = F.fkt_plan_batch((X, off), "ratquad", leaf, p, theta=theta, prec="f32", **KW)
     bt = torch.as_tensor(b, device="cuda")
     x, it, outer, rr = F.fkt_cg_solve_refined(p64, p32, sig2, bt, rtol=rtol, maxit=2000, precond="block_jacobi")
-    print(f"refined: {it} FP32 iterations, {outer} steps, FP64 relres {rr:.2e}")
-    assert rr <= rtol and 1 <= outer <= 10
+    print(f"refined: {it} FP32 iterations, {outer} FP64 residual replacements, FP64 relres {rr:.2e}")
+    assert rr <= rtol and 1 <= outer <= 40
     x = x.cpu().numpy()
     for i in range(len(sizes)):
         a0, a1 = off[i], off[i + 1]

@@ -158,8 +158,9 @@ def test_mixed_precision_cg_reaches_tolerance(F):
     """CG with the MVM in FP32 (vectors, scalars and the preconditioners in
     FP64) still reaches relative residual 1e-6, and its solution agrees with
     the FP64 plan's to the FP32 operator's accuracy. That accuracy bounds
-    its residual under the FP64 operator; "refined" (FP32 CG corrections to
-    FP64 residuals, fkt_cg_solve_refined) must meet 1e-6 there."""
+    its residual under the FP64 operator; "refined" (FP32 CG with its
+    residual replaced by the FP64 one, fkt_cg_solve_refined) must meet 1e-6
+    there."""
     import torch
     n, sig2 = 5000, 1e-2
     X = _gp_points(n, 73)
@@ -174,7 +175,7 @@ def test_mixed_precision_cg_reaches_tolerance(F):
         for pc in ("none", "block_jacobi"):
             if prec == "refined":
                 x, it, outer, rr = F.fkt_cg_solve_refined(plan64, plan32, sig2, b, rtol=1e-6, maxit=3000, precond=pc)
-                print(f"refined {pc}: {it} FP32 iterations, {outer} FP64 residual steps")
+                print(f"refined {pc}: {it} FP32 iterations, {outer} FP64 residual replacements")
             else:
                 solve = F.fkt_cg_solve64 if prec == "mixed" else F.fkt_cg_solve
                 x, it, rr = solve(plan, sig2, b, rtol=1e-6, maxit=3000, precond=pc)
