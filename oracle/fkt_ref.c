@@ -412,9 +412,10 @@ void ref_fkt_rows(void *h, double theta, int p, const double *Tb, int kind, cons
     }
 }
 
-/* Algorithm 1 in its own order: for every node, its far targets receive the
- * compressed block times y[node]; for every leaf, its near targets receive the
- * dense block times y[leaf]. Far/near sets come from the per-target walk. */
+/* Algorithm 1, node by node: each node passes its points' weights through the
+ * truncated expansion to every target in its far set, and each leaf adds the
+ * exact kernel block times its weights to every target in its near set. The
+ * far and near sets come from the per-target walk. */
 void ref_fkt_alg1(void *h, double theta, int p, const double *Tb, int kind, const double *prm,
                   const double *x, int nrhs, double *out)
 {
@@ -426,7 +427,7 @@ void ref_fkt_alg1(void *h, double theta, int p, const double *Tb, int kind, cons
     int64_t *fb = malloc(sizeof(int64_t) * nn), *nb = malloc(sizeof(int64_t) * nn);
     int64_t ftot = 0, ntot = 0;
     memset(out, 0, sizeof(double) * n * nrhs);
-    /* n.far and n.near as target lists per node */
+    /* far and near sets as target lists per node */
     for (t = 0; t < n; ++t) {
         int64_t nf = 0, nq = 0, q;
         walk(T, 0, T->X + t * d, theta * theta, fb, nn, &nf, nb, nn, &nq);
@@ -446,7 +447,7 @@ void ref_fkt_alg1(void *h, double theta, int p, const double *Tb, int kind, cons
     }
     for (b = 0; b < nn; ++b) {
         int64_t q;
-        /* z[n.far] += m2t * (s2m * y[n.indices]) */
+        /* far set of node b: expansion about b's centre, pair by pair */
 #pragma omp parallel for schedule(dynamic, 8)
         for (q = fcnt[b]; q < fcnt[b + 1]; ++q) {
             int64_t tt = flist[q], i; int a, c;
@@ -459,7 +460,7 @@ void ref_fkt_alg1(void *h, double theta, int p, const double *Tb, int kind, cons
                 for (c = 0; c < nrhs; ++c) out[tt * nrhs + c] += v * x[s * nrhs + c];
             }
         }
-        /* if leaf: z[n.near] += K(n.near, n.indices) * y[n.indices] */
+        /* near set of leaf b (empty for inner nodes): exact kernel entries */
 #pragma omp parallel for schedule(dynamic, 8)
         for (q = ncnt[b]; q < ncnt[b + 1]; ++q) {
             int64_t tt = nlist[q], i; int c;
@@ -493,4 +494,258 @@ void ref_counts(void *h, double theta, int64_t *nfar_nodes, int64_t *nfar_pts,
         }
         free(fb); free(nb);
     }
+}
+
+/* ------------------------------------------- factorised CPU FKT (Cartesian) */
+/*
+ * The same operator as Algorithm 1 at the same tree, partition and
+ * truncation, factorised through moments, but with a basis that shares
+ * nothing with the harmonic one: by Theorem 3.1 the terms of radial power
+ * j form the degree-j part of the Taylor expansion of y -> K(|r - y|) about
+ * the node centre (r the target and y the source, both relative to it), so
+ * the p-truncated expansion is that Taylor polynomial of total degree p:
+ *     K~(y, r) = sum_{|beta| <= p} c_beta(r) y^beta,
+ * with Cartesian monomials y^beta. Per node b the moments are
+ *     M_b[beta] = sum_{s in b} x_s (X_s - c_b)^beta,
+ * and each far target t gets sum_beta c_beta(t - c_b) M_b[beta].
+ *
+ * Taylor coefficients: with rho = |r - y|^2 and h(rho) = K(sqrt(rho)), set
+ * g_n(y) = h^(n)(|r - y|^2). Differentiating, d g_n / d y_a =
+ * -2 (r_a - y_a) g_{n+1}(y), and comparing the coefficients of y^(beta - e_a)
+ * on both sides gives, for any axis a with beta_a >= 1,
+ *     beta_a c^(n)_beta = 2 c^(n+1)_(beta - 2 e_a) - 2 r_a c^(n+1)_(beta - e_a)
+ * (the first term only when beta_a >= 2), with c^(n)_0 = h^(n)(|r|^2); the
+ * wanted coefficients are c^(0). The rho-derivatives h^(n) are closed forms
+ * per kernel (rho_derivs below). */
+typedef struct {
+    int d, p, nm;
+    int *expo;      /* [nm][d] exponents, ordered by total degree            */
+    int *deg;       /* [nm] total degree                                       */
+    int *axis;      /* [nm] first axis with a nonzero exponent (-1 for 0)      */
+    int *m1, *m2;   /* [nm] index of beta - e_axis, beta - 2 e_axis (or -1)    */
+} cart_basis;
+
+static int cart_find(const cart_basis *B, const int *e, int upto)
+{
+    int i, a;
+    for (i = 0; i < upto; ++i) {
+        for (a = 0; a < B->d; ++a) if (B->expo[i * B->d + a] != e[a]) break;
+        if (a == B->d) return i;
+    }
+    return -1;
+}
+
+static void cart_basis_init(cart_basis *B, int d, int p)
+{
+    int k, i, a, cnt = 0, e[MAXD];
+    int64_t cap = 1;
+    for (i = 1; i <= d; ++i) cap = cap * (p + i) / i;   /* C(p+d, d) */
+    B->d = d; B->p = p; B->nm = (int)cap;
+    B->expo = calloc((size_t)cap * d, sizeof(int));
+    B->deg = malloc(sizeof(int) * cap); B->axis = malloc(sizeof(int) * cap);
+    B->m1 = malloc(sizeof(int) * cap); B->m2 = malloc(sizeof(int) * cap);
+    /* all exponent vectors of degree k, by counting in base k+1 (small d, p) */
+    for (k = 0; k <= p; ++k) {
+        for (a = 0; a < d; ++a) e[a] = 0;
+        for (;;) {
+            int s = 0;
+            for (a = 0; a < d; ++a) s += e[a];
+            if (s == k) { memcpy(B->expo + (size_t)cnt * d, e, sizeof(int) * d); B->deg[cnt++] = k; }
+            for (a = 0; a < d; ++a) { if (++e[a] <= k) break; e[a] = 0; }
+            if (a == d) break;
+        }
+    }
+    for (i = 0; i < B->nm; ++i) {
+        int *bi = B->expo + (size_t)i * d;
+        B->axis[i] = -1; B->m1[i] = B->m2[i] = -1;
+        for (a = 0; a < d; ++a) if (bi[a] > 0) break;
+        if (a == d) continue;
+        B->axis[i] = a;
+        memcpy(e, bi, sizeof(int) * d);
+        e[a] -= 1; B->m1[i] = cart_find(B, e, i);
+        if (bi[a] >= 2) { e[a] -= 1; B->m2[i] = cart_find(B, e, i); }
+    }
+}
+
+static void cart_basis_free(cart_basis *B)
+{
+    free(B->expo); free(B->deg); free(B->axis); free(B->m1); free(B->m2);
+}
+
+/* E_n = d^n/drho^n exp(-c sqrt(rho)) at sqrt(rho) = r: for n >= 1,
+ * (-1)^n e^{-cr} sum_{k<n} (n-1+k)! / (k! (n-1-k)!) c^(n-k) / (2^(n+k) r^(n+k))
+ * (the reverse Bessel polynomial; every term has the same sign). */
+static double exp_sqrt_deriv(int n, double c, double r)
+{
+    double e = exp(-c * r), s = 0.0;
+    int k;
+    if (n == 0) return e;
+    for (k = 0; k < n; ++k) {
+        double w = 1.0; int i;
+        for (i = n - k; i <= n - 1 + k; ++i) w *= i;       /* (n-1+k)! / (n-1-k)! */
+        for (i = 2; i <= k; ++i) w /= i;                   /* / k! */
+        s += w * pow(c, n - k) / (pow(2.0, n + k) * pow(r, n + k));
+    }
+    return ((n & 1) ? -1.0 : 1.0) * e * s;
+}
+
+/* h^(n)(rho) = d^n/drho^n K(sqrt(rho)) at rho = r^2, n = 0..p, in closed form
+ * per kernel (prm: lengthscale, shape, variance):
+ *   Gaussian exp(-c rho), c = 1/(2 l^2):   (-c)^n exp(-c rho)
+ *   exponential exp(-c r), c = 1/l:        E_n
+ *   Matern-3/2 (1 + cr) e^{-cr}:           K' = -c^2 r e^{-cr}, so h' = -(c^2/2) E_0
+ *                                          and h^(n) = -(c^2/2) E_{n-1}
+ *   Matern-5/2 (1 + cr + c^2 r^2/3) e^{-cr}: K' = -(c^2/3) r (1 + cr) e^{-cr}, so
+ *                                          h^(n) = -(c^2/6) (Matern-3/2)^(n-1)
+ *   rational quadratic (1 + c rho)^(-a):   (-a)(-a-1)..(-a-n+1) c^n (1 + c rho)^(-a-n)
+ *   Cauchy: the same with a = 1, c = 1/l^2
+ *   r^-q = rho^(-q/2):                      (-q/2)(-q/2-1)..(-q/2-n+1) rho^(-q/2-n) */
+static void rho_derivs(int kind, const double *prm, double r, int p, double *h)
+{
+    const double ell = prm[0], shape = prm[1], var = prm[2], rho = r * r;
+    int n;
+    for (n = 0; n <= p; ++n) {
+        double v = NAN;
+        switch (kind) {
+        case K_GAUSS: { double c = 1.0 / (2.0 * ell * ell); v = pow(-c, n) * exp(-c * rho); break; }
+        case K_EXP: v = exp_sqrt_deriv(n, 1.0 / ell, r); break;
+        case K_MATERN32: { double c = sqrt(3.0) / ell;
+            v = (n == 0) ? (1.0 + c * r) * exp(-c * r) : -0.5 * c * c * exp_sqrt_deriv(n - 1, c, r); break; }
+        case K_MATERN52: { double c = sqrt(5.0) / ell;
+            if (n == 0) v = (1.0 + c * r + c * c * r * r / 3.0) * exp(-c * r);
+            else if (n == 1) v = -(c * c / 6.0) * (1.0 + c * r) * exp(-c * r);
+            else v = (c * c / 6.0) * (0.5 * c * c) * exp_sqrt_deriv(n - 2, c, r);
+            break; }
+        case K_RQ:
+        case K_CAUCHY: { double a = (kind == K_RQ) ? shape : 1.0;
+            double c = (kind == K_RQ) ? 1.0 / (2.0 * shape * ell * ell) : 1.0 / (ell * ell), f = 1.0; int i;
+            for (i = 0; i < n; ++i) f *= -a - i;
+            v = f * pow(c, n) * pow(1.0 + c * rho, -a - n); break; }
+        case K_POWER: { double f = 1.0; int i;
+            for (i = 0; i < n; ++i) f *= -0.5 * shape - i;
+            v = f * pow(rho, -0.5 * shape - n); break; }
+        }
+        h[n] = var * v;
+    }
+}
+
+/* Taylor coefficients c^(0)_beta of y -> K(|r - y|) at y = 0 (work: 2 nm doubles) */
+static void cart_coeffs(const cart_basis *B, int kind, const double *prm, const double *r, double *c, double *work)
+{
+    const int p = B->p, d = B->d;
+    double h[MAXP + 1], rr = 0.0, *cur = work, *nxt = work + B->nm;
+    int n, i, a;
+    for (a = 0; a < d; ++a) rr += r[a] * r[a];
+    rho_derivs(kind, prm, sqrt(rr), p, h);
+    /* level n holds degrees 0..p-n; start at n = p, go down to n = 0 */
+    nxt[0] = h[p];
+    for (n = p - 1; n >= 0; --n) {
+        double *lev = (n == 0) ? c : cur;
+        lev[0] = h[n];
+        for (i = 1; i < B->nm && B->deg[i] <= p - n; ++i) {
+            int ax = B->axis[i], ba = B->expo[i * d + ax];
+            double v = -r[ax] * nxt[B->m1[i]];
+            if (B->m2[i] >= 0) v += nxt[B->m2[i]];
+            lev[i] = 2.0 * v / ba;
+        }
+        if (n > 0) { double *t = cur; cur = nxt; nxt = t; }
+    }
+    if (p == 0) c[0] = h[0];
+}
+
+/* The Cartesian truncated expansion for one (source offset rp, target offset
+ * r) pair: sum_beta c_beta(r) rp^beta (compared with ref_expansion by tests). */
+double ref_cart_pair(int d, int p, int kind, const double *prm, const double *rp, const double *r)
+{
+    cart_basis B;
+    double *c, *w, *mono, s = 0.0;
+    int i;
+    cart_basis_init(&B, d, p);
+    c = malloc(sizeof(double) * B.nm); w = malloc(sizeof(double) * 2 * B.nm); mono = malloc(sizeof(double) * B.nm);
+    cart_coeffs(&B, kind, prm, r, c, w);
+    mono[0] = 1.0;
+    for (i = 1; i < B.nm; ++i) mono[i] = mono[B.m1[i]] * rp[B.axis[i]];
+    for (i = 0; i < B.nm; ++i) s += c[i] * mono[i];
+    free(c); free(w); free(mono); cart_basis_free(&B);
+    return s;
+}
+
+/* h^(n)(|r|^2) for n = 0..p (exported for tests). */
+void ref_rho_derivs(int p, int kind, const double *prm, double rr, double *h)
+{
+    rho_derivs(kind, prm, rr, p, h);
+}
+
+/*
+ * Factorised FKT, selected rows: moments of every node from its own points,
+ * then, for each target, the Taylor coefficients about each far node's
+ * centre against that node's moments, plus the exact kernel entries of its
+ * near leaves. targets (original indices) may be NULL for all rows in
+ * original order; nthreads <= 0 uses the OpenMP default.
+ */
+void ref_fkt_cart(void *h, double theta, int p, int kind, const double *prm, const double *x, int nrhs,
+                  int64_t nt, const int64_t *targets, double *out)
+{
+    ref_tree *T = h;
+    const int d = T->d;
+    const int64_t nn = T->nnodes;
+    cart_basis B;
+    double *mom;
+    int64_t b, q;
+    cart_basis_init(&B, d, p);
+    mom = calloc((size_t)nn * B.nm * nrhs, sizeof(double));
+#pragma omp parallel
+    {
+        double *mono = malloc(sizeof(double) * B.nm);
+#pragma omp for schedule(dynamic, 1)
+        for (b = 0; b < nn; ++b) {
+            double *M = mom + (size_t)b * B.nm * nrhs;
+            int64_t i;
+            for (i = T->start[b]; i < T->end[b]; ++i) {
+                int64_t s = T->perm[i];
+                double y[MAXD];
+                int a, k, c;
+                for (a = 0; a < d; ++a) y[a] = T->X[s * d + a] - T->ctr[b * d + a];
+                mono[0] = 1.0;
+                for (k = 1; k < B.nm; ++k) mono[k] = mono[B.m1[k]] * y[B.axis[k]];
+                for (k = 0; k < B.nm; ++k)
+                    for (c = 0; c < nrhs; ++c) M[(size_t)k * nrhs + c] += mono[k] * x[s * nrhs + c];
+            }
+        }
+        free(mono);
+    }
+#pragma omp parallel
+    {
+        int64_t *fb = malloc(sizeof(int64_t) * nn), *nb = malloc(sizeof(int64_t) * nn);
+        double *cf = malloc(sizeof(double) * B.nm), *w = malloc(sizeof(double) * 2 * B.nm);
+#pragma omp for schedule(dynamic, 16)
+        for (q = 0; q < nt; ++q) {
+            const int64_t t = targets ? targets[q] : q;
+            const double *xt = T->X + t * d;
+            double *o = out + q * nrhs;
+            int64_t nf = 0, nq = 0, f, i;
+            int a, c, k;
+            for (c = 0; c < nrhs; ++c) o[c] = 0.0;
+            walk(T, 0, xt, theta * theta, fb, nn, &nf, nb, nn, &nq);
+            for (f = 0; f < nf; ++f) {
+                const double *M = mom + (size_t)fb[f] * B.nm * nrhs;
+                double r[MAXD];
+                for (a = 0; a < d; ++a) r[a] = xt[a] - T->ctr[fb[f] * d + a];
+                cart_coeffs(&B, kind, prm, r, cf, w);
+                for (k = 0; k < B.nm; ++k)
+                    for (c = 0; c < nrhs; ++c) o[c] += cf[k] * M[(size_t)k * nrhs + c];
+            }
+            for (f = 0; f < nq; ++f) {
+                const int64_t l = nb[f];
+                for (i = T->start[l]; i < T->end[l]; ++i) {
+                    const int64_t s = T->perm[i];
+                    const double v = kern_value(kind, prm, dist(xt, T->X + s * d, d));
+                    for (c = 0; c < nrhs; ++c) o[c] += v * x[s * nrhs + c];
+                }
+            }
+        }
+        free(fb); free(nb); free(cf); free(w);
+    }
+    free(mom);
+    cart_basis_free(&B);
 }
