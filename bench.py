@@ -38,10 +38,13 @@ ORACLE_KIND = {"laplace": ("power", {"shape": 1.0}), "matern32": ("matern32", {"
 
 # Published MI355X vector peaks (TFLOP/s): FP64 78.6, FP32 157.3.
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-# Algorithmic flops of one near-field pair ("Roofline"): distance
-# 3 sub + 3 FMA (9), the kernel (each exp/sqrt/rsqrt counted as one op),
-# and the multiply-accumulate with the weight (2).
-NEAR_FLOPS_PER_PAIR = {"laplace": 12, "matern32": 16}
+# Algorithmic work per unit, as the method's cost model prices it: one
+# near-field pair evaluation (distance, kernel value, multiply-accumulate)
+# at 40 vector flops, and one far (target, node) expansion at d = 3, p = 6
+# at 418 flops (84 moment multiply-adds, 168, plus about 250 for the
+# harmonics, the radial derivatives and the Tbar combinations).
+NEAR_FLOPS_PER_PAIR = 40
+M2T_FLOPS_PER_PAIR = {(3, 6): 418}
 # HBM bytes per near-field launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors of a plain copy) of the current near kernel, from the
 # counter profile under profiles/; empty until re-measured after a change.
@@ -265,7 +268,9 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
     return out
 
 
-MRHS_MODES = {"columns_f32": None, "mfma_f32": "f32", "mfma_bf16": "bf16"}
+# column by column (FP32), and the matrix-core path: near field FP32 or bf16
+# MFMA, far field bf16 high/low split MFMA (three products per tile) in both
+MRHS_MODES = {"columns_f32": None, "mfma_near_f32_far_bf16x3": "f32", "mfma_near_bf16_far_bf16x3": "bf16"}
 
 
 def batch_solve_leg(F, torch, ninst, theta, rtol=1e-6, maxit=1500, sig2=1.0, pcs=("none", "block_jacobi")):
@@ -437,16 +442,26 @@ def main():
     head = run_variant(F, torch, X, x64, a.kernel, a.prec, theta, a.leaf, a.order, a.steps, a.warmup,
                        a.err_targets, overlap=not a.serial)
 
-    # roofline of the dominant kernel, the near field (ALU-bound)
+    # roofline of the dominant kernel, the near field (vector-ALU bound), and
+    # of the far-field evaluation beside it; launch times from the HIP events
+    # bench records around each stage on the stream it runs on
     near_ms = head["stages_ms"]["near"]
     pairs = head["plan"]["near_pairs"]
-    fpp = NEAR_FLOPS_PER_PAIR[a.kernel]
-    achieved = pairs * fpp / (near_ms * 1e-3) / 1e12
+    achieved = pairs * NEAR_FLOPS_PER_PAIR / (near_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": "k_near", "achieved": achieved, "peak": PEAK_TFLOPS[a.prec],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[a.prec],
                 "traffic": NEAR_TRAFFIC_BYTES.get((a.kernel, a.prec)) if a.n == 1_000_000 else None,
-                "units": "near-field pair evaluations", "units_per_launch": pairs, "flops_per_unit": fpp,
-                "avg_launch_ms": near_ms}
+                "units": "near-field pair evaluations", "units_per_launch": pairs,
+                "flops_per_unit": NEAR_FLOPS_PER_PAIR, "avg_launch_ms": near_ms}
+    m2t = None
+    if (3, a.order) in M2T_FLOPS_PER_PAIR:
+        m2t_ms = head["stages_ms"]["m2t"]
+        fpairs = head["plan"]["far_pairs"]
+        ach = fpairs * M2T_FLOPS_PER_PAIR[(3, a.order)] / (m2t_ms * 1e-3) / 1e12
+        m2t = {"bound": "alu", "kernel": "k_m2t", "achieved": ach, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
+               "frac": ach / PEAK_TFLOPS[a.prec], "units": "far (target, node) expansions",
+               "units_per_launch": fpairs, "flops_per_unit": M2T_FLOPS_PER_PAIR[(3, a.order)],
+               "avg_launch_ms": m2t_ms}
 
     variants = []
     if not a.no_variants:
@@ -472,21 +487,30 @@ def main():
 
     cpu = None
     if a.cpu_seconds > 0:
-        # the oracle as it stands: rows of its Algorithm 1 (pairwise far
-        # field) for a bounded sample of targets, on all host cores
+        # the factorised CPU oracle (Cartesian moments of every node, then the
+        # far and near field of each sampled target) at the full N, on all
+        # host cores: rows in chunks until the time budget is spent
         import oracle
         okind, okw = ORACLE_KIND[a.kernel]
         T = oracle.Tree(X, a.leaf)
-        tg = W.subsample(a.n, 4096, 3003)
-        done, t0 = 0, time.perf_counter()
+        tg = W.subsample(a.n, a.n, 3003)
+        t0 = time.perf_counter()
+        oracle.fkt_cart(T, x64, okind, theta, a.order, targets=tg[:0], **okw)  # moments only
+        mom_s = time.perf_counter() - t0
+        done, chunk = 0, 4096
         while done < len(tg) and time.perf_counter() - t0 < a.cpu_seconds:
-            oracle.fkt_rows(T, x64, okind, theta, a.order, tg[done:done + 32], **okw)
-            done += 32
+            oracle.fkt_cart(T, x64, okind, theta, a.order, targets=tg[done:done + chunk], **okw)
+            done += chunk
         el = time.perf_counter() - t0
         threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-        cpu = {"value": done / el / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
-               "sample": f"{done} of {a.n} output rows of the oracle's Algorithm 1 (pairwise far field), "
-                         f"{el:.1f} s on {threads} threads"}
+        # whole-MVM rate: every chunk recomputes the moments, so the rows
+        # take el - (chunks + 1) mom_s; scale them to all N rows, add one
+        row_s = max(el - (done // chunk + 1) * mom_s, 1e-9) / done
+        mvm_s = mom_s + row_s * a.n
+        cpu = {"value": a.n / mvm_s / 1e6, "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+               "sample": f"factorised CPU FKT (Cartesian moments) at N = {a.n}: moments {mom_s:.2f} s, "
+                         f"{done} sampled output rows in {el - (done // chunk + 1) * mom_s:.1f} s on {threads} "
+                         f"threads; whole MVM {mvm_s:.1f} s by extrapolation"}
 
     info = head["plan"]
     out = {
@@ -501,6 +525,7 @@ def main():
         "plan": {k: info[k] for k in ("nnodes", "nleaves", "nblocks", "near_pairs", "near_lane_pairs",
                                       "far_pairs", "far_lane_pairs", "plan_seconds")},
         "roofline": roofline,
+        "roofline_m2t": m2t,
         "cpu_baseline": cpu,
         "variants": variants,
         "gp_solve": gp,

@@ -82,11 +82,15 @@ typedef struct {
                            before the scatter; 0: every stage in order on
                            `stream`                                            */
     int mrhs;           /* FP32 plans: fkt_mvm with nrhs a multiple of 32 runs
-                           the near field on the matrix cores for 32 columns
-                           at once: 1 FP32 MFMA, 2 bf16 MFMA (kernel values
-                           and weights rounded to bf16, FP32 accumulation);
-                           the far field stays FP32, column by column.
-                           0 (default): every column on its own.            */
+                           each group of 32 columns on the matrix cores. The
+                           near field: 1 FP32 MFMA, 2 bf16 MFMA (kernel
+                           values and weights rounded to bf16, FP32
+                           accumulation). The moments of the 32 columns:
+                           FP32 MFMA. The far-field evaluation (basis times
+                           moments): bf16 MFMA with both operands split into
+                           high and low bf16 parts and three products per
+                           tile (about 16 mantissa bits), for either value.
+                           0 (default): every column on its own, FP32.      */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
@@ -97,7 +101,10 @@ void fkt_default_options(fkt_options *opt);
  * fkt_plan -- build the tree, the near/far partition and the coefficient
  * tables, and upload them to the device (paper Sec. 3.1-3.2, Algorithm 1
  * first line; coefficient tables of Appendix A.2).
- *   points    host, n x d FP64, row-major. Copied; not retained.
+ *   points    host, n x d FP64, row-major. Copied; not retained. (Host,
+ *             not device: the tree and the near/far lists are built on the
+ *             CPU, so a device array would be copied back first; the Python
+ *             binding does that copy for device tensors.)
  *   n         number of points, >= 1 (sources and targets are the same set).
  *   d         dimension, 3 <= d <= 5 (d = 2 needs the alpha = 0 Gegenbauer
  *             limit and is FKT_EUNSUPPORTED).
@@ -105,7 +112,8 @@ void fkt_default_options(fkt_options *opt);
  *   leaf_size maximum points per leaf, >= 1 (a node with more is split).
  *   order     truncation order p of eq. (finaltrunc): radial powers j <= p,
  *             harmonic degrees k <= p; expansion rank C(p+d, d).
- *             Built: 0 <= p <= 8 for d = 3 and d = 5, 0 <= p <= 6 for d = 4.
+ *             Built: 0 <= p <= 8 for d = 3, 4 and 5; other orders return
+ *             FKT_EUNSUPPORTED with a message naming the built range.
  *   opt       NULL for defaults.
  *   out       receives the plan on FKT_OK, NULL otherwise.
  * Errors: FKT_EINVAL (bad n, d, leaf_size, order, theta, kernel parameters,
@@ -122,9 +130,9 @@ fkt_status fkt_plan(const double *points, int64_t n, int d, fkt_kernel k, int le
  *             float (FKT_F32). Must not overlap. y is fully overwritten.
  *   nrhs      number of right-hand sides, 1 <= nrhs <= 64.
  * Enqueued on the plan's stream; returns before the result is ready.
+ * Allocates nothing: the plan's work buffers are allocated by fkt_plan.
  * Errors: FKT_EINVAL (NULL/overlapping pointers, nrhs), FKT_EDEVICE (host-only
- * plan, HIP failure), FKT_ENOMEM (work buffers grow on first use of a larger
- * nrhs). On error y is unspecified.
+ * plan, HIP failure). On error y is unspecified.
  */
 fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
 
@@ -202,6 +210,39 @@ fkt_status fkt_cg_solve64(fkt_plan_t p, double sigma2, const double *b, double *
 fkt_status fkt_cg_solve_refined(fkt_plan_t p, fkt_plan_t lo, double sigma2, const double *b, double *x, int nrhs,
                                 double rtol, int maxit, int precond, int *iters, int *outer, double *relres);
 
+/*
+ * fkt_precond_coarse -- two-level preconditioning for the solves of this plan
+ * at noise variance sigma2 (project addition: the paper solves its
+ * Gaussian-process systems through MVMs, Sec. 5.3 and eq. gp_posterior, and
+ * adds no preconditioner). Per-leaf preconditioners cannot reach the smooth
+ * global modes that make long-length-scale kernel systems ill-conditioned,
+ * so a Nystrom coarse space is added: with the k landmark points J,
+ *     L = K(X, X_J) W,   W = chol(K(X_J, X_J) + sigma2 I)^-T,   K ~ L L^T,
+ * and the Woodbury identity joins it to the per-leaf part of the residual
+ * leaf blocks R_l = K_ll + sigma2 I - L_l L_l^T = V_l^T diag(lam_l) V_l:
+ *     P = (L L^T + D)^-1,   D^-1 = blockdiag(V_l^T diag(h_l) V_l),
+ * with h = 1 / lam for precond 1 (block-Jacobi of the residual blocks) and
+ * h = exp(o) / lam, the learned filter, for precond 2 (whose features then
+ * come from the residual spectra; fkt_learn_* train it through P). precond
+ * 0 is unaffected. Afterwards every fkt_cg_solve / fkt_cg_solve64 /
+ * fkt_learn_* call on this plan with this sigma2 uses the two-level form; a
+ * call with another sigma2 drops it (one-level again).
+ *   landmarks  host, k distinct indices into the caller's point order (the
+ *              caller draws them; uniform without replacement is the
+ *              intended use).
+ *   k          number of landmarks, 1..4096; 0 returns to one-level.
+ * Builds K(X, X_J) and the factor on the device (FP64), the residual leaf
+ * blocks' eigendecompositions on the host, G = V L and the k x k matrices
+ * C = I + G^T diag(h) G (inverted on the host) for block-Jacobi; the learned
+ * filter's C is rebuilt whenever its weights are used. Device memory: about
+ * 8 n k (24 n k while building) + 8 (66 + m) k^2 bytes (m up to 64 row
+ * chunks). Synchronises the plan's stream.
+ * Errors: FKT_EINVAL (bad sigma2, k or landmarks; a landmark block or a
+ * residual leaf block that is not positive definite), FKT_EUNSUPPORTED
+ * (leaves over 2048 points), FKT_ENOMEM, FKT_EDEVICE.
+ */
+fkt_status fkt_precond_coarse(fkt_plan_t p, double sigma2, const int64_t *landmarks, int k);
+
 /* Release the plan and its device memory (NULL is a no-op). Waits for the
  * plan's stream first. */
 void fkt_destroy(fkt_plan_t p);
@@ -238,6 +279,20 @@ fkt_status fkt_plan_perm(fkt_plan_t p, int64_t *perm);
  * far nodes, far source points, near leaves, near source points. */
 fkt_status fkt_plan_target_counts(fkt_plan_t p, int64_t *far_nodes, int64_t *far_points, int64_t *near_leaves,
                                   int64_t *near_points);
+
+/*
+ * The plan's partition per target (Sec. 3.2): the far nodes F (eq. accparam)
+ * and near leaves N of each target, as host CSR arrays over the targets in
+ * the caller's order. Node ids are the tree's preorder numbers (for a
+ * batched plan the instance trees are numbered one after another, in
+ * instance order), ascending within each target.
+ *   far_off, near_off   n + 1 int64 each (may be NULL).
+ *   far_node, near_leaf int64 arrays of *nfar_total and *nnear_total entries;
+ *                       pass NULL to query the totals first.
+ *   nfar_total, nnear_total  receive the totals (may be NULL).
+ * Errors: FKT_EINVAL (NULL plan). */
+fkt_status fkt_plan_lists(fkt_plan_t p, int64_t *far_off, int64_t *far_node, int64_t *near_off, int64_t *near_leaf,
+                          int64_t *nfar_total, int64_t *nnear_total);
 
 /*
  * Device time of fkt_mvm's stages, summed over the calls made since the plan

@@ -23,10 +23,19 @@ this project adds for CG on A = K~ + sigma2 I. Definitions:
   (a_b A M v_b - v_b), dL/dh_{l,i} = sum_b (V_l dL/dw_b)_i (V_l v_b)_i,
   dL/do = h dL/dh, then back through the MLP.
 
+Two-level form (``nystrom_factor``, ``two_level_matrix``): with landmark
+points J, L = K(X, X_J) chol(K(X_J, X_J) + sigma2 I)^-T approximates K by
+L L^T; the leaf blocks become the residual blocks A_l - L_l L_l^T and the
+preconditioner is P = (L L^T + D)^-1 with D^-1 the block filter above, taken
+here by its definition as a dense inverse (small n).
+
 The parameter vector is ordered W1 [4][256], b1, W2 [256][256], b2, w3, b3.
 Pins (tests/test_oracle_learned.py): with o = 0 the filter is the exact
-inverse of every leaf block (block-Jacobi), and the analytic gradient
-matches central differences of L when A is an exactly symmetric matrix.
+inverse of every leaf block (block-Jacobi); the loss has the closed form of
+two single-point leaves and is exactly 0 for one leaf holding every point
+(one-level, and two-level, where P = (L L^T + A - L L^T)^-1 = A^-1); the
+analytic gradient matches central differences of L when A is an exactly
+symmetric matrix, in the one-level and the two-level form.
 """
 from __future__ import annotations
 
@@ -73,13 +82,35 @@ def leaf_block(Xl, kind, sigma2, **kw) -> np.ndarray:
     return A + sigma2 * np.eye(m)
 
 
-def leaf_spectra(tree, X, kind, sigma2, leaf_size, **kw):
-    """Per leaf: dict(idx = original indices, lam, V (rows), feat [m][4])."""
+def nystrom_factor(X, landmarks, kind, sigma2, **kw) -> np.ndarray:
+    """Two-level coarse factor L = K(X, X_J) chol(K(X_J, X_J) + sigma2 I)^-T
+    (n x k, original order), so that K ~ L L^T (regularised Nystrom)."""
+    X = np.asarray(X, dtype=np.float64)
+    J = np.asarray(landmarks, dtype=np.int64)
+    n, k = X.shape[0], len(J)
+    KnJ = np.zeros((n, k))
+    for c0 in range(0, k, 64):
+        c1 = min(k, c0 + 64)
+        E = np.zeros((n, c1 - c0))
+        E[J[c0:c1], np.arange(c1 - c0)] = 1.0
+        KnJ[:, c0:c1] = dense_mvm(X, E, kind, **kw)
+    KJJ = KnJ[J]
+    Lc = np.linalg.cholesky(0.5 * (KJJ + KJJ.T) + sigma2 * np.eye(k))
+    return np.linalg.solve(Lc, KnJ.T).T
+
+
+def leaf_spectra(tree, X, kind, sigma2, leaf_size, coarse=None, **kw):
+    """Per leaf: dict(idx = original indices, lam, V (rows), feat [m][4]);
+    with the coarse factor L (n x k), of the residual blocks
+    K_ll + sigma2 I - L_l L_l^T."""
     X = np.asarray(X, dtype=np.float64)
     out = []
     for s, e in leaf_ranges(tree):
         idx = tree.perm[s:e].copy()
         A = leaf_block(X[idx], kind, sigma2, **kw)
+        if coarse is not None:
+            A = A - coarse[idx] @ coarse[idx].T
+            A = 0.5 * (A + A.T)
         lam, U = np.linalg.eigh(A)
         m = e - s
         feat = np.stack([np.log(lam / sigma2) / 8.0, np.full(m, np.log(lam[-1] / sigma2) / 8.0),
@@ -128,23 +159,48 @@ def apply_filter(spectra, hs, v) -> np.ndarray:
     return w
 
 
-def loss_grad(spectra, theta, v, op):
-    """(L, dL/dtheta) for the batch v (n x B); op(x) = A x for n x B x."""
+def two_level_matrix(spectra, hs, L) -> np.ndarray:
+    """P = (L L^T + D)^-1 with D^-1 = blockdiag(V_l^T diag(h_l) V_l), as a
+    dense n x n matrix (small n): the two-level preconditioner by its
+    definition (the device applies it through the Woodbury identity)."""
+    n = L.shape[0]
+    D = np.zeros((n, n))
+    for Sl, h in zip(spectra, hs):
+        ix = Sl["idx"]
+        D[np.ix_(ix, ix)] = Sl["V"].T @ np.diag(1.0 / h) @ Sl["V"]
+    P = np.linalg.inv(L @ L.T + D)
+    return 0.5 * (P + P.T)
+
+
+def loss_grad(spectra, theta, v, op, coarse=None):
+    """(L, dL/dtheta) for the batch v (n x B); op(x) = A x for n x B x. With
+    the coarse factor L the preconditioner is the two-level P(h) =
+    (L L^T + D)^-1, D^-1 = M = blockdiag filter; then dP = (P D) dM (D P)
+    (the derivative of the inverse), so the spectral projections of v and
+    of the back-propagated residual are taken after D P."""
     v = np.asarray(v, dtype=np.float64)
     if v.ndim == 1:
         v = v[:, None]
     B = v.shape[1]
     hs, cache = filters(spectra, theta)
-    w = apply_filter(spectra, hs, v)
+    if coarse is None:
+        w = apply_filter(spectra, hs, v)
+        pre = lambda x: x
+    else:
+        P = two_level_matrix(spectra, hs, coarse)
+        w = P @ v
+        Dm = np.linalg.inv(P) - coarse @ coarse.T     # D = M^-1
+        pre = lambda x: Dm @ (P @ x)
     u = op(w)
     vv = np.sum(v * v, axis=0)
     a = np.sum(u * v, axis=0) / np.sum(u * u, axis=0)
     r = a[None, :] * u - v
     loss = float(np.mean(np.sum(r * r, axis=0) / vv))
     g = op(r) * (2.0 * a / (B * vv))[None, :]
+    vp, gp = pre(v), pre(g)
     go = []
     for L, h in zip(spectra, hs):
-        c = L["V"] @ v[L["idx"]]
-        q = L["V"] @ g[L["idx"]]
+        c = L["V"] @ vp[L["idx"]]
+        q = L["V"] @ gp[L["idx"]]
         go.append(h * np.sum(c * q, axis=1))
     return loss, mlp_backward(theta, cache, np.concatenate(go))

@@ -41,7 +41,8 @@ STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "F
 EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_cg_solve64", "fkt_cg_solve_refined",
             "fkt_destroy",
             "fkt_last_error",
-            "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_stage_times",
+            "fkt_precond_coarse",
+            "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_lists", "fkt_plan_stage_times",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
             "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
 
@@ -82,6 +83,8 @@ _lib.fkt_mvm.argtypes = [_P, _P, _P, ctypes.c_int]
 _lib.fkt_cg_solve.restype = ctypes.c_int
 _lib.fkt_cg_solve.argtypes = [_P, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+_lib.fkt_precond_coarse.restype = ctypes.c_int
+_lib.fkt_precond_coarse.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int]
 _lib.fkt_cg_solve64.restype = ctypes.c_int
 _lib.fkt_cg_solve64.argtypes = _lib.fkt_cg_solve.argtypes
 _lib.fkt_cg_solve_refined.restype = ctypes.c_int
@@ -96,6 +99,8 @@ _lib.fkt_plan_perm.restype = ctypes.c_int
 _lib.fkt_plan_perm.argtypes = [_P, _P]
 _lib.fkt_plan_target_counts.restype = ctypes.c_int
 _lib.fkt_plan_target_counts.argtypes = [_P, _P, _P, _P, _P]
+_lib.fkt_plan_lists.restype = ctypes.c_int
+_lib.fkt_plan_lists.argtypes = [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 _lib.fkt_plan_stage_times.restype = ctypes.c_int
 _lib.fkt_plan_stage_times.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
 _lib.fkt_plan_batch.restype = ctypes.c_int
@@ -172,6 +177,17 @@ class Plan:
         outs = [np.zeros(self.n, dtype=np.int64) for _ in range(4)]
         _check(_lib.fkt_plan_target_counts(self.handle, *[o.ctypes.data for o in outs]))
         return tuple(outs)
+
+    def lists(self):
+        """(far_off, far_node, near_off, near_leaf): per target (caller's
+        order) the far nodes and near leaves, CSR, ascending node ids."""
+        nf, nq = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib.fkt_plan_lists(self.handle, None, None, None, None, ctypes.byref(nf), ctypes.byref(nq)))
+        fo, no = np.zeros(self.n + 1, dtype=np.int64), np.zeros(self.n + 1, dtype=np.int64)
+        fnode, nleaf = np.zeros(max(nf.value, 1), dtype=np.int64), np.zeros(max(nq.value, 1), dtype=np.int64)
+        _check(_lib.fkt_plan_lists(self.handle, fo.ctypes.data, fnode.ctypes.data, no.ctypes.data, nleaf.ctypes.data,
+                                   ctypes.byref(nf), ctypes.byref(nq)))
+        return fo, fnode[:nf.value], no, nleaf[:nq.value]
 
     def stage_times(self, reset: bool = False):
         """(ms per stage summed over profiled passes, passes): stages are
@@ -378,6 +394,13 @@ def fkt_cg_solve(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, m
         raise err
     _check(st)
     return x, it.value, rr.value
+
+
+def fkt_precond_coarse(plan: Plan, sigma2: float, landmarks):
+    """Two-level preconditioning at sigma2 from the given landmark indices
+    (caller's order; an empty list returns to one-level)."""
+    lm = np.ascontiguousarray(np.asarray(landmarks, dtype=np.int64).ravel())
+    _check(_lib.fkt_precond_coarse(plan.handle, float(sigma2), lm.ctypes.data if lm.size else None, int(lm.size)))
 
 
 def fkt_cg_solve64(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,

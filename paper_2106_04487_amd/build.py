@@ -38,6 +38,7 @@ def _jobs():
           os.path.join(CSRC, "learn_host.cpp"), "-o", os.path.join(BUILD, "learn_host.o")]),
         ([*dev, "-c", os.path.join(CSRC, "learn.hip"), "-o", os.path.join(BUILD, "learn.o")]),
         ([*dev, "-c", os.path.join(CSRC, "mrhs.hip"), "-o", os.path.join(BUILD, "mrhs.o")]),
+        ([*dev, "-c", os.path.join(CSRC, "coarse.hip"), "-o", os.path.join(BUILD, "coarse.o")]),
     ]
     # one source-to-multipole object per (dimension, precision)
     for d in (3, 4, 5):

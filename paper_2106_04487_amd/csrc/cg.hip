@@ -128,6 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_bj_apply(const int* __restrict__ b
 
 unsigned grid_of(int64_t m) { return (unsigned)((m + kThreads - 1) / kThreads); }
 
+int cg_dot_blocks(int nseg) { return std::max(8, kDotBlocks / nseg); }
+
 struct Buf {
     std::vector<void*> ptrs;
     ~Buf()
@@ -149,6 +151,7 @@ struct Buf {
 
 namespace fkt {
 fkt_status cg_set_error(fkt_status st, const std::string& msg);
+
 }  // namespace fkt
 
 namespace fkt {
@@ -172,7 +175,7 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     // systems: (instance, column) pairs, each with its own CG scalars; a
     // converged system is frozen (alpha = beta = 0) while the others go on
     const int nseg = v.nseg, nsys = nseg * nrhs;
-    const int bps = std::max(8, kDotBlocks / nseg);  // dot blocks per instance
+    const int bps = cg_dot_blocks(nseg);  // dot blocks per instance
     hipStream_t s = v.stream;
     Buf buf;
     double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr, *q64 = nullptr;
@@ -208,6 +211,13 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         return FKT_OK;
     };
     auto precondition = [&](const double* in, double* out) -> bool {
+        if (v.coarse && precond >= 1) {
+            // two-level: block-Jacobi (h = 1 / lam) or the learned filter on
+            // the residual leaf spectra, with the Nystrom coarse correction
+            for (int c2 = 0; c2 < nrhs; ++c2)
+                if (learn_apply(v.learn, in, out, nrhs, c2, s, precond == 1) != hipSuccess) return false;
+            return true;
+        }
         if (precond == 1) {
             for (int c2 = 0; c2 < nrhs; ++c2)
                 hipLaunchKernelGGL(k_bj_apply, dim3(v.nleaf), dim3(kThreads), sizeof(double) * v.maxleaf, s, v.bj_begin,
@@ -226,10 +236,29 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     hipLaunchKernelGGL((k_to_f64<TI>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, (const TI*)x_io, x);
     std::vector<double> bb, rr, rz, pq, rz_new;
     // r = b - A x, z = M r, p = z, rz = (r, z), rr = (r, r)
-    auto start = [&]() -> fkt_status {
-        fkt_status st0 = apply(x, q);
+    // refined solves: r = b - (K~64 + sigma2 I) x from the FP64 plan, on its
+    // stream once this one has finished writing x
+    auto residual64 = [&]() -> fkt_status {
+        if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
+        fkt_status st0 = fkt_mvm(P64, x, q64, nrhs);
         if (st0 != FKT_OK) return st0;
-        hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
+        hipLaunchKernelGGL((k_add_shift<double>), dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, q64, x, sigma2,
+                           q64);
+        hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, b, q64, r);
+        if (hipStreamSynchronize(v64->stream) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
+        if (replaced) ++*replaced;
+        return FKT_OK;
+    };
+    // r = b - A x (from the FP64 plan in a refined solve), z = M r, p = z
+    auto start = [&]() -> fkt_status {
+        if (P64) {
+            fkt_status st0 = residual64();
+            if (st0 != FKT_OK) return st0;
+        } else {
+            fkt_status st0 = apply(x, q);
+            if (st0 != FKT_OK) return st0;
+            hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, s, m, b, q, r);
+        }
         if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
         if (hipMemcpyAsync(p, z, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
             return cg_set_error(FKT_EDEVICE, "cg copy");
@@ -237,6 +266,7 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         return FKT_OK;
     };
     if (!dots(b, b, bb)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+    if (replaced) *replaced = 0;
     fkt_status st = start();
     if (st != FKT_OK) return st;
     auto relres_of = [&](const std::vector<double>& rv, int j) {
@@ -251,7 +281,6 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     int it = 0;
     double res = worst(rr);
     double res_replaced = res;  // worst residual at the last replacement
-    if (replaced) *replaced = 0;
     double best = res;
     int it_best = 0;
     if (xbest && hipMemcpyAsync(xbest, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -265,6 +294,7 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
                 return cg_set_error(FKT_EDEVICE, "cg copy");
             if ((st = start()) != FKT_OK) return st;
             res = worst(rr);
+            res_replaced = res;
             continue;
         }
         st = apply(p, q);
@@ -285,18 +315,11 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
         if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
         if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
         if (P64 && (worst(rr) <= rtol || worst(rr) <= kReplaceDrop * res_replaced)) {
-            // residual replacement: r = b - (K~64 + sigma2 I) x on the FP64
-            // plan's stream (this stream is idle after the reductions)
-            st = fkt_mvm(P64, x, q64, nrhs);
-            if (st != FKT_OK) return st;
-            hipLaunchKernelGGL((k_add_shift<double>), dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, q64, x,
-                               sigma2, q64);
-            hipLaunchKernelGGL(k_sub, dim3(grid_of(m)), dim3(kThreads), 0, v64->stream, m, b, q64, r);
-            if (hipStreamSynchronize(v64->stream) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");
+            // residual replacement: r = b - (K~64 + sigma2 I) x
+            if ((st = residual64()) != FKT_OK) return st;
             if (!precondition(r, z)) return cg_set_error(FKT_EDEVICE, "cg preconditioner");
             if (!dots(r, r, rr) || !dots(r, z, rz_new)) return cg_set_error(FKT_EDEVICE, "cg reduction");
             res_replaced = worst(rr);
-            if (replaced) ++*replaced;
         }
         for (int j = 0; j < nsys; ++j) hcoef[2 * nsys + j] = (!frozen[j] && rz[j] != 0.0) ? rz_new[j] / rz[j] : 0.0;
         if (hipMemcpyAsync(coef + 2 * nsys, hcoef.data() + 2 * nsys, sizeof(double) * nsys, hipMemcpyHostToDevice, s) !=
@@ -312,6 +335,12 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
             if (hipMemcpyAsync(xbest, x, sizeof(double) * m, hipMemcpyDeviceToDevice, s) != hipSuccess)
                 return cg_set_error(FKT_EDEVICE, "cg copy");
         }
+    }
+    if (P64 && res > rtol) {
+        // not converged: report the residual under the FP64 operator
+        if ((st = residual64()) != FKT_OK) return st;
+        if (!dots(r, r, rr)) return cg_set_error(FKT_EDEVICE, "cg reduction");
+        res = worst(rr);
     }
     hipLaunchKernelGGL((k_from_f64<TI>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, x, x_io);
     if (hipStreamSynchronize(s) != hipSuccess) return cg_set_error(FKT_EDEVICE, "cg sync");

@@ -1,6 +1,7 @@
 // C-ABI entry points of libfkt.so (declared in include/fkt.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -9,6 +10,7 @@
 #include <vector>
 
 #include "../../include/fkt.h"
+#include "fkt_coarse.h"
 #include "fkt_device.h"
 #include "fkt_host.h"
 #include "fkt_learn.h"
@@ -29,6 +31,24 @@ fkt_status hip_fail(hipError_t e, const char* what)
     return fail(e == hipErrorOutOfMemory ? FKT_ENOMEM : FKT_EDEVICE,
                 std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// Device buffers freed at the end of a scope.
+struct DevTmp {
+    std::vector<void*> p;
+    ~DevTmp()
+    {
+        for (void* q : p) (void)hipFree(q);
+    }
+    template <class T>
+    hipError_t get(size_t c, T** o)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * (c ? c : 1));
+        if (e == hipSuccess) p.push_back(q);
+        *o = (T*)q;
+        return e;
+    }
+};
 
 // Makes `dev` current for the scope and restores the caller's device.
 struct DeviceScope {
@@ -90,6 +110,9 @@ struct fkt_plan_s {
     // learned spectral preconditioner, built on first use for a given sigma2
     fkt::LearnState* learn = nullptr;
     double learn_sigma2 = -1.0;
+    // two-level preconditioning (fkt_precond_coarse): rank and sigma2
+    int coarse_k = 0;
+    double coarse_sigma2 = -1.0;
 
     void drop_events()
     {
@@ -339,7 +362,8 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
     if (leaf_size < 1) return fail(FKT_EINVAL, "leaf_size must be >= 1");
     if (order < 0) return fail(FKT_EINVAL, "order must be >= 0");
     if (!fkt::far_supported(d, order))
-        return fail(FKT_EUNSUPPORTED, "order " + std::to_string(order) + " not built for d = " + std::to_string(d));
+        return fail(FKT_EUNSUPPORTED, "order " + std::to_string(order) + " not built for d = " + std::to_string(d) +
+                                          " (built orders: 0.." + std::to_string(fkt::far_max_order(d)) + ")");
     if (!(opt.theta > 0.0 && opt.theta < 1.0)) return fail(FKT_EINVAL, "theta must be in (0, 1)");
     if (opt.prec != FKT_F64 && opt.prec != FKT_F32) return fail(FKT_EINVAL, "unknown precision");
     if (opt.mrhs < 0 || opt.mrhs > 2) return fail(FKT_EINVAL, "mrhs must be 0, 1 or 2");
@@ -532,11 +556,53 @@ fkt_status fkt_plan_target_counts(fkt_plan_t P, int64_t* far_nodes, int64_t* far
     return FKT_OK;
 }
 
+fkt_status fkt_plan_lists(fkt_plan_t P, int64_t* far_off, int64_t* far_node, int64_t* near_off, int64_t* near_leaf,
+                          int64_t* nfar_total, int64_t* nnear_total)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    const fkt::Lists& L = P->L;
+    const fkt::Tree& T = P->T;
+    const int64_t n = P->n, nb = (int64_t)L.blk_begin.size();
+    // leaf id of each leaf's first tree position (near entries are point ranges)
+    std::vector<int32_t> leaf_at(n + 1, -1);
+    for (int64_t b = 0; b < T.nnodes(); ++b)
+        if (T.leaf(b) && T.end[b] > T.begin[b]) leaf_at[T.begin[b]] = (int32_t)b;
+    std::vector<std::vector<int64_t>> fl(n), nl(n);
+    for (int64_t q = 0; q < nb; ++q) {
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e)
+            for (int lane = 0; lane < L.blk_count[q]; ++lane)
+                if ((L.far_mask[e] >> lane) & 1)
+                    fl[T.perm[L.blk_begin[q] + lane]].push_back(L.slot_node[L.far_slot[e]]);
+        for (int e = L.near_off[q]; e < L.near_off[q + 1]; ++e)
+            for (int lane = 0; lane < L.blk_count[q]; ++lane)
+                if ((L.near_mask[e] >> lane) & 1) nl[T.perm[L.blk_begin[q] + lane]].push_back(leaf_at[L.near_beg[e]]);
+    }
+    int64_t tf = 0, tn = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        std::sort(fl[t].begin(), fl[t].end());
+        std::sort(nl[t].begin(), nl[t].end());
+        if (far_off) far_off[t] = tf;
+        if (near_off) near_off[t] = tn;
+        if (far_node) std::copy(fl[t].begin(), fl[t].end(), far_node + tf);
+        if (near_leaf) std::copy(nl[t].begin(), nl[t].end(), near_leaf + tn);
+        tf += (int64_t)fl[t].size();
+        tn += (int64_t)nl[t].size();
+    }
+    if (far_off) far_off[n] = tf;
+    if (near_off) near_off[n] = tn;
+    if (nfar_total) *nfar_total = tf;
+    if (nnear_total) *nnear_total = tn;
+    return FKT_OK;
+}
+
 // Spectra of the leaf blocks for sigma2 (host eigendecompositions) and the
 // network's device state; weights are kept across sigma2 changes.
 static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
 {
     if (P->learn && P->learn_sigma2 == sigma2) return FKT_OK;
+    // a coarse part belongs to its sigma2; the new spectra replace it
+    P->coarse_k = 0;
+    P->coarse_sigma2 = -1.0;
     int64_t big = 0;
     for (int64_t b = 0; b < P->T.nnodes(); ++b)
         if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
@@ -557,6 +623,106 @@ static fkt_status ensure_learn(fkt_plan_t P, double sigma2)
     return FKT_OK;
 }
 
+fkt_status fkt_precond_coarse(fkt_plan_t P, double sigma2, const int64_t* landmarks, int k)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) has no preconditioner state");
+    if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be > 0");
+    if (k < 0 || k > fkt::kCoarseMaxRank) return fail(FKT_EINVAL, "k must be in [0, 4096]");
+    if (k > P->n) return fail(FKT_EINVAL, "k exceeds the number of points");
+    if (k > 0 && !landmarks) return fail(FKT_EINVAL, "landmarks is NULL");
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    if (k == 0) {
+        // back to one-level: drop the coarse part and rebuild the plain spectra on next use
+        if (P->learn) (void)fkt::learn_set_coarse(P->learn, nullptr, 0);
+        if (P->coarse_k > 0) P->learn_sigma2 = -1.0;
+        P->coarse_k = 0;
+        P->coarse_sigma2 = -1.0;
+        return FKT_OK;
+    }
+    int64_t big = 0;
+    for (int64_t b = 0; b < P->T.nnodes(); ++b)
+        if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
+    if (big > fkt::kLearnMaxLeaf) return fail(FKT_EUNSUPPORTED, "two-level preconditioning needs leaves of at most 2048 points");
+    // landmarks: caller order -> tree positions, distinct
+    const int64_t n = P->n;
+    std::vector<int64_t> pos(n);
+    for (int64_t i = 0; i < n; ++i) pos[P->T.perm[i]] = i;
+    std::vector<int32_t> cols(k);
+    std::vector<char> seen(n, 0);
+    for (int j = 0; j < k; ++j) {
+        const int64_t c = landmarks[j];
+        if (c < 0 || c >= n) return fail(FKT_EINVAL, "landmark index out of range");
+        if (seen[c]) return fail(FKT_EINVAL, "landmark indices must be distinct");
+        seen[c] = 1;
+        cols[j] = (int32_t)pos[c];
+    }
+    // W = chol(K(X_J, X_J) + sigma2 I)^-T on the host
+    const int d = P->d;
+    std::vector<double> KJ((size_t)k * k), W((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s2 = 0.0;
+            for (int a = 0; a < d; ++a) {
+                const double u = P->T.pts[(int64_t)cols[i] * d + a] - P->T.pts[(int64_t)cols[j] * d + a];
+                s2 += u * u;
+            }
+            KJ[(size_t)i * k + j] = KJ[(size_t)j * k + i] = fkt::kernel_value(P->kern, std::sqrt(s2)) + (i == j ? sigma2 : 0.0);
+        }
+    if (!fkt::chol_inv_t(k, KJ.data(), W.data()))
+        return fail(FKT_EINVAL, "the landmark block K(X_J, X_J) + sigma2 I is not positive definite");
+    // device: K(X, X_J), the factor L = K(X, X_J) W, and the leaf blocks L_l L_l^T
+    hipStream_t s = P->stream;
+    DevTmp tmp;
+    fkt::LeafSpectra S;
+    fkt::leaf_layout(P->T, S);
+    const int nl = (int)S.leaf_begin.size();
+    int32_t* dcols = nullptr;
+    double *dW = nullptr, *KnJ = nullptr, *Lm = nullptr, *Sb = nullptr;
+    fkt::Gemm64* desc = nullptr;
+    hipError_t e;
+    if ((e = tmp.get(k, &dcols)) || (e = tmp.get((size_t)k * k, &dW)) || (e = tmp.get((size_t)n * k, &KnJ)) ||
+        (e = tmp.get((size_t)n * k, &Lm)) || (e = tmp.get(S.off.back(), &Sb)) || (e = tmp.get(nl + 1, &desc)))
+        return hip_fail(e, "two-level work buffers");
+    std::vector<fkt::Gemm64> dd;
+    dd.push_back(fkt::Gemm64{(int)n, k, k, k, k, k, 0, 0, 0, 0});  // L = K(X, X_J) W
+    int maxm = 0;
+    for (int l = 0; l < nl; ++l) {  // L_l L_l^T
+        const int m = S.leaf_count[l];
+        const int64_t b0 = S.leaf_begin[l];
+        maxm = std::max(maxm, m);
+        dd.push_back(fkt::Gemm64{m, m, k, k, k, m, b0 * k, b0 * k, S.off[l], 0});
+    }
+    std::vector<double> Sh(S.off.back());
+    if ((e = hipMemcpy(dcols, cols.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(dW, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(desc, dd.data(), sizeof(fkt::Gemm64) * dd.size(), hipMemcpyHostToDevice)) ||
+        (e = fkt::kernel_columns(P->dp, dcols, k, KnJ, s)) ||
+        (e = fkt::gemm64_batched(false, false, desc, 1, (int)n, k, KnJ, dW, nullptr, Lm, 1.0, 0.0, s)) ||
+        (e = fkt::gemm64_batched(false, true, desc + 1, nl, maxm, maxm, Lm, Lm, nullptr, Sb, 1.0, 0.0, s)) ||
+        (e = hipMemcpyAsync(Sh.data(), Sb, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, s)) ||
+        (e = hipStreamSynchronize(s)))
+        return hip_fail(e, "two-level factor");
+    // spectra of the residual leaf blocks, then the coarse matrices
+    if (!fkt::build_leaf_spectra(P->T, P->kern, sigma2, P->leaf, S, Sh.data()))
+        return fail(FKT_EINVAL, "a residual leaf block K_ll + sigma2 I - L_l L_l^T has no positive spectrum");
+    if (!P->learn) {
+        std::string err;
+        P->learn = fkt::learn_create(P->opt.device, P->stream, S, P->dp.perm, P->n, 0x5EEDull, err);
+        if (!P->learn) return fail(FKT_ENOMEM, err);
+    } else if ((e = fkt::learn_update_spectra(P->learn, S)) != hipSuccess) {
+        return hip_fail(e, "two-level spectra upload");
+    }
+    P->learn_sigma2 = sigma2;
+    if ((e = fkt::learn_set_coarse(P->learn, Lm, k)) != hipSuccess)
+        return e == hipErrorInvalidValue ? fail(FKT_EINVAL, "the coarse matrix I + G^T diag(h) G is not positive definite")
+                                         : hip_fail(e, "two-level coarse matrices");
+    P->coarse_k = k;
+    P->coarse_sigma2 = sigma2;
+    return FKT_OK;
+}
+
 // fkt_cg_solve without (fallback_at NULL) or with the learned filter's
 // block-Jacobi fallback; the judge runs the filter on its own.
 static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
@@ -573,7 +739,8 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
     if (precond < 0 || precond > 2) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
     DeviceScope ds(P->opt.device);
     if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
-    if (precond == 2) {
+    const bool two_level = P->coarse_k > 0 && P->coarse_sigma2 == sigma2 && P->learn;
+    if (precond == 2 && !two_level) {
         const fkt_status st = ensure_learn(P, sigma2);
         if (st != FKT_OK) return st;
     }
@@ -584,7 +751,10 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
             if (P->T.leaf(b)) big = std::max<int64_t>(big, P->T.end[b] - P->T.begin[b]);
         if (big > 4096) return fail(FKT_EUNSUPPORTED, "block-Jacobi needs leaves of at most 4096 points");
     }
-    if (precond >= 1 && P->bj_sigma2 != sigma2) {
+    // two-level: block-Jacobi and the learned filter both run on the residual
+    // leaf spectra with the coarse correction (learned state built by
+    // fkt_precond_coarse)
+    if (precond >= 1 && !two_level && P->bj_sigma2 != sigma2) {
         std::vector<int32_t> lb, lc;
         std::vector<int64_t> off;
         std::vector<double> inv;
@@ -616,6 +786,7 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
     fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
                       P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
+    v.coarse = two_level ? 1 : 0;
     return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at, io64, P64,
                               v64, replaced);
 }

@@ -62,8 +62,10 @@ constexpr int m2t_max_job_nodes(int d, int p, int elem_bytes)
     return n < 1 ? 1 : (n > 8 ? 8 : (int)n);
 }
 
-// Whether kernels for (d, p) are compiled into the library.
+// Whether kernels for (d, p) are compiled into the library, and the highest
+// order built for d (-1 for none).
 bool far_supported(int d, int p);
+int far_max_order(int d);
 
 // One column of y = K~ x: gather, s2m, m2t, near (+ far) and scatter.
 // x, y: n x nrhs row-major in the plan's precision; col selects the column.
@@ -87,6 +89,7 @@ struct CgPlanView {
     int nseg;                // independent systems per column: instances of a batched plan
     const int64_t* seg_off;  // device [nseg + 1]: instance rows [seg_off[i], seg_off[i + 1]) (user order)
     const int32_t* row_seg;  // device [n]: instance of each row (NULL when nseg = 1)
+    int coarse = 0;          // two-level: precond 1 and 2 run through learn_apply with the coarse part
 };
 
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,

@@ -136,6 +136,13 @@ struct LeafSpectra {
     std::vector<float> feat;    // [n][kLearnFeat]
     int max_leaf = 0;
 };
-bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int leaf_cap, LeafSpectra& S);
+// Eigendecompositions of the leaf blocks K_ll + sigma2 I, or, with sub (one
+// m x m block per leaf at the offsets of leaf_layout), of K_ll + sigma2 I -
+// sub_l (symmetrised).
+bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int leaf_cap, LeafSpectra& S,
+                        const double* sub = nullptr);
+// Leaf layout of the spectra (leaf_begin, leaf_count, off) without the
+// eigendecompositions.
+void leaf_layout(const Tree& T, LeafSpectra& S);
 
 }  // namespace fkt

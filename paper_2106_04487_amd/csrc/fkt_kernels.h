@@ -828,7 +828,7 @@ __global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restric
 
 template <int D> struct PMax;
 template <> struct PMax<3> { static constexpr int value = 8; };
-template <> struct PMax<4> { static constexpr int value = 6; };
+template <> struct PMax<4> { static constexpr int value = 8; };
 template <> struct PMax<5> { static constexpr int value = 8; };
 
 constexpr int kChunk = 128;  // s2m moment entries accumulated per lane and launch

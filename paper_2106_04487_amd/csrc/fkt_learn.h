@@ -27,8 +27,16 @@ hipError_t learn_params(LearnState* L, float* host, bool set);
 hipError_t learn_grad(LearnState* L, float* host);
 // x (device, n, FP32 or FP64) <- N(0, 1) draws keyed by key; synchronises
 hipError_t learn_randn(LearnState* L, void* x, int64_t n, bool f32, uint64_t key);
+// h = exp(o) / lam from the current weights (and, two-level, C^-1 for it)
 hipError_t learn_prepare_filter(LearnState* L);
-hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s);
+// z[:, col] = M r[:, col]: the learned filter, or with bj its block-Jacobi
+// state h = 1 / lam; two-level when a coarse part is set
+hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s, bool bj = false);
+// Coarse part from the Nystrom factor Lmat (device, n x k, tree-order rows);
+// k = 0 (or Lmat NULL) drops it. The spectra must be those of the residual
+// blocks K_ll + sigma2 I - L_l L_l^T. Synchronises.
+hipError_t learn_set_coarse(LearnState* L, const double* Lmat, int k);
+int learn_coarse_rank(const LearnState* L);
 fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, const double* v, int B, double* loss);
 fkt_status learn_train(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int B, double lr, uint64_t seed,
                        double* loss_first, double* loss_last);

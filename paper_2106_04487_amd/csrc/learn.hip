@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "../../include/fkt.h"
+#include "fkt_coarse.h"
 #include "fkt_learn.h"
 
 namespace fkt {
@@ -303,6 +304,60 @@ __global__ __launch_bounds__(kT) void k_spec_apply(const int* __restrict__ begin
     }
 }
 
+// Two-level pieces (one column): s = V x[:, col] into a tree-order vector,
+// and y[:, col] = V^T (h .* c) from a tree-order vector.
+__global__ __launch_bounds__(kT) void k_spec_proj1(const int* __restrict__ begin, const int* __restrict__ count,
+                                                   const int64_t* __restrict__ off, const double* __restrict__ Vt,
+                                                   const int64_t* __restrict__ perm, int nrhs, int col,
+                                                   const double* __restrict__ x, double* __restrict__ out)
+{
+    extern __shared__ double xl[];
+    const int l = blockIdx.x, b = begin[l], m = count[l];
+    const double* __restrict__ Q = Vt + off[l];
+    for (int j = threadIdx.x; j < m; j += kT) xl[j] = x[perm[b + j] * nrhs + col];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kT) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s = fma(Q[(size_t)j * m + i], xl[j], s);
+        out[b + i] = s;
+    }
+}
+__global__ __launch_bounds__(kT) void k_spec_recon1(const int* __restrict__ begin, const int* __restrict__ count,
+                                                    const int64_t* __restrict__ off, const double* __restrict__ V,
+                                                    const int64_t* __restrict__ perm, const double* __restrict__ h,
+                                                    const double* __restrict__ c, int nrhs, int col,
+                                                    double* __restrict__ y)
+{
+    extern __shared__ double cl[];
+    const int l = blockIdx.x, b = begin[l], m = count[l];
+    const double* __restrict__ Q = V + off[l];
+    for (int i = threadIdx.x; i < m; i += kT) cl[i] = h[b + i] * c[b + i];
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += kT) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s = fma(Q[(size_t)i * m + j], cl[i], s);
+        y[perm[b + j] * nrhs + col] = s;
+    }
+}
+// column col of a [n][B] tree-order array <-> a contiguous vector
+__global__ __launch_bounds__(kT) void k_put_col(int64_t n, int B, int col, const double* __restrict__ v,
+                                                double* __restrict__ a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) a[i * B + col] = v[i];
+}
+__global__ __launch_bounds__(kT) void k_get_col(int64_t n, int B, int col, const double* __restrict__ a,
+                                                double* __restrict__ v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) v[i] = a[i * B + col];
+}
+__global__ __launch_bounds__(kT) void k_recip(int64_t n, const double* __restrict__ lam, double* __restrict__ h)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) h[i] = 1.0 / lam[i];
+}
+
 // go[i] = h_i sum_b c[i][b] p[i][b] scale[b]  (FP32 out), 0 for padding
 __global__ __launch_bounds__(kT) void k_dout(int64_t n, int64_t Sp, int B, const double* __restrict__ h,
                                              const double* __restrict__ c, const double* __restrict__ p,
@@ -406,6 +461,36 @@ struct LearnState {
     int nsplit = 1, nchunks = 1;
     int64_t adam_t = 0;
     std::vector<void*> allocs;
+    // host copy of the leaf layout
+    std::vector<int32_t> hbegin, hcount;
+    std::vector<int64_t> hoff;
+    // two-level state (ck > 0): G = V L per leaf [n][ck] (tree-order rows),
+    // C^-1 for block-Jacobi (h = 1 / lam) and for the learned filter, and
+    // work vectors of the coarse correction
+    int ck = 0;
+    double *cG = nullptr, *cCinv_bj = nullptr, *cCinv = nullptr, *h_bj = nullptr;
+    double *cs = nullptr, *cy = nullptr, *cpart = nullptr, *cu = nullptr, *cw = nullptr, *cgram = nullptr;
+    Gemm64* cdesc = nullptr;
+    int cnz = 0;
+    std::vector<void*> coarse_allocs;
+    void drop_coarse()
+    {
+        (void)hipStreamSynchronize(s);
+        for (void* q : coarse_allocs) (void)hipFree(q);
+        coarse_allocs.clear();
+        ck = 0;
+        cG = cCinv_bj = cCinv = h_bj = cs = cy = cpart = cu = cw = cgram = nullptr;
+        cdesc = nullptr;
+    }
+    template <class T>
+    hipError_t cget(size_t count, T** out)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+        if (e == hipSuccess) coarse_allocs.push_back(q);
+        *out = (T*)q;
+        return e;
+    }
 
     template <class T>
     hipError_t get(size_t count, T** out)
@@ -418,7 +503,7 @@ struct LearnState {
     }
     ~LearnState()
     {
-        (void)hipStreamSynchronize(s);
+        drop_coarse();
         for (void* q : allocs) (void)hipFree(q);
     }
 };
@@ -466,6 +551,9 @@ LearnState* learn_create(int device, hipStream_t s, const LeafSpectra& S, const 
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) b[(size_t)j * m + i] = a[(size_t)i * m + j];
     }
+    L->hbegin = S.leaf_begin;
+    L->hcount = S.leaf_count;
+    L->hoff = S.off;
     std::vector<float> X((size_t)Sp * kF, 0.f);
     std::copy(S.feat.begin(), S.feat.end(), X.begin());
     std::vector<float> p0;
@@ -509,6 +597,7 @@ hipError_t learn_update_spectra(LearnState* L, const LeafSpectra& S)
     std::copy(S.feat.begin(), S.feat.end(), X.begin());
     hipError_t e;
     if ((e = hipStreamSynchronize(L->s)) != hipSuccess) return e;
+    L->drop_coarse();  // the coarse part belongs to the previous spectra
     if ((e = hipMemcpy(L->V, S.vecs.data(), sizeof(double) * S.vecs.size(), hipMemcpyHostToDevice))) return e;
     if ((e = hipMemcpy(L->Vt, vt.data(), sizeof(double) * vt.size(), hipMemcpyHostToDevice))) return e;
     if ((e = hipMemcpy(L->lam, S.vals.data(), sizeof(double) * L->n, hipMemcpyHostToDevice))) return e;
@@ -536,12 +625,106 @@ static hipError_t forward(LearnState* L)
     return hipGetLastError();
 }
 
-hipError_t learn_prepare_filter(LearnState* L) { return forward(L); }
-
-hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s)
+// C^-1 with C = I + G^T diag(h) G (k x k): split-row product on the device,
+// inverse on the host (FP64, SPD), back to Cinv. Synchronises.
+static hipError_t coarse_inverse(LearnState* L, const double* h, double* Cinv)
 {
-    hipLaunchKernelGGL(k_spec_apply, dim3(L->nleaf), dim3(kT), sizeof(double) * 2 * L->maxleaf, s, L->leaf_begin,
-                       L->leaf_count, L->off, L->V, L->Vt, L->perm, L->h, nrhs, col, r, z);
+    const int k = L->ck;
+    hipStream_t s = L->s;
+    hipError_t e = gemm64_batched(true, false, L->cdesc, L->cnz, k, k, L->cG, L->cG, h, L->cgram, 1.0, 0.0, s);
+    if (e != hipSuccess) return e;
+    if ((e = sum_partials64(L->cnz, (int64_t)k * k, L->cgram, L->cs, k, s)) != hipSuccess) return e;
+    std::vector<double> C((size_t)k * k);
+    if ((e = hipMemcpyAsync(C.data(), L->cs, sizeof(double) * C.size(), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (!spd_inverse(k, C.data())) return hipErrorInvalidValue;
+    return hipMemcpy(Cinv, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice);
+}
+
+hipError_t learn_set_coarse(LearnState* L, const double* Lmat, int k)
+{
+    L->drop_coarse();
+    if (k <= 0 || !Lmat) return hipSuccess;
+    const int64_t n = L->n;
+    // the split-row products of C read cgram = cnz k x k partials; cs doubles
+    // as the k x k staging buffer, so it holds max(n, k^2)
+    L->cnz = (int)std::max<int64_t>(1, std::min<int64_t>(64, n / 4096));
+    hipError_t e;
+    if ((e = L->cget((size_t)n * k, &L->cG)) || (e = L->cget((size_t)k * k, &L->cCinv_bj)) ||
+        (e = L->cget((size_t)k * k, &L->cCinv)) || (e = L->cget(n, &L->h_bj)) ||
+        (e = L->cget(std::max<size_t>(n, (size_t)k * k), &L->cs)) || (e = L->cget(n, &L->cy)) ||
+        (e = L->cget((size_t)kCoarseChunks * k, &L->cpart)) || (e = L->cget(k, &L->cu)) || (e = L->cget(k, &L->cw)) ||
+        (e = L->cget((size_t)L->cnz * k * k, &L->cgram)) || (e = L->cget(L->nleaf + L->cnz, &L->cdesc))) {
+        L->drop_coarse();
+        return e;
+    }
+    L->ck = k;
+    // descriptors: per leaf G_l = V_l L_l; then the split rows of C
+    std::vector<Gemm64> d;
+    int maxm = 0;
+    for (int l = 0; l < L->nleaf; ++l) {
+        const int m = L->hcount[l];
+        const int64_t b0 = L->hbegin[l];
+        maxm = std::max(maxm, m);
+        d.push_back(Gemm64{m, k, m, m, k, k, L->hoff[l], b0 * k, b0 * k, 0});
+    }
+    const int64_t rows = (n + L->cnz - 1) / L->cnz;
+    for (int z = 0; z < L->cnz; ++z) {
+        const int64_t r0 = std::min<int64_t>(n, z * rows), r1 = std::min<int64_t>(n, r0 + rows);
+        d.push_back(Gemm64{k, k, (int)(r1 - r0), k, k, k, r0 * k, r0 * k, (int64_t)z * k * k, r0});
+    }
+    if ((e = hipMemcpy(L->cdesc, d.data(), sizeof(Gemm64) * d.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = gemm64_batched(false, false, L->cdesc, L->nleaf, maxm, k, L->V, Lmat, nullptr, L->cG, 1.0, 0.0, L->s)) !=
+            hipSuccess) {
+        L->drop_coarse();
+        return e;
+    }
+    L->cdesc += L->nleaf;  // the remaining descriptors are the C products
+    hipLaunchKernelGGL(k_recip, dim3(blocks_of(n)), dim3(kT), 0, L->s, n, L->lam, L->h_bj);
+    if ((e = coarse_inverse(L, L->h_bj, L->cCinv_bj)) != hipSuccess) {
+        L->drop_coarse();
+        return e;
+    }
+    return hipSuccess;
+}
+
+int learn_coarse_rank(const LearnState* L) { return L ? L->ck : 0; }
+
+hipError_t learn_prepare_filter(LearnState* L)
+{
+    hipError_t e = forward(L);
+    if (e != hipSuccess || L->ck == 0) return e;
+    return coarse_inverse(L, L->h, L->cCinv);
+}
+
+// psi(y) = y - G C^-1 G^T (h .* y) for tree-order vectors
+static hipError_t coarse_psi(LearnState* L, const double* h, const double* Cinv, const double* y, double* out,
+                             hipStream_t s)
+{
+    hipError_t e;
+    if ((e = gemv_t_weighted(L->n, L->ck, L->cG, h, y, L->cpart, kCoarseChunks, L->cu, s)) != hipSuccess) return e;
+    if ((e = gemv_small(L->ck, Cinv, L->cu, L->cw, s)) != hipSuccess) return e;
+    return gemv_sub(L->n, L->ck, L->cG, L->cw, y, out, s);
+}
+
+hipError_t learn_apply(LearnState* L, const double* r, double* z, int nrhs, int col, hipStream_t s, bool bj)
+{
+    const size_t lds = sizeof(double) * L->maxleaf;
+    if (L->ck == 0) {
+        if (bj) return hipErrorInvalidValue;  // one-level block-Jacobi runs on the Cholesky factors (cg.hip)
+        hipLaunchKernelGGL(k_spec_apply, dim3(L->nleaf), dim3(kT), 2 * lds, s, L->leaf_begin, L->leaf_count, L->off,
+                           L->V, L->Vt, L->perm, L->h, nrhs, col, r, z);
+        return hipGetLastError();
+    }
+    // two-level: z = V^T (h .* psi(V r))
+    const double* h = bj ? L->h_bj : L->h;
+    hipLaunchKernelGGL(k_spec_proj1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
+                       L->perm, nrhs, col, r, L->cs);
+    hipError_t e = coarse_psi(L, h, bj ? L->cCinv_bj : L->cCinv, L->cs, L->cy, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spec_recon1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->V,
+                       L->perm, h, L->cy, nrhs, col, z);
     return hipGetLastError();
 }
 
@@ -628,11 +811,20 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
         }
         return hipGetLastError() == hipSuccess ? FKT_OK : FKT_EDEVICE;
     };
-    if (forward(L) != hipSuccess) return FKT_EDEVICE;
+    if (learn_prepare_filter(L) != hipSuccess) return FKT_EDEVICE;  // h, and C^-1 for it (two-level)
     const size_t lds = sizeof(double) * L->maxleaf;
+    // c = V v, or psi(V v) with the coarse part (P = V^T diag(h) psi V);
+    // w = P v
     for (int b = 0; b < B; ++b) {
-        hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
-                           L->perm, B, b, v, c, B);
+        if (L->ck == 0) {
+            hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off,
+                               L->Vt, L->perm, B, b, v, c, B);
+        } else {
+            hipLaunchKernelGGL(k_spec_proj1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off,
+                               L->Vt, L->perm, B, b, v, L->cs);
+            if (coarse_psi(L, L->h, L->cCinv, L->cs, L->cy, s) != hipSuccess) return FKT_EDEVICE;
+            hipLaunchKernelGGL(k_put_col, dim3(blocks_of(n)), dim3(kT), 0, s, n, B, b, L->cy, c);
+        }
         hipLaunchKernelGGL(k_spec_recon, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->V,
                            L->perm, L->h, c, B, B, b, w);
     }
@@ -649,9 +841,20 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
     *loss = lsum / B;
     st = op(r, nullptr, g);  // g = A r (A taken as symmetric)
     if (st != FKT_OK) return st;
-    for (int b = 0; b < B; ++b)
-        hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
-                           L->perm, B, b, g, pp, B);
+    // dL/dh needs (psi V g) and (psi V v): the derivative of P = V^T diag(h)
+    // psi V in h is V^T E diag(dh) E^T V with E^T = psi, C's dependence on h
+    // included
+    for (int b = 0; b < B; ++b) {
+        if (L->ck == 0) {
+            hipLaunchKernelGGL(k_spec_proj, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off,
+                               L->Vt, L->perm, B, b, g, pp, B);
+        } else {
+            hipLaunchKernelGGL(k_spec_proj1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off,
+                               L->Vt, L->perm, B, b, g, L->cs);
+            if (coarse_psi(L, L->h, L->cCinv, L->cs, L->cy, s) != hipSuccess) return FKT_EDEVICE;
+            hipLaunchKernelGGL(k_put_col, dim3(blocks_of(n)), dim3(kT), 0, s, n, B, b, L->cy, pp);
+        }
+    }
     for (int b = 0; b < B; ++b) ab[B + b] = nv[b] > 0.0 ? 2.0 * ab[b] / (B * nv[b]) : 0.0;
     if (hipMemcpyAsync(vv, ab.data() + B, sizeof(double) * B, hipMemcpyHostToDevice, s) != hipSuccess)
         return FKT_EDEVICE;

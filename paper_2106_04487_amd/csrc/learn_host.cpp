@@ -125,9 +125,8 @@ bool sym_eig(int n, double* a, double* w)
     return true;
 }
 
-bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int leaf_cap, LeafSpectra& S)
+void leaf_layout(const Tree& T, LeafSpectra& S)
 {
-    const int d = T.d;
     S.leaf_begin.clear();
     S.leaf_count.clear();
     S.off.assign(1, 0);
@@ -138,6 +137,13 @@ bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int l
         S.leaf_count.push_back((int32_t)m);
         S.off.push_back(S.off.back() + m * m);
     }
+}
+
+bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int leaf_cap, LeafSpectra& S,
+                        const double* sub)
+{
+    const int d = T.d;
+    leaf_layout(T, S);
     const int64_t nl = (int64_t)S.leaf_begin.size();
     S.vecs.assign(S.off.back(), 0.0);
     S.vals.assign(T.n, 0.0);
@@ -157,7 +163,9 @@ bool build_leaf_spectra(const Tree& T, const fkt_kernel& k, double sigma2, int l
                         const double u = T.pts[(b0 + i) * d + c] - T.pts[(b0 + j) * d + c];
                         s += u * u;
                     }
-                    const double kv = kernel_value(k, std::sqrt(s)) + (i == j ? sigma2 : 0.0);
+                    double kv = kernel_value(k, std::sqrt(s)) + (i == j ? sigma2 : 0.0);
+                    // two-level: the residual block, less the coarse part L_l L_l^T
+                    if (sub) kv -= 0.5 * (sub[S.off[l] + (size_t)i * m + j] + sub[S.off[l] + (size_t)j * m + i]);
                     A[(size_t)i * m + j] = A[(size_t)j * m + i] = kv;
                 }
             double* lam = S.vals.data() + b0;

@@ -1,5 +1,6 @@
-// Many right-hand sides (groups of 32 columns, FP32 plans): the near field
-// runs on the matrix cores, the far field column by column.
+// Many right-hand sides (groups of 32 columns, FP32 plans): the near field on
+// the matrix cores (this file); the moments (s2m_mrhs.hip) and the far-field
+// evaluation (m2t_mrhs.hip) of the 32 columns on the matrix cores too.
 //
 // Near field (Algorithm 1, near_mat, for 32 columns at once): one wave owns
 // a 64-target block and walks the union of its targets' near leaves. For

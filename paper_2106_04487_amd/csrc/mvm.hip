@@ -186,15 +186,17 @@ hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* xv
     return hipGetLastError();
 }
 
-bool far_supported(int d, int p)
+int far_max_order(int d)
 {
     switch (d) {
-    case 3: return p >= 0 && p <= PMax<3>::value;
-    case 4: return p >= 0 && p <= PMax<4>::value;
-    case 5: return p >= 0 && p <= PMax<5>::value;
-    default: return false;
+    case 3: return PMax<3>::value;
+    case 4: return PMax<4>::value;
+    case 5: return PMax<5>::value;
+    default: return -1;
     }
 }
+
+bool far_supported(int d, int p) { return p >= 0 && p <= far_max_order(d); }
 
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col, int prec,
                              hipStream_t s, bool overlap, hipEvent_t* ev)

@@ -66,13 +66,51 @@ def test_loss_and_gradient_match_oracle(F, prec):
     lref, gref = LR.loss_grad(sp, params.astype(np.float64), v, op)
     gerr = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
     print(f"loss gpu {loss:.10e} oracle {lref:.10e}; gradient rel err {gerr:.3e}")
-    # FP32 network: o (and so h) carries ~1e-6 relative rounding
+    # FP32 network: o (and so h) carries ~1e-6 relative rounding; the whole
+    # gradient agrees to about 2e-6, so the bar is ten times that
     assert abs(loss - lref) <= 1e-5 * lref
-    assert gerr <= 2e-3
+    assert gerr <= 3e-5
     offs = np.cumsum([0] + [int(np.prod(s)) for _, s in LR.SIZES])
     for (name, _), a, b in zip(LR.SIZES, offs[:-1], offs[1:]):
         e = np.linalg.norm(grad[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-30)
-        assert e <= 5e-3, (name, e)
+        print(f"  gradient block {name}: rel err {e:.2e}")
+        assert e <= 3e-4, (name, e)
+    plan.close()
+
+
+@pytest.mark.parametrize("weights", ["random", "near_zero_output"])
+def test_cg_filter_apply_matches_oracle(F, weights):
+    """The CG-side filter kernel (M r for the solve, not the training path):
+    one PCG step from x0 = 0 gives x1 = alpha M b, so its direction must be
+    the oracle's M b (oracle/learned.apply_filter). With random weights, and
+    with an output layer of w3 = 0, b3 = 1e-30 (non-zero, so the solve takes
+    the spectral path, and M is block-Jacobi to rounding)."""
+    import torch
+    n, leaf, theta, p, sig2 = 2500, 100, 0.4, 5, 1e-2
+    X = _gp_points(n, 64)
+    kw = dict(lengthscale=0.3)
+    plan = F.fkt_plan(X, "matern52", leaf, p, theta=theta, **kw)
+    params = np.random.default_rng(15).normal(0.0, 0.15, LR.NPARAMS)
+    if weights != "random":
+        P = LR.unpack(params)
+        P["w3"][:] = 0.0
+        P["b3"] = np.array(1e-30)
+        params = LR.pack(P)
+    params = params.astype(np.float32)
+    F.fkt_learn_params(plan, sig2, params)
+    b = W.normal_rhs(n, 1, 76)[:, 0]
+    with pytest.raises(F.FktError) as ei:
+        F.fkt_cg_solve(plan, sig2, torch.as_tensor(b, device="cuda"), rtol=1e-30, maxit=1, precond="learned")
+    assert ei.value.iters == 1 and plan.info()["cg_fallback_iter"] == -1
+    x1 = ei.value.x.cpu().numpy()
+    T = oracle.Tree(X, leaf)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, leaf, **kw)
+    hs, _ = LR.filters(sp, params.astype(np.float64))
+    ref = LR.apply_filter(sp, hs, b[:, None])[:, 0]
+    a = float(x1 @ ref / (ref @ ref))
+    err = float(np.linalg.norm(x1 - a * ref) / np.linalg.norm(x1))
+    print(f"{weights}: one PCG step vs oracle M b: step {a:.4e}, direction error {err:.2e}")
+    assert a > 0 and err <= 1e-5
     plan.close()
 
 
@@ -194,3 +232,89 @@ def test_mixed_precision_cg_reaches_tolerance(F):
                   f"FP64-operator residual {t64:.2e} / {t32:.2e}")
             assert rel <= 1e-4
         assert sol[("refined", pc)][2] <= 1.01e-6
+
+
+def _two_level_case(F, n=2500, leaf=100, p=5, theta=0.4, k=96, seed=64):
+    X = _gp_points(n, seed)
+    kw = dict(lengthscale=0.3)
+    plan = F.fkt_plan(X, "matern52", leaf, p, theta=theta, **kw)
+    J = W.subsample(n, k, 77)
+    return X, kw, plan, J
+
+
+@pytest.mark.parametrize("weights", ["block_jacobi", "random"])
+def test_two_level_apply_matches_oracle(F, weights):
+    """Two-level preconditioner (Nystrom coarse space + residual leaf blocks,
+    joined by the Woodbury identity on the device) against its definition
+    P = (L L^T + D)^-1 as a dense inverse in the oracle: one PCG step from
+    zero gives x1 = alpha P b. Block-Jacobi of the residual blocks is basis
+    independent and FP64 throughout (bar 1e-10); the learned filter carries
+    the FP32 network's rounding (bar 1e-5)."""
+    import torch
+    sig2 = 1e-2
+    X, kw, plan, J = _two_level_case(F)
+    F.fkt_precond_coarse(plan, sig2, J)
+    params = np.zeros(LR.NPARAMS) if weights == "block_jacobi" else np.random.default_rng(16).normal(0.0, 0.15, LR.NPARAMS)
+    params = params.astype(np.float32)
+    F.fkt_learn_params(plan, sig2, params)
+    pc = "block_jacobi" if weights == "block_jacobi" else "learned"
+    b = W.normal_rhs(len(X), 1, 78)[:, 0]
+    with pytest.raises(F.FktError) as ei:
+        F.fkt_cg_solve(plan, sig2, torch.as_tensor(b, device="cuda"), rtol=1e-30, maxit=1, precond=pc)
+    x1 = ei.value.x.cpu().numpy()
+    T = oracle.Tree(X, 100)
+    Lf = LR.nystrom_factor(X, J, "matern52", sig2, **kw)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 100, coarse=Lf, **kw)
+    hs = [1.0 / Sl["lam"] for Sl in sp] if weights == "block_jacobi" else LR.filters(sp, params.astype(np.float64))[0]
+    ref = LR.two_level_matrix(sp, hs, Lf) @ b
+    a = float(x1 @ ref / (ref @ ref))
+    err = float(np.linalg.norm(x1 - a * ref) / np.linalg.norm(x1))
+    print(f"two-level {weights}: one PCG step vs oracle P b: direction error {err:.2e}")
+    assert a > 0 and err <= (1e-10 if weights == "block_jacobi" else 1e-5)
+    plan.close()
+
+
+def test_two_level_loss_and_gradient_match_oracle(F):
+    """fkt_learn_loss_grad through the two-level preconditioner against the
+    oracle's loss_grad with the coarse factor (dP = (P D) dM (D P))."""
+    sig2, theta, p = 1e-2, 0.4, 5
+    X, kw, plan, J = _two_level_case(F)
+    F.fkt_precond_coarse(plan, sig2, J)
+    params = np.random.default_rng(17).normal(0.0, 0.15, LR.NPARAMS).astype(np.float32)
+    F.fkt_learn_params(plan, sig2, params)
+    v = W.normal_rhs(len(X), 3, 79)
+    loss, grad = F.fkt_learn_loss_grad(plan, sig2, v)
+    T = oracle.Tree(X, 100)
+    Lf = LR.nystrom_factor(X, J, "matern52", sig2, **kw)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 100, coarse=Lf, **kw)
+    op = lambda x: oracle.fkt_alg1(T, x, "matern52", theta, p, **kw) + sig2 * x
+    lref, gref = LR.loss_grad(sp, params.astype(np.float64), v, op, coarse=Lf)
+    gerr = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
+    print(f"two-level loss gpu {loss:.10e} oracle {lref:.10e}; gradient rel err {gerr:.3e}")
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert gerr <= 3e-5
+    plan.close()
+
+
+def test_two_level_cuts_cg_iterations(F):
+    """At length scale 0.3 (the GP workload's) per-leaf block-Jacobi barely
+    helps CG; with a 256-landmark coarse space the same block-Jacobi, now of
+    the residual blocks, needs a fraction of the iterations."""
+    import torch
+    n, sig2 = 6000, 1e-2
+    X = _gp_points(n, 80)
+    plan = F.fkt_plan(X, "matern52", 128, 6, theta=0.3, lengthscale=0.3)
+    b = torch.as_tensor(W.gp_targets(X, 0.3, sig2, 512, 81), device="cuda")
+    its = {}
+    _, its["one_level"], _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=5000, precond="block_jacobi")
+    F.fkt_precond_coarse(plan, sig2, W.subsample(n, 256, 82))
+    _, its["two_level"], rr = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=5000, precond="block_jacobi")
+    print(f"block-Jacobi CG iterations at length scale 0.3: {its}")
+    assert rr <= 1e-6 and its["two_level"] <= 0.5 * its["one_level"]
+    # back to one-level: the same count as before (the MVM's atomic sums
+    # change the rounding from run to run, and so, slightly, the count of an
+    # ill-conditioned solve)
+    F.fkt_precond_coarse(plan, sig2, [])
+    _, it1, _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=5000, precond="block_jacobi")
+    assert abs(it1 - its["one_level"]) <= 0.02 * its["one_level"]
+    plan.close()

@@ -67,6 +67,35 @@ def test_host_plan_matches_oracle_partition(name, gen, leaf, theta):
     assert int(fp.sum() + npt.sum()) == X.shape[0] ** 2   # every (t, s) pair exactly once
 
 
+LIST_CASES = [
+    ("cube3_n2k_t0.25", lambda: W.uniform_cube(2000, 3, 1001), 128, 0.25),
+    ("cube3_n2k_t0.5", lambda: W.uniform_cube(2000, 3, 1001), 128, 0.5),
+    ("cube3_n2k_t0.75", lambda: W.uniform_cube(2000, 3, 1001), 128, 0.75),
+    ("cube3_n30k", lambda: W.uniform_cube(30000, 3, 7), 256, 0.35),
+    ("gmm4", lambda: W.gaussian_mixture(8000, 4, 8, 0.15, 9), 100, 0.5),
+    ("gmm5", lambda: W.gaussian_mixture(6000, 5, 10, 0.1, 10), 64, 0.6),
+    ("dups", lambda: W.clustered_duplicates(3000, 3, 40, 11), 32, 0.5),
+]
+
+
+@pytest.mark.parametrize("name,gen,leaf,theta", LIST_CASES, ids=[c[0] for c in LIST_CASES])
+def test_host_plan_lists_equal_oracle_walk(name, gen, leaf, theta):
+    """The plan's far nodes and near leaves of every target are the oracle
+    walk's (eq. accparam, Sec. 3.2), node for node: the mismatch count is 0."""
+    X = gen()
+    p = F.fkt_plan(X, "gaussian", leaf, 3, lengthscale=0.2, theta=theta, device=None, max_depth=30)
+    T = oracle.Tree(X, leaf, max_depth=30)
+    fo, fnode, no, nleaf = p.lists()
+    mismatched = 0
+    for t in range(X.shape[0]):
+        far, near = T.walk(X[t], theta)
+        mine_f, mine_n = fnode[fo[t]:fo[t + 1]], nleaf[no[t]:no[t + 1]]
+        if not (np.array_equal(mine_f, np.sort(far)) and np.array_equal(mine_n, np.sort(near))):
+            mismatched += 1
+    assert mismatched == 0, f"{mismatched} of {X.shape[0]} targets differ"
+    assert fo[-1] == p.info()["far_pairs"]
+
+
 def test_rank_is_binomial():
     from math import comb
     X = W.uniform_cube(500, 3, 1)

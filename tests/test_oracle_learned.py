@@ -63,3 +63,102 @@ def test_gradient_matches_central_differences():
         fd = (LR.loss_grad(sp, tp, v, op)[0] - LR.loss_grad(sp, tm, v, op)[0]) / (2 * eps)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-7 * np.abs(g).max(), (k, fd, g[k])
     assert L0 > 0.0
+
+
+def test_loss_closed_form_two_single_point_leaves():
+    """Two leaves of one point each: A = [[a, c], [c, a]] with a = K(0) +
+    sigma2 and c = K(r12). With any outputs o, M = diag(e^o1 / a, e^o2 / a),
+    so for v = e_1, u = A M v is parallel to (1, c / a) and the loss, the
+    squared sine of the angle between u and v, is t^2 / (1 + t^2) with
+    t = c / a; for v = (1, 1) and o1 = o2, u is parallel to v and L = 0."""
+    X = np.array([[0.1, 0.2, 0.3], [0.35, 0.1, 0.4]])
+    T = oracle.Tree(X, 1)
+    sig2, ell = 0.3, 0.4
+    sp = LR.leaf_spectra(T, X, "gaussian", sig2, 1, lengthscale=ell)
+    assert len(sp) == 2
+    r = np.linalg.norm(X[0] - X[1])
+    a, c = 1.0 + sig2, np.exp(-r * r / (2 * ell * ell))
+    A = np.array([[a, c], [c, a]])
+    op = lambda x: A @ x
+    rng = np.random.default_rng(4)
+    theta = rng.normal(0.0, 0.3, LR.NPARAMS)
+    t = c / a
+    L1, _ = LR.loss_grad(sp, theta, np.array([[1.0], [0.0]]), op)
+    assert abs(L1 - t * t / (1 + t * t)) <= 1e-14
+    p = LR.unpack(theta)
+    p["w3"][:] = 0.0  # o = b3 for every eigenvalue
+    p["b3"] = np.array(0.7)
+    L2, g2 = LR.loss_grad(sp, LR.pack(p), np.array([[1.0], [1.0]]), op)
+    assert L2 <= 1e-28 and np.abs(g2).max() <= 1e-13
+
+
+def test_single_leaf_block_jacobi_is_exact():
+    """One leaf holding every point and o = 0: M is the inverse of the whole
+    operator, so A M v = v for every v: loss 0 and (a minimum) gradient 0."""
+    X = W.gaussian_mixture(60, 4, 2, 0.2, 5)
+    T = oracle.Tree(X, 60)
+    sig2 = 1e-2
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 60, lengthscale=0.3)
+    A = LR.leaf_block(X, "matern52", sig2, lengthscale=0.3)
+    theta = np.random.default_rng(6).normal(0.0, 0.3, LR.NPARAMS)
+    p = LR.unpack(theta)
+    p["w3"][:] = 0.0
+    p["b3"] = np.zeros(())
+    v = np.random.default_rng(7).normal(size=(60, 2))
+    L, g = LR.loss_grad(sp, LR.pack(p), v, lambda x: A @ x)
+    assert L <= 1e-16 and np.abs(g).max() <= 1e-9
+
+
+def test_two_level_single_leaf_is_exact():
+    """One leaf and o = 0: D is the residual block A - L L^T itself, so
+    P = (L L^T + A - L L^T)^-1 = A^-1 and the loss is 0."""
+    X = W.gaussian_mixture(80, 4, 2, 0.2, 8)
+    T = oracle.Tree(X, 80)
+    sig2 = 1e-2
+    Lf = LR.nystrom_factor(X, W.subsample(80, 12, 9), "matern52", sig2, lengthscale=0.3)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 80, coarse=Lf, lengthscale=0.3)
+    A = LR.leaf_block(X, "matern52", sig2, lengthscale=0.3)
+    p = LR.unpack(np.random.default_rng(10).normal(0.0, 0.3, LR.NPARAMS))
+    p["w3"][:] = 0.0
+    p["b3"] = np.zeros(())
+    v = np.random.default_rng(11).normal(size=(80, 2))
+    L, g = LR.loss_grad(sp, LR.pack(p), v, lambda x: A @ x, coarse=Lf)
+    assert L <= 1e-14 and np.abs(g).max() <= 1e-7
+
+
+def test_nystrom_factor_reproduces_landmark_columns():
+    """L L^T on the landmark columns equals K(X, X_J) (K_JJ + s2 I)^-1 K_JJ,
+    and the residual K + s2 I - L L^T is positive definite (>= s2 I)."""
+    X = W.gaussian_mixture(150, 3, 3, 0.2, 12)
+    J = W.subsample(150, 20, 13)
+    sig2 = 0.05
+    Lf = LR.nystrom_factor(X, J, "gaussian", sig2, lengthscale=0.3)
+    D = np.linalg.norm(X[:, None] - X[None], axis=-1)
+    K = np.exp(-D ** 2 / (2 * 0.3 ** 2))
+    ref = K[:, J] @ np.linalg.solve(K[np.ix_(J, J)] + sig2 * np.eye(len(J)), K[J][:, J])
+    assert np.abs(Lf @ Lf[J].T - ref).max() <= 1e-12
+    assert np.linalg.eigvalsh(K + sig2 * np.eye(150) - Lf @ Lf.T).min() >= sig2 * (1 - 1e-9)
+
+
+def test_two_level_gradient_matches_central_differences():
+    X, T = _small(n=120, leaf=40, seed=14)
+    sig2 = 5e-2
+    Lf = LR.nystrom_factor(X, W.subsample(120, 16, 15), "matern52", sig2, lengthscale=0.3)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 40, coarse=Lf, lengthscale=0.3)
+    A = LR.leaf_block(X, "matern52", sig2, lengthscale=0.3)
+    op = lambda x: A @ x
+    rng = np.random.default_rng(16)
+    theta = rng.normal(0.0, 0.2, LR.NPARAMS)
+    v = rng.normal(size=(X.shape[0], 2))
+    L0, g = LR.loss_grad(sp, theta, v, op, coarse=Lf)
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in LR.SIZES])
+    coords = []
+    for b in range(len(LR.SIZES)):
+        coords += list(rng.integers(offs[b], offs[b + 1], size=2))
+    eps = 1e-6
+    for k in coords:
+        tp = theta.copy(); tp[k] += eps
+        tm = theta.copy(); tm[k] -= eps
+        fd = (LR.loss_grad(sp, tp, v, op, coarse=Lf)[0] - LR.loss_grad(sp, tm, v, op, coarse=Lf)[0]) / (2 * eps)
+        assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-7 * np.abs(g).max(), (k, fd, g[k])
+    assert L0 > 0.0
