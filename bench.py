@@ -105,86 +105,76 @@ def nsweep_leg(F, torch, steps, err_targets, kernel="matern32", prec="f64"):
     return out
 
 
-def gp_solve(F, torch, n, lengthscale, theta, order, rtol, maxit, train_steps):
+def gp_solve(F, torch, n, theta, order, rank, rtol, maxit, train_steps, fp64_none=False):
     """Gaussian-process solve (K~ + sigma2 I) x = y by CG through the FKT MVM
-    on the d = 4 mixture: no preconditioner, block-Jacobi, and the learned
-    per-leaf spectral filter after train_steps Adam steps (batch 8), judged by
-    block-Jacobi on 200 CG iterations (reverted to block-Jacobi if worse);
-    then the same three with the MVM in FP32 (mixed precision)."""
+    at the GP workload's settings (d = 4 mixture, Matern-5/2 length scale 0.3,
+    sigma2 = 1e-2). Every solve stops at relative residual rtol under the
+    FP64 operator:
+      * none: plain CG, FP32 MVMs with the residual replaced by the FP64 one
+        (fkt_cg_solve_refined; and plain FP64 CG with fp64_none);
+      * block_jacobi: two-level (Nystrom coarse space of `rank` landmarks,
+        block-Jacobi of the residual leaf blocks), FP64 MVMs and refined;
+      * learned: the same two-level form with the learned per-leaf filter
+        after train_steps Adam steps, judged by block-Jacobi on 200 CG
+        iterations (reverted to block-Jacobi exactly if worse)."""
     spec = W.WORKLOADS["gmm4_n200k_gp"]
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
     y = W.gp_targets(X, spec["lengthscale"], spec["sigma2"], spec["nfeat"], spec["rhs_seed"])
+    ell, sig2, kern = spec["lengthscale"], spec["sigma2"], spec["kernel"]
     t0 = time.perf_counter()
-    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, lengthscale=lengthscale)
+    p64 = F.fkt_plan(X, kern, spec["leaf"], order, theta=theta, lengthscale=ell)
+    p32 = F.fkt_plan(X, kern, spec["leaf"], order, theta=theta, prec="f32", lengthscale=ell)
     plan_s = time.perf_counter() - t0
     b = torch.as_tensor(y, device="cuda")
-    sig2 = spec["sigma2"]
-    out = {"workload": f"gmm{spec['d']}_n{n}_matern52_l{lengthscale}_gp", "n": n, "d": spec["d"],
-           "lengthscale": lengthscale, "theta": theta, "p": order, "sigma2": sig2, "rtol": rtol, "maxit": maxit,
-           "plan_seconds": plan_s}
+    out = {"workload": f"gmm{spec['d']}_n{n}_matern52_l{ell}_gp", "n": n, "d": spec["d"], "lengthscale": ell,
+           "theta": theta, "p": order, "leaf": spec["leaf"], "sigma2": sig2, "rtol": rtol, "maxit": maxit,
+           "coarse_rank": rank, "plan_seconds_f64_and_f32": plan_s}
 
-    def solve(name, pc):
-        # FP32 plans: FP32 MVMs with FP64 b and solution (fkt_cg_solve64)
+    def timed(name, fn):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            x, it, rr = F.fkt_cg_solve64(plan, sig2, b, rtol=rtol, maxit=maxit, precond=pc)
+            res = fn()
             ok = True
         except F.FktError as e:
             if e.status != 5:
                 raise
-            x, it, rr, ok = e.x, e.iters, e.relres, False
+            res = (None, e.iters, getattr(e, "outer", None), e.relres) if hasattr(e, "outer") else (None, e.iters, e.relres)
+            ok = False
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
-        out[name] = {"iterations": it, "relres": rr, "converged": ok, "seconds": sec}
-        print(f"bench: gp solve n={n} l={lengthscale} precond={name}: {it} iterations, {sec:.2f} s, relres {rr:.2e}",
-              file=sys.stderr, flush=True)
+        if len(res) == 4:
+            rec = {"iterations_f32": res[1], "fp64_replacements": res[2], "relres_fp64": res[3]}
+        else:
+            rec = {"iterations": res[1], "relres_fp64": res[2]}
+        rec.update({"converged": ok, "seconds": sec})
+        out[name] = rec
+        print(f"bench: gp {name}: {rec}", file=sys.stderr, flush=True)
 
-    solve("none", "none")
-    solve("block_jacobi", "block_jacobi")
+    refined = lambda pc: (lambda: F.fkt_cg_solve_refined(p64, p32, sig2, b, rtol=rtol, maxit=maxit, precond=pc))
+    plain = lambda pc: (lambda: F.fkt_cg_solve(p64, sig2, b, rtol=rtol, maxit=maxit, precond=pc))
+    timed("none_refined", refined("none"))
+    if fp64_none:
+        timed("none", plain("none"))
+    # two-level preconditioning: the same landmarks on both plans
+    lm = W.subsample(n, rank, 4242)
+    t0 = time.perf_counter()
+    F.fkt_precond_coarse(p64, sig2, lm)
+    F.fkt_precond_coarse(p32, sig2, lm)
+    out["coarse_setup_seconds_both_plans"] = time.perf_counter() - t0
+    timed("block_jacobi", plain("block_jacobi"))
+    timed("block_jacobi_refined", refined("block_jacobi"))
+    t0 = time.perf_counter()
+    l0, l1, accepted = F.fkt_learn_train(p64, sig2, steps=train_steps, batch=4, lr=3e-3, seed=1, judge_iters=200)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    F.fkt_learn_params(plan, sig2)  # leaf spectra (host eigendecompositions)
-    spectra_s = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    l0, l1, accepted = F.fkt_learn_train(plan, sig2, steps=train_steps, batch=8, lr=3e-3, seed=1, judge_iters=200)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    solve("learned", "learned")
-    out["learned"]["fallback_to_block_jacobi_at"] = plan.info()["cg_fallback_iter"]
-    out["learned"].update({"spectra_seconds": spectra_s, "train_seconds": train_s, "train_steps": train_steps,
-                           "train_loss_first": l0, "train_loss_last": l1, "kept_after_block_jacobi_judge": accepted})
-    params = F.fkt_learn_params(plan, sig2)
-    plan64 = plan
-
-    # mixed precision: the same solves with the MVM in FP32 (CG vectors,
-    # scalars and preconditioners stay FP64; the learned weights carry over)
-    t0 = time.perf_counter()
-    plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, prec="f32", lengthscale=lengthscale)
-    out["f32_plan_seconds"] = time.perf_counter() - t0
-    F.fkt_learn_params(plan, sig2, params)
-    for name in ("none", "block_jacobi", "learned"):
-        solve("f32_mvm_" + name, name)
-    # FP32 CG with the residual replaced by the FP64 one: rtol under the
-    # FP64 operator
-    for name in ("none", "block_jacobi", "learned"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        try:
-            x, it, outer, rr = F.fkt_cg_solve_refined(plan64, plan, sig2, b, rtol=rtol, maxit=maxit, precond=name)
-            ok = True
-        except F.FktError as e:
-            if e.status != 5:
-                raise
-            it, outer, rr, ok = e.iters, e.outer, e.relres, False
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t0
-        out["refined_" + name] = {"iterations_f32": it, "fp64_replacements": outer, "relres": rr, "converged": ok,
-                                  "seconds": sec}
-        print(f"bench: gp solve n={n} refined precond={name}: {it} FP32 iterations, {outer} FP64 replacements, "
-              f"{sec:.2f} s, relres {rr:.2e}", file=sys.stderr, flush=True)
-    plan.close()
-    plan64.close()
+    out["learned_training"] = {"steps": train_steps, "seconds": time.perf_counter() - t0, "loss_first": l0,
+                               "loss_last": l1, "kept_after_block_jacobi_judge": accepted}
+    timed("learned", plain("learned"))
+    out["learned"]["fallback_to_block_jacobi_at"] = p64.info()["cg_fallback_iter"]
+    F.fkt_learn_params(p32, sig2, F.fkt_learn_params(p64, sig2))
+    timed("learned_refined", refined("learned"))
+    p32.close()
+    p64.close()
     return out
 
 
@@ -400,10 +390,13 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
     ap.add_argument("--serial", action="store_true",
                     help="run near and far fields one after the other on one stream (default: concurrently)")
-    ap.add_argument("--gp-n", type=int, default=50_000,
-                    help="points of the GP solves (the d = 4 mixture workload at 200k takes minutes); 0 skips them")
-    ap.add_argument("--gp-maxit", type=int, default=3000)
-    ap.add_argument("--gp-train-steps", type=int, default=100)
+    ap.add_argument("--gp-n", type=int, default=200_000, help="points of the GP solves; 0 skips them")
+    ap.add_argument("--gp-theta", type=float, default=0.3)
+    ap.add_argument("--gp-order", type=int, default=8)
+    ap.add_argument("--gp-rank", type=int, default=2048, help="landmarks of the two-level preconditioner")
+    ap.add_argument("--gp-maxit", type=int, default=10000)
+    ap.add_argument("--gp-train-steps", type=int, default=30)
+    ap.add_argument("--gp-fp64-none", action="store_true", help="also plain FP64 CG without a preconditioner")
     ap.add_argument("--batch-theta", type=float, default=0.3)
     ap.add_argument("--batch-leaf", type=int, default=0, help="0: the library's autotuner picks it")
     ap.add_argument("--batch-no-per-instance", action="store_true")
@@ -432,7 +425,8 @@ def main():
         elif a.leg == "nsweep":
             out = nsweep_leg(F, torch, a.steps, a.err_targets, a.kernel, a.prec)
         else:
-            out = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
+            out = gp_solve(F, torch, a.gp_n, a.gp_theta, a.gp_order, a.gp_rank, 1e-6, a.gp_maxit, a.gp_train_steps,
+                           a.gp_fp64_none)
         print(json.dumps(out))
         return
 
@@ -475,8 +469,8 @@ def main():
 
     gp = None
     if a.gp_n > 0 and not a.no_variants:
-        # the workload's length scale 0.3, and 0.1 where per-leaf preconditioning has something to act on
-        gp = [gp_solve(F, torch, a.gp_n, ell, 0.35, 6, 1e-6, a.gp_maxit, a.gp_train_steps) for ell in (0.3, 0.1)]
+        gp = gp_solve(F, torch, a.gp_n, a.gp_theta, a.gp_order, a.gp_rank, 1e-6, a.gp_maxit, a.gp_train_steps,
+                      a.gp_fp64_none)
 
     batch = mrhs = bsolve = None
     if not a.no_variants:

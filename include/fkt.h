@@ -322,8 +322,9 @@ fkt_status fkt_plan_batch(const double *points, const int64_t *offsets, int nins
                           int order, const fkt_options *opt, fkt_plan_t *out);
 
 /*
- * A whole fkt_mvm(p, x, y, nrhs) captured once into a HIP graph (stages in
- * order on one stream; x and y are baked in) and replayed with
+ * A whole fkt_mvm(p, x, y, nrhs) captured once into a HIP graph (the stages
+ * as fkt_mvm enqueues them, the near field on its own branch with
+ * opt.overlap; x and y are baked in) and replayed with
  * fkt_graph_launch on the plan's stream. The plan must outlive the graph;
  * replays of graphs of one plan must not overlap (they share its work
  * buffers). Errors: FKT_EINVAL, FKT_EDEVICE, FKT_ENOMEM.
@@ -391,6 +392,36 @@ fkt_status fkt_learn_loss_grad(fkt_plan_t p, double sigma2, const double *v, int
  * Synchronises the plan's stream. */
 fkt_status fkt_learn_train(fkt_plan_t p, double sigma2, int steps, int batch, double lr, uint64_t seed,
                            double *loss_first, double *loss_last, int judge_iters, int *accepted);
+
+/*
+ * Training of the learned filter by the condition number of the
+ * preconditioned operator (an objective aligned with CG's convergence;
+ * fkt_learn_train's one-step residual objective drives the filter toward
+ * block-Jacobi or past it). Each of `steps` Adam steps (lr, beta1 0.9, beta2
+ * 0.999) runs `lanczos` PCG iterations from zero with the current filter
+ * (one- or two-level, as fkt_cg_solve with precond 2 would) on a fresh
+ * Gaussian right-hand side (SplitMix64 + Box-Muller, keyed by seed and
+ * step); PCG's step lengths are the Lanczos tridiagonal of P A and its
+ * preconditioned residuals the Lanczos vectors, so the extreme Ritz pairs
+ * (lambda, u), u^T P^-1 u = 1, follow at no further operator cost. The
+ * objective is log kappa = log lambda_max - log lambda_min; P^-1 is affine
+ * in the block part D = blockdiag(V_l^T diag(1/h_l) V_l), so its gradient in
+ * the network outputs is (V u_max)_i^2 / h_i - (V u_min)_i^2 / h_i, then back
+ * through the MLP. cond_first / cond_last (host, may be NULL) receive the
+ * Ritz estimate of kappa at the first and the last step (before its
+ * update). judge_iters and accepted as fkt_learn_train. lanczos in
+ * [2, 1000]. Errors: as fkt_learn_train; FKT_EDEVICE on a PCG breakdown.
+ * Synchronises the plan's stream.
+ */
+fkt_status fkt_learn_train_cond(fkt_plan_t p, double sigma2, int steps, int lanczos, double lr, uint64_t seed,
+                                double *cond_first, double *cond_last, int judge_iters, int *accepted);
+
+/* The condition-number objective of fkt_learn_train_cond for one right-hand
+ * side b (device, n FP64, caller's order; not modified): cond (host)
+ * receives the Ritz estimate of kappa, grad (host, fkt_learn_nparams()
+ * floats, may be NULL) the gradient of log kappa. Does not change the
+ * weights. */
+fkt_status fkt_learn_cond_grad(fkt_plan_t p, double sigma2, const double *b, int lanczos, double *cond, float *grad);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,11 @@ inverse of every leaf block (block-Jacobi); the loss has the closed form of
 two single-point leaves and is exactly 0 for one leaf holding every point
 (one-level, and two-level, where P = (L L^T + A - L L^T)^-1 = A^-1); the
 analytic gradient matches central differences of L when A is an exactly
-symmetric matrix, in the one-level and the two-level form.
+symmetric matrix, in the one-level and the two-level form; the gradient of
+the condition-number objective (``cond_grad``) matches central differences
+of log kappa from dense eigenvalues, and its Lanczos estimate
+(``cond_grad_lanczos``, the device's algorithm) matches ``cond_grad`` when
+the Lanczos run is long enough to resolve the extreme eigenpairs.
 """
 from __future__ import annotations
 
@@ -170,6 +174,79 @@ def two_level_matrix(spectra, hs, L) -> np.ndarray:
         D[np.ix_(ix, ix)] = Sl["V"].T @ np.diag(1.0 / h) @ Sl["V"]
     P = np.linalg.inv(L @ L.T + D)
     return 0.5 * (P + P.T)
+
+
+def cond_grad(spectra, theta, A, coarse=None):
+    """(kappa, d log kappa / d theta) of the preconditioned operator P A, by
+    the dense generalized eigenproblem A u = lam P^-1 u (small n): with
+    u^T P^-1 u = 1, d lam / d h_i = lam (V u)_i^2 / h_i^2 because P^-1 =
+    L L^T + D(h) and dD = V^T diag(-dh / h^2) V; so d log kappa / d o_i =
+    (V u_max)_i^2 / h_i - (V u_min)_i^2 / h_i, then back through the MLP."""
+    import scipy.linalg
+    hs, cache = filters(spectra, theta)
+    n = sum(len(Sl["lam"]) for Sl in spectra)
+    D = np.zeros((n, n))
+    for Sl, h in zip(spectra, hs):
+        ix = Sl["idx"]
+        D[np.ix_(ix, ix)] = Sl["V"].T @ np.diag(1.0 / h) @ Sl["V"]
+    Pinv = D if coarse is None else coarse @ coarse.T + D
+    lam, U = scipy.linalg.eigh(A, 0.5 * (Pinv + Pinv.T))
+    umax, umin = U[:, -1], U[:, 0]
+    go = []
+    for Sl, h in zip(spectra, hs):
+        a = Sl["V"] @ umax[Sl["idx"]]
+        b = Sl["V"] @ umin[Sl["idx"]]
+        go.append((a * a - b * b) / h)
+    return float(lam[-1] / lam[0]), mlp_backward(theta, cache, np.concatenate(go))
+
+
+def cond_grad_lanczos(spectra, theta, op, b, T, coarse=None):
+    """The device's estimate of cond_grad, step by step: T PCG iterations
+    from zero on b with the current preconditioner P (dense here), the
+    Lanczos tridiagonal of P A from the step lengths (diagonal 1/alpha_j +
+    beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j), the Ritz
+    vectors of its extreme eigenvalues from the Lanczos vectors (-1)^j z_j /
+    sqrt(r_j . z_j), and the gradient formula of cond_grad with them.
+    op(x) = A x for a vector x."""
+    hs, cache = filters(spectra, theta)
+    n = sum(len(Sl["lam"]) for Sl in spectra)
+    if coarse is None:
+        Pm = np.zeros((n, n))
+        for Sl, h in zip(spectra, hs):
+            Pm[np.ix_(Sl["idx"], Sl["idx"])] = Sl["V"].T @ np.diag(h) @ Sl["V"]
+    else:
+        Pm = two_level_matrix(spectra, hs, coarse)
+    r = np.array(b, dtype=np.float64)
+    z = Pm @ r
+    p = z.copy()
+    rho = r @ z
+    Z, al, be = [z / np.sqrt(rho)], [], []
+    for j in range(T):
+        q = op(p)
+        a = rho / (p @ q)
+        r = r - a * q
+        z = Pm @ r
+        rn = r @ z
+        al.append(a)
+        be.append(rn / rho)
+        if j + 1 < T:
+            Z.append((-1.0) ** (j + 1) * z / np.sqrt(rn))
+        p = z + (rn / rho) * p
+        rho = rn
+    Tm = np.zeros((T, T))
+    for j in range(T):
+        Tm[j, j] = 1.0 / al[j] + (be[j - 1] / al[j - 1] if j else 0.0)
+        if j + 1 < T:
+            Tm[j, j + 1] = Tm[j + 1, j] = np.sqrt(be[j]) / al[j]
+    w, S = np.linalg.eigh(Tm)
+    Z = np.array(Z)
+    umax, umin = S[:, -1] @ Z, S[:, 0] @ Z
+    go = []
+    for Sl, h in zip(spectra, hs):
+        a = Sl["V"] @ umax[Sl["idx"]]
+        c = Sl["V"] @ umin[Sl["idx"]]
+        go.append((a * a - c * c) / h)
+    return float(w[-1] / w[0]), mlp_backward(theta, cache, np.concatenate(go))
 
 
 def loss_grad(spectra, theta, v, op, coarse=None):

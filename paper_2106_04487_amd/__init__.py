@@ -44,6 +44,7 @@ EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_c
             "fkt_precond_coarse",
             "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_lists", "fkt_plan_stage_times",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
+            "fkt_learn_train_cond", "fkt_learn_cond_grad",
             "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
 
 
@@ -121,6 +122,12 @@ _lib.fkt_learn_params.restype = ctypes.c_int
 _lib.fkt_learn_params.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int]
 _lib.fkt_learn_loss_grad.restype = ctypes.c_int
 _lib.fkt_learn_loss_grad.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]
+_lib.fkt_learn_train_cond.restype = ctypes.c_int
+_lib.fkt_learn_train_cond.argtypes = [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
+_lib.fkt_learn_cond_grad.restype = ctypes.c_int
+_lib.fkt_learn_cond_grad.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _P]
 _lib.fkt_learn_train.restype = ctypes.c_int
 _lib.fkt_learn_train.argtypes = [_P, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
@@ -475,6 +482,27 @@ def fkt_learn_train(plan: Plan, sigma2: float, steps: int, batch: int = 8, lr: f
     _check(_lib.fkt_learn_train(plan.handle, float(sigma2), int(steps), int(batch), float(lr), int(seed),
                                 ctypes.byref(l0), ctypes.byref(l1), int(judge_iters), ctypes.byref(acc)))
     return l0.value, l1.value, bool(acc.value)
+
+
+def fkt_learn_train_cond(plan: Plan, sigma2: float, steps: int, lanczos: int = 30, lr: float = 1e-2, seed: int = 1,
+                         judge_iters: int = 0):
+    """Adam steps on the condition number of the preconditioned operator
+    (Lanczos from PCG); returns (kappa_first, kappa_last, accepted)."""
+    c0, c1, acc = ctypes.c_double(0.0), ctypes.c_double(0.0), ctypes.c_int(1)
+    _check(_lib.fkt_learn_train_cond(plan.handle, float(sigma2), int(steps), int(lanczos), float(lr), int(seed),
+                                     ctypes.byref(c0), ctypes.byref(c1), int(judge_iters), ctypes.byref(acc)))
+    return c0.value, c1.value, bool(acc.value)
+
+
+def fkt_learn_cond_grad(plan: Plan, sigma2: float, b, lanczos: int = 30):
+    """(kappa estimate, gradient of log kappa) for the right-hand side b."""
+    import torch
+    b = torch.as_tensor(b, dtype=torch.float64, device="cuda").contiguous()
+    c = ctypes.c_double(0.0)
+    g = np.zeros(fkt_learn_nparams(), dtype=np.float32)
+    _check(_lib.fkt_learn_cond_grad(plan.handle, float(sigma2), b.data_ptr(), int(lanczos), ctypes.byref(c),
+                                    g.ctypes.data))
+    return c.value, g
 
 
 def fkt_destroy(plan: Plan):

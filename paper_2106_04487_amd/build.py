@@ -7,7 +7,9 @@ the package would first load the library being rebuilt)
 from __future__ import annotations
 
 import argparse
+import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -66,16 +68,41 @@ def _objects():
     return [j[j.index("-o") + 1] for j in _jobs()]
 
 
+_INCLUDE = re.compile(r'^\s*#\s*include\s*"([^"]+)"', re.M)
+_COMMENTS = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def _deps(src):
+    """The source and every header it includes with quotes, transitively."""
+    seen, todo = [], [os.path.abspath(src)]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.append(f)
+        for inc in _INCLUDE.findall(open(f).read()):
+            todo.append(os.path.abspath(os.path.join(os.path.dirname(f), inc)))
+    return seen
+
+
+def _fingerprint(cmd):
+    """Hash of the command and of its inputs with comments and blank space
+    removed: an edit that only touches comments leaves objects current."""
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for src in [a for a in cmd if a.endswith((".cpp", ".hip"))]:
+        for f in _deps(src):
+            text = " ".join(_COMMENTS.sub(" ", open(f).read()).split())
+            h.update(f.encode() + b"\0" + text.encode())
+    return h.hexdigest()
+
+
 def _stale(cmd) -> bool:
-    """An object is stale when it is older than its source or any header."""
+    """An object is stale when it is missing or its fingerprint changed."""
     out = cmd[cmd.index("-o") + 1]
-    if not os.path.exists(out):
+    fp = out + ".fp"
+    if not os.path.exists(out) or not os.path.exists(fp):
         return True
-    deps = [a for a in cmd if a.endswith((".cpp", ".hip"))]
-    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    deps += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
-    t = os.path.getmtime(out)
-    return any(os.path.getmtime(d) > t for d in deps)
+    return open(fp).read().strip() != _fingerprint(cmd)
 
 
 def build(jobs: int = 8, verbose: bool = False, incremental: bool = False) -> str:
@@ -86,9 +113,14 @@ def build(jobs: int = 8, verbose: bool = False, incremental: bool = False) -> st
     def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
+        out = cmd[cmd.index("-o") + 1]
+        fp = _fingerprint(cmd) if out.endswith(".o") else None  # inputs as compiled
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
+        if fp:
+            with open(out + ".fp", "w") as f:
+                f.write(fp + "\n")
         return r
 
     todo = [j for j in _jobs() if not incremental or _stale(j)]
@@ -104,7 +136,8 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("-v", action="store_true")
-    ap.add_argument("--incremental", action="store_true", help="recompile only objects older than their inputs")
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only objects whose inputs changed (comments aside)")
     a = ap.parse_args()
     print(build(a.jobs, a.v, a.incremental))
     sys.exit(0)

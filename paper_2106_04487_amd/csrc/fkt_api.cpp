@@ -837,6 +837,8 @@ static fkt_status learn_entry(fkt_plan_t P, double sigma2)
     return ensure_learn(P, sigma2);
 }
 
+static fkt_status judge_filter(fkt_plan_t P, double sigma2, uint64_t seed, int judge_iters, int* accepted);
+
 int64_t fkt_learn_nparams(void) { return fkt::kLearnParams; }
 
 fkt_status fkt_learn_params(fkt_plan_t P, double sigma2, float* params, int set)
@@ -880,11 +882,56 @@ fkt_status fkt_learn_train(fkt_plan_t P, double sigma2, int steps, int batch, do
     if (st != FKT_OK) return st;
     st = fkt::learn_train(P, P->learn, (int)P->opt.prec, sigma2, steps, batch, lr, seed, loss_first, loss_last);
     if (st != FKT_OK) return fail(st, "learned preconditioner training");
+    return judge_filter(P, sigma2, seed, judge_iters, accepted);
+}
+
+fkt_status fkt_learn_cond_grad(fkt_plan_t P, double sigma2, const double* b, int lanczos, double* cond, float* grad)
+{
+    if (!b || !cond) return fail(FKT_EINVAL, "b or cond is NULL");
+    if (lanczos < 2 || lanczos > 1000) return fail(FKT_EINVAL, "lanczos must be in [2, 1000]");
+    DeviceScope ds(P ? P->opt.device : 0);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt_status st = learn_entry(P, sigma2);
+    if (st != FKT_OK) return st;
+    double* r = nullptr;
+    hipError_t e = hipMalloc(&r, sizeof(double) * P->n);
+    if (e != hipSuccess) return hip_fail(e, "condition-number work vector");
+    e = hipMemcpyAsync(r, b, sizeof(double) * P->n, hipMemcpyDeviceToDevice, P->stream);
+    st = e == hipSuccess ? fkt::learn_cond_grad(P, P->learn, (int)P->opt.prec, sigma2, r, lanczos, cond) : FKT_EDEVICE;
+    (void)hipFree(r);
+    if (st != FKT_OK) return fail(st, "condition-number objective (a breakdown or a non-positive Ritz value)");
+    if (grad) {
+        e = fkt::learn_grad(P->learn, grad);
+        if (e != hipSuccess) return hip_fail(e, "learned preconditioner gradient copy");
+    }
+    return FKT_OK;
+}
+
+fkt_status fkt_learn_train_cond(fkt_plan_t P, double sigma2, int steps, int lanczos, double lr, uint64_t seed,
+                                double* cond_first, double* cond_last, int judge_iters, int* accepted)
+{
+    if (steps < 0) return fail(FKT_EINVAL, "steps must be >= 0");
+    if (lanczos < 2 || lanczos > 1000) return fail(FKT_EINVAL, "lanczos must be in [2, 1000]");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return fail(FKT_EINVAL, "lr must be > 0");
+    if (judge_iters < 0) return fail(FKT_EINVAL, "judge_iters must be >= 0");
+    DeviceScope ds(P ? P->opt.device : 0);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    fkt_status st = learn_entry(P, sigma2);
+    if (st != FKT_OK) return st;
+    st = fkt::learn_train_cond(P, P->learn, (int)P->opt.prec, sigma2, steps, lanczos, lr, seed, cond_first, cond_last);
+    if (st != FKT_OK) return fail(st, "learned preconditioner training (condition number)");
+    return judge_filter(P, sigma2, seed, judge_iters, accepted);
+}
+
+// Block-Jacobi judges a trained filter: judge_iters CG iterations on a
+// Gaussian right-hand side with each preconditioner; if the learned filter
+// ends with the larger residual, its last layer is zeroed, which is
+// block-Jacobi exactly.
+static fkt_status judge_filter(fkt_plan_t P, double sigma2, uint64_t seed, int judge_iters, int* accepted)
+{
+    fkt_status st = FKT_OK;
     if (accepted) *accepted = 1;
     if (judge_iters == 0) return FKT_OK;
-    // block-Jacobi judges: judge_iters CG iterations on a Gaussian right-hand
-    // side with each preconditioner; if the learned filter ends with the
-    // larger residual, its last layer is zeroed, which is block-Jacobi exactly
     const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
     void *b = nullptr, *x = nullptr;
     hipError_t e;
@@ -947,8 +994,11 @@ fkt_status fkt_graph_create(fkt_plan_t P, const void* x, void* y, int nrhs, fkt_
         return fail(FKT_ENOMEM, "graph allocation");
     }
     G->plan = P;
-    // the whole MVM, stages in order on one stream (no memset nodes: the
-    // accumulators are cleared by the gather kernel)
+    // the whole MVM as fkt_mvm enqueues it (no memset nodes: the
+    // accumulators are cleared by the gather kernel); with opt.overlap the
+    // near field's branch on the plan's second stream joins the capture
+    // through the fork event and returns through the join event, so the
+    // graph keeps the near/far concurrency of eager launches
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t le = hipSuccess;
@@ -956,7 +1006,8 @@ fkt_status fkt_graph_create(fkt_plan_t P, const void* x, void* y, int nrhs, fkt_
             le = fkt::launch_mvm_mrhs(P->dp, P->wk, P->mr, (const float*)x, (float*)y, nrhs, cap);
         else
             for (int c = 0; c < nrhs && le == hipSuccess; ++c)
-                le = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, cap, false, nullptr);
+                le = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, cap, P->opt.overlap != 0,
+                                            nullptr);
         e = hipStreamEndCapture(cap, &G->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }

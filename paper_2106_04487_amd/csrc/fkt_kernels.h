@@ -831,7 +831,17 @@ template <> struct PMax<3> { static constexpr int value = 8; };
 template <> struct PMax<4> { static constexpr int value = 8; };
 template <> struct PMax<5> { static constexpr int value = 8; };
 
-constexpr int kChunk = 128;  // s2m moment entries accumulated per lane and launch
+// s2m moment entries accumulated per lane and launch: the rank split into
+// equal chunks of at most 48 FP64 or 96 FP32 accumulators (96 or 192 bytes
+// of registers per lane), so a unit keeps several waves per SIMD; every
+// chunk regenerates the harmonics, which costs less than the accumulation.
+template <typename T>
+constexpr int s2m_chunk(int R)
+{
+    const int cap = sizeof(T) == 8 ? 48 : 96;
+    const int nch = (R + cap - 1) / cap;
+    return (R + nch - 1) / nch;
+}
 
 }  // namespace
 

@@ -40,6 +40,12 @@ int learn_coarse_rank(const LearnState* L);
 fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, const double* v, int B, double* loss);
 fkt_status learn_train(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int B, double lr, uint64_t seed,
                        double* loss_first, double* loss_last);
+// Condition-number objective (learn.hip): log kappa(P A) from T PCG / Lanczos
+// iterations on b (device, n; overwritten), gradient into the state's
+// gradient buffer; and `steps` Adam steps of it on fresh Gaussian b.
+fkt_status learn_cond_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, double* b, int T, double* cond);
+fkt_status learn_train_cond(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int T, double lr,
+                            uint64_t seed, double* cond_first, double* cond_last);
 
 }  // namespace fkt
 

@@ -358,6 +358,46 @@ __global__ __launch_bounds__(kT) void k_recip(int64_t n, const double* __restric
     if (i < n) h[i] = 1.0 / lam[i];
 }
 
+// Condition-number objective: go[i] = (a_i^2 - b_i^2) / h_i (FP32), 0 for
+// padding, with a, b the spectral coordinates of the two extreme Ritz vectors.
+__global__ __launch_bounds__(kT) void k_dout_cond(int64_t n, int64_t Sp, const double* __restrict__ h,
+                                                  const double* __restrict__ a, const double* __restrict__ b,
+                                                  float* __restrict__ go)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= Sp) return;
+    go[i] = i < n ? (float)((a[i] * a[i] - b[i] * b[i]) / h[i]) : 0.f;
+}
+
+// u = sum_j c[j] Z[j][:] (Z: T rows of n)
+__global__ __launch_bounds__(kT) void k_combine(int64_t n, int T, const double* __restrict__ c,
+                                                const double* __restrict__ Z, double* __restrict__ u)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int j = 0; j < T; ++j) s = fma(c[j], Z[(int64_t)j * n + i], s);
+    u[i] = s;
+}
+
+// y = a x + y, and the scaled copy z = a x
+__global__ __launch_bounds__(kT) void k_axpy1(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+__global__ __launch_bounds__(kT) void k_scale1(int64_t n, double a, const double* __restrict__ x, double* __restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) z[i] = a * x[i];
+}
+// p = z + beta p
+__global__ __launch_bounds__(kT) void k_xpby1(int64_t n, const double* __restrict__ z, double beta, double* __restrict__ p)
+{
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i < n) p[i] = fma(beta, p[i], z[i]);
+}
+
 // go[i] = h_i sum_b c[i][b] p[i][b] scale[b]  (FP32 out), 0 for padding
 __global__ __launch_bounds__(kT) void k_dout(int64_t n, int64_t Sp, int B, const double* __restrict__ h,
                                              const double* __restrict__ c, const double* __restrict__ p,
@@ -862,6 +902,152 @@ fkt_status learn_loss_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2,
     if (backward(L) != hipSuccess) return FKT_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return FKT_EDEVICE;
     return FKT_OK;
+}
+
+// Condition-number objective. PCG (the current filter, one- or two-level)
+// from x0 = 0 on b runs T iterations; its step lengths define the Lanczos
+// tridiagonal of P A (diagonal 1/alpha_j + beta_{j-1}/alpha_{j-1}, off
+// diagonal sqrt(beta_j)/alpha_j) and its preconditioned residuals the
+// Lanczos vectors (-1)^j z_j / sqrt(r_j . z_j), which are orthonormal in
+// the P^-1 inner product. The extreme Ritz pairs (lambda, u) then give
+// log kappa = log lambda_max - log lambda_min. Since P^-1 = L L^T + D with D
+// = blockdiag(V^T diag(1/h) V) affine in 1/h, d lambda = lambda (V u)_i^2
+// dh_i / h_i^2 at u^T P^-1 u = 1, so d log kappa / do_i = (V u_max)_i^2 / h_i
+// - (V u_min)_i^2 / h_i. Leaves the gradient in L->G; b is overwritten.
+fkt_status learn_cond_grad(fkt_plan_t P, LearnState* L, int prec, double sigma2, double* b, int T, double* cond)
+{
+    const int64_t n = L->n;
+    hipStream_t s = L->s;
+    std::vector<void*> tmp;
+    auto get = [&](size_t bytes, void** out) {
+        hipError_t e = hipMalloc(out, bytes ? bytes : 256);
+        if (e == hipSuccess) tmp.push_back(*out);
+        return e;
+    };
+    struct Free {
+        std::vector<void*>& t;
+        ~Free()
+        {
+            for (void* q : t) (void)hipFree(q);
+        }
+    } fr{tmp};
+    double *z, *p, *q, *Z, *ua, *ub, *ta, *tb, *part, *cd;
+    void *op_in, *op_out;
+    const size_t es = prec == 1 ? sizeof(float) : sizeof(double);
+    if (get(sizeof(double) * n, (void**)&z) || get(sizeof(double) * n, (void**)&p) || get(sizeof(double) * n, (void**)&q) ||
+        get(sizeof(double) * n * T, (void**)&Z) || get(sizeof(double) * n, (void**)&ua) ||
+        get(sizeof(double) * n, (void**)&ub) || get(sizeof(double) * n, (void**)&ta) ||
+        get(sizeof(double) * n, (void**)&tb) || get(sizeof(double) * kDotBlocks, (void**)&part) ||
+        get(sizeof(double) * 2 * T, (void**)&cd) || get(es * n, &op_in) || get(es * n, &op_out))
+        return FKT_ENOMEM;
+    std::vector<double> hp(kDotBlocks);
+    auto dot = [&](const double* a, const double* bb, double* out) -> bool {
+        hipLaunchKernelGGL(k_coldot, dim3(kDotBlocks), dim3(kT), 0, s, n, 1, a, bb, part);
+        if (hipMemcpyAsync(hp.data(), part, sizeof(double) * kDotBlocks, hipMemcpyDeviceToHost, s) != hipSuccess) return false;
+        if (hipStreamSynchronize(s) != hipSuccess) return false;
+        double t = 0.0;
+        for (double v : hp) t += v;
+        *out = t;
+        return true;
+    };
+    auto op = [&](const double* in, double* out) -> fkt_status {  // out = (K~ + sigma2 I) in
+        if (prec == 1) {
+            hipLaunchKernelGGL((k_cvt<float>), dim3(blocks_of(n)), dim3(kT), 0, s, n, in, (float*)op_in);
+            fkt_status st = fkt_mvm(P, op_in, op_out, 1);
+            if (st != FKT_OK) return st;
+            hipLaunchKernelGGL((k_resid<float>), dim3(blocks_of(n)), dim3(kT), 0, s, n, (const float*)op_out, in,
+                               (const double*)nullptr, sigma2, out);
+        } else {
+            fkt_status st = fkt_mvm(P, in, op_out, 1);
+            if (st != FKT_OK) return st;
+            hipLaunchKernelGGL((k_resid<double>), dim3(blocks_of(n)), dim3(kT), 0, s, n, (const double*)op_out, in,
+                               (const double*)nullptr, sigma2, out);
+        }
+        return hipGetLastError() == hipSuccess ? FKT_OK : FKT_EDEVICE;
+    };
+    if (learn_prepare_filter(L) != hipSuccess) return FKT_EDEVICE;
+    // PCG on b (the residual r lives in b)
+    double* r = b;
+    std::vector<double> alpha(T), beta(T);
+    if (learn_apply(L, r, z, 1, 0, s) != hipSuccess) return FKT_EDEVICE;
+    double rho = 0.0;
+    if (!dot(r, z, &rho) || !(rho > 0.0)) return FKT_EDEVICE;
+    hipLaunchKernelGGL(k_scale1, dim3(blocks_of(n)), dim3(kT), 0, s, n, 1.0 / std::sqrt(rho), z, Z);
+    hipLaunchKernelGGL(k_scale1, dim3(blocks_of(n)), dim3(kT), 0, s, n, 1.0, z, p);
+    int Tk = T;
+    for (int j = 0; j < T; ++j) {
+        fkt_status st = op(p, q);
+        if (st != FKT_OK) return st;
+        double pq = 0.0;
+        if (!dot(p, q, &pq) || !(pq > 0.0)) { Tk = j; break; }
+        alpha[j] = rho / pq;
+        hipLaunchKernelGGL(k_axpy1, dim3(blocks_of(n)), dim3(kT), 0, s, n, -alpha[j], q, r);
+        if (learn_apply(L, r, z, 1, 0, s) != hipSuccess) return FKT_EDEVICE;
+        double rn = 0.0;
+        if (!dot(r, z, &rn)) return FKT_EDEVICE;
+        if (!(rn > 0.0)) { Tk = j + 1; beta[j] = 0.0; break; }
+        beta[j] = rn / rho;
+        if (j + 1 < T)
+            hipLaunchKernelGGL(k_scale1, dim3(blocks_of(n)), dim3(kT), 0, s, n, ((j + 1) & 1 ? -1.0 : 1.0) / std::sqrt(rn),
+                               z, Z + (int64_t)(j + 1) * n);
+        hipLaunchKernelGGL(k_xpby1, dim3(blocks_of(n)), dim3(kT), 0, s, n, z, beta[j], p);
+        rho = rn;
+    }
+    if (Tk < 2) return FKT_EDEVICE;
+    // Lanczos tridiagonal and its extreme eigenpairs (host)
+    std::vector<double> Tm((size_t)Tk * Tk, 0.0), w(Tk);
+    for (int j = 0; j < Tk; ++j) {
+        Tm[(size_t)j * Tk + j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+        if (j + 1 < Tk) Tm[(size_t)j * Tk + j + 1] = Tm[(size_t)(j + 1) * Tk + j] = std::sqrt(beta[j]) / alpha[j];
+    }
+    if (!sym_eig(Tk, Tm.data(), w.data()) || !(w[0] > 0.0)) return FKT_EDEVICE;
+    *cond = w[Tk - 1] / w[0];
+    std::vector<double> cc(2 * (size_t)Tk);
+    for (int j = 0; j < Tk; ++j) {
+        cc[j] = Tm[(size_t)(Tk - 1) * Tk + j];  // eigenvector of lambda_max (row Tk-1)
+        cc[Tk + j] = Tm[j];                     // and of lambda_min (row 0)
+    }
+    if (hipMemcpyAsync(cd, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return FKT_EDEVICE;
+    hipLaunchKernelGGL(k_combine, dim3(blocks_of(n)), dim3(kT), 0, s, n, Tk, cd, Z, ua);
+    hipLaunchKernelGGL(k_combine, dim3(blocks_of(n)), dim3(kT), 0, s, n, Tk, cd + Tk, Z, ub);
+    const size_t lds = sizeof(double) * L->maxleaf;
+    hipLaunchKernelGGL(k_spec_proj1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
+                       L->perm, 1, 0, ua, ta);
+    hipLaunchKernelGGL(k_spec_proj1, dim3(L->nleaf), dim3(kT), lds, s, L->leaf_begin, L->leaf_count, L->off, L->Vt,
+                       L->perm, 1, 0, ub, tb);
+    hipLaunchKernelGGL(k_dout_cond, dim3(blocks_of(L->Sp)), dim3(kT), 0, s, n, L->Sp, L->h, ta, tb, L->go);
+    if (backward(L) != hipSuccess) return FKT_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return FKT_EDEVICE;
+    return FKT_OK;
+}
+
+fkt_status learn_train_cond(fkt_plan_t P, LearnState* L, int prec, double sigma2, int steps, int T, double lr,
+                            uint64_t seed, double* cond_first, double* cond_last)
+{
+    double* b = nullptr;
+    if (hipMalloc(&b, sizeof(double) * L->n) != hipSuccess) return FKT_ENOMEM;
+    fkt_status st = FKT_OK;
+    for (int it = 0; it < steps; ++it) {
+        const uint64_t key = seed * 0x2545F4914F6CDD1Dull + (uint64_t)it * 0x9E3779B97F4A7C15ull;
+        hipLaunchKernelGGL(k_randn, dim3(blocks_of(L->n)), dim3(kT), 0, L->s, L->n, key, b);
+        double cond = 0.0;
+        st = learn_cond_grad(P, L, prec, sigma2, b, T, &cond);
+        if (st != FKT_OK) break;
+        if (it == 0 && cond_first) *cond_first = cond;
+        if (cond_last) *cond_last = cond;
+        L->adam_t += 1;
+        const float c1 = 1.f - std::pow(0.9f, (float)L->adam_t), c2 = 1.f - std::pow(0.999f, (float)L->adam_t);
+        hipLaunchKernelGGL(k_adam, dim3(blocks_of(kNP)), dim3(kT), 0, L->s, kNP, L->P, L->G, L->Am, L->Av, (float)lr, c1,
+                           c2);
+        if (hipGetLastError() != hipSuccess) {
+            st = FKT_EDEVICE;
+            break;
+        }
+    }
+    (void)hipStreamSynchronize(L->s);
+    (void)hipFree(b);
+    return st;
 }
 
 hipError_t learn_randn(LearnState* L, void* x, int64_t n, bool f32, uint64_t key)

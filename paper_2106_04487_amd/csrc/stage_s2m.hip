@@ -15,7 +15,8 @@ void launch_s2m_chunks(const DevPlan& a, const T* src, T* mom, T* part, hipStrea
 {
     constexpr int R = cbinom(P + D, D);
     if constexpr (C0 < R) {
-        constexpr int C1 = (C0 + kChunk < R) ? C0 + kChunk : R;
+        constexpr int CH = s2m_chunk<T>(R);
+        constexpr int C1 = (C0 + CH < R) ? C0 + CH : R;
         hipLaunchKernelGGL((k_s2m<D, P, T, C0, C1>), dim3(a.nunits), dim3(kWave), 0, s, a, src, mom, part);
         launch_s2m_chunks<D, P, T, C1>(a, src, mom, part, s);
     }

@@ -318,3 +318,36 @@ def test_two_level_cuts_cg_iterations(F):
     _, it1, _ = F.fkt_cg_solve(plan, sig2, b, rtol=1e-6, maxit=5000, precond="block_jacobi")
     assert abs(it1 - its["one_level"]) <= 0.02 * its["one_level"]
     plan.close()
+
+
+def test_cond_gradient_matches_oracle(F):
+    """fkt_learn_cond_grad (Lanczos from the device's PCG run, two-level
+    filter with random weights) against the oracle's same algorithm on the
+    same right-hand side (oracle/learned.cond_grad_lanczos, itself pinned
+    against the dense eigenproblem). theta is small enough that every pair
+    is near, so the operator is the exact kernel matrix and the oracle's A
+    is dense. 25 Lanczos steps: short enough that both PCG runs, whose
+    rounding differs, stay together."""
+    import torch
+    n, leaf, sig2 = 1500, 100, 1e-2
+    X = _gp_points(n, 83)
+    kw = dict(lengthscale=0.3)
+    plan = F.fkt_plan(X, "matern52", leaf, 4, theta=0.02, **kw)
+    assert plan.info()["far_pairs"] == 0
+    J = W.subsample(n, 48, 84)
+    F.fkt_precond_coarse(plan, sig2, J)
+    params = np.random.default_rng(21).normal(0.0, 0.1, LR.NPARAMS).astype(np.float32)
+    F.fkt_learn_params(plan, sig2, params)
+    b = torch.as_tensor(W.normal_rhs(n, 1, 85)[:, 0], device="cuda")
+    kappa, grad = F.fkt_learn_cond_grad(plan, sig2, b, lanczos=25)
+    T = oracle.Tree(X, leaf)
+    Lf = LR.nystrom_factor(X, J, "matern52", sig2, **kw)
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, leaf, coarse=Lf, **kw)
+    A = LR.leaf_block(X, "matern52", sig2, **kw)
+    kref, gref = LR.cond_grad_lanczos(sp, params.astype(np.float64), lambda v: A @ v, b.cpu().numpy(), 25,
+                                      coarse=Lf)
+    gerr = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
+    print(f"kappa gpu {kappa:.8e} oracle {kref:.8e}; gradient rel err {gerr:.2e}")
+    assert abs(kappa - kref) <= 1e-6 * kref
+    assert gerr <= 1e-4
+    plan.close()

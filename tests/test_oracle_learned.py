@@ -162,3 +162,54 @@ def test_two_level_gradient_matches_central_differences():
         fd = (LR.loss_grad(sp, tp, v, op, coarse=Lf)[0] - LR.loss_grad(sp, tm, v, op, coarse=Lf)[0]) / (2 * eps)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g[k])) + 1e-7 * np.abs(g).max(), (k, fd, g[k])
     assert L0 > 0.0
+
+
+@pytest.mark.parametrize("two_level", [False, True])
+def test_cond_gradient_matches_central_differences(two_level):
+    """d log kappa(P A) / d theta against central differences of log kappa
+    from scipy's dense generalized eigenvalues (one- and two-level P)."""
+    import scipy.linalg
+    X, T = _small(n=120, leaf=40, seed=18)
+    sig2 = 5e-2
+    Lf = LR.nystrom_factor(X, W.subsample(120, 12, 19), "matern52", sig2, lengthscale=0.3) if two_level else None
+    sp = LR.leaf_spectra(T, X, "matern52", sig2, 40, coarse=Lf, lengthscale=0.3)
+    A = LR.leaf_block(X, "matern52", sig2, lengthscale=0.3)
+    rng = np.random.default_rng(20)
+    theta = rng.normal(0.0, 0.2, LR.NPARAMS)
+
+    def logk(th):
+        hs, _ = LR.filters(sp, th)
+        D = np.zeros_like(A)
+        for Sl, h in zip(sp, hs):
+            D[np.ix_(Sl["idx"], Sl["idx"])] = Sl["V"].T @ np.diag(1.0 / h) @ Sl["V"]
+        Pinv = D if Lf is None else Lf @ Lf.T + D
+        lam = scipy.linalg.eigvalsh(A, 0.5 * (Pinv + Pinv.T))
+        return np.log(lam[-1] / lam[0])
+
+    kappa, g = LR.cond_grad(sp, theta, A, coarse=Lf)
+    assert abs(np.log(kappa) - logk(theta)) <= 1e-10
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in LR.SIZES])
+    coords = []
+    for b in range(len(LR.SIZES)):
+        coords += list(rng.integers(offs[b], offs[b + 1], size=2))
+    eps = 1e-6
+    for k in coords:
+        tp = theta.copy(); tp[k] += eps
+        tm = theta.copy(); tm[k] -= eps
+        fd = (logk(tp) - logk(tm)) / (2 * eps)
+        assert abs(fd - g[k]) <= 1e-5 * max(1.0, abs(g[k])) + 1e-6 * np.abs(g).max(), (k, fd, g[k])
+
+
+def test_cond_lanczos_estimate_converges_to_exact():
+    """PCG run as long as the problem (n = 120 steps) resolves the extreme
+    eigenpairs of P A: the Lanczos estimate equals the exact cond_grad."""
+    X, T = _small(n=120, leaf=40, seed=22)
+    sig2 = 0.1
+    sp = LR.leaf_spectra(T, X, "gaussian", sig2, 40, lengthscale=0.4)
+    A = LR.leaf_block(X, "gaussian", sig2, lengthscale=0.4)
+    theta = np.random.default_rng(23).normal(0.0, 0.1, LR.NPARAMS)
+    b = np.random.default_rng(24).normal(size=120)
+    k_ex, g_ex = LR.cond_grad(sp, theta, A)
+    k_la, g_la = LR.cond_grad_lanczos(sp, theta, lambda x: A @ x, b, 119)
+    assert abs(k_la - k_ex) <= 1e-8 * k_ex
+    assert np.linalg.norm(g_la - g_ex) <= 1e-6 * np.linalg.norm(g_ex)
