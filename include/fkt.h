@@ -225,8 +225,8 @@ fkt_status fkt_cg_solve_refined(fkt_plan_t p, fkt_plan_t lo, double sigma2, cons
  * h = exp(o) / lam, the learned filter, for precond 2 (whose features then
  * come from the residual spectra; fkt_learn_* train it through P). precond
  * 0 is unaffected. Afterwards every fkt_cg_solve / fkt_cg_solve64 /
- * fkt_learn_* call on this plan with this sigma2 uses the two-level form; a
- * call with another sigma2 drops it (one-level again).
+ * fkt_cg_solve_noalloc / fkt_learn_* call on this plan with this sigma2 uses
+ * the two-level form; a call with another sigma2 drops it (one-level again).
  *   landmarks  host, k distinct indices into the caller's point order (the
  *              caller draws them; uniform without replacement is the
  *              intended use).
@@ -242,6 +242,30 @@ fkt_status fkt_cg_solve_refined(fkt_plan_t p, fkt_plan_t lo, double sigma2, cons
  * (leaves over 2048 points), FKT_ENOMEM, FKT_EDEVICE.
  */
 fkt_status fkt_precond_coarse(fkt_plan_t p, double sigma2, const int64_t *landmarks, int k);
+
+/*
+ * fkt_cg_solve_noalloc -- fkt_cg_solve for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same solve, arguments, results and errors, with
+ * the CG work vectors (about 8 n nrhs doubles plus reduction partials) in a
+ * fixed scratch array of 64 MiB that the library holds on each GPU it runs
+ * on until the process ends. It calls no hipMalloc, hipFree or other
+ * allocating routine.
+ *   Limits: n * nrhs up to about 1.04e6 on an FP64 plan (0.93e6 with
+ *   precond 2) and 1.19e6 on an FP32 plan (1.04e6 with precond 2); larger
+ *   problems return FKT_EINVAL naming the bytes needed.
+ *   precond 1 needs the block-Jacobi factors of this sigma2, and precond 2
+ *   also the learned filter's state for it, built beforehand by
+ *   fkt_cg_solve (or fkt_learn_params) on this plan, or else the two-level
+ *   state of fkt_precond_coarse for this sigma2; otherwise FKT_EINVAL.
+ *   Every call on one GPU shares that GPU's scratch array (which keeps the
+ *   last call's contents; the solve initialises every entry it reads), so
+ *   calls that overlap in time on one GPU -- from several host threads or on
+ *   streams that are not ordered -- race and must be serialised by the
+ *   caller.
+ */
+fkt_status fkt_cg_solve_noalloc(fkt_plan_t p, double sigma2, const void *b, void *x, int nrhs, double rtol, int maxit,
+                                int precond, int *iters, double *relres);
 
 /* Release the plan and its device memory (NULL is a no-op). Waits for the
  * plan's stream first. */

@@ -41,7 +41,7 @@ STATUS = {0: "FKT_OK", 1: "FKT_EINVAL", 2: "FKT_ENOMEM", 3: "FKT_EDEVICE", 4: "F
 EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_cg_solve64", "fkt_cg_solve_refined",
             "fkt_destroy",
             "fkt_last_error",
-            "fkt_precond_coarse",
+            "fkt_cg_solve_noalloc", "fkt_precond_coarse",
             "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_lists", "fkt_plan_stage_times",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
             "fkt_learn_train_cond", "fkt_learn_cond_grad",
@@ -86,6 +86,8 @@ _lib.fkt_cg_solve.argtypes = [_P, ctypes.c_double, _P, _P, ctypes.c_int, ctypes.
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
 _lib.fkt_precond_coarse.restype = ctypes.c_int
 _lib.fkt_precond_coarse.argtypes = [_P, ctypes.c_double, _P, ctypes.c_int]
+_lib.fkt_cg_solve_noalloc.restype = ctypes.c_int
+_lib.fkt_cg_solve_noalloc.argtypes = _lib.fkt_cg_solve.argtypes
 _lib.fkt_cg_solve64.restype = ctypes.c_int
 _lib.fkt_cg_solve64.argtypes = _lib.fkt_cg_solve.argtypes
 _lib.fkt_cg_solve_refined.restype = ctypes.c_int
@@ -408,6 +410,28 @@ def fkt_precond_coarse(plan: Plan, sigma2: float, landmarks):
     (caller's order; an empty list returns to one-level)."""
     lm = np.ascontiguousarray(np.asarray(landmarks, dtype=np.int64).ravel())
     _check(_lib.fkt_precond_coarse(plan.handle, float(sigma2), lm.ctypes.data if lm.size else None, int(lm.size)))
+
+
+def fkt_cg_solve_noalloc(plan: Plan, sigma2: float, b, x, *, rtol: float = 1e-6, maxit: int = 1000, precond=0):
+    """fkt_cg_solve without any device allocation, in the library or here:
+    x (a device tensor of b's shape and dtype, the initial guess) is
+    overwritten with the solution. Returns (iters, relres); raises FktError
+    (FKT_ENOTCONV carries .iters and .relres)."""
+    precond = PRECONDS[precond] if isinstance(precond, str) else int(precond)
+    b = _device_matrix(plan, b, "b")
+    x = _device_matrix(plan, x, "x")
+    if b.shape != x.shape:
+        raise ValueError("b and x must have the same shape")
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = _lib.fkt_cg_solve_noalloc(plan.handle, float(sigma2), b.data_ptr(), x.data_ptr(), nrhs, float(rtol),
+                                   int(maxit), int(precond), ctypes.byref(it), ctypes.byref(rr))
+    if st == 5:
+        err = FktError(st, _lib.fkt_last_error().decode())
+        err.iters, err.relres = it.value, rr.value
+        raise err
+    _check(st)
+    return it.value, rr.value
 
 
 def fkt_cg_solve64(plan: Plan, sigma2: float, b, x0=None, *, rtol: float = 1e-6, maxit: int = 1000,

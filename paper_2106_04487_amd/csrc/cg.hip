@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -130,8 +131,12 @@ unsigned grid_of(int64_t m) { return (unsigned)((m + kThreads - 1) / kThreads); 
 
 int cg_dot_blocks(int nseg) { return std::max(8, kDotBlocks / nseg); }
 
+// CG work buffers: allocated per solve with hipMalloc, or carved (256-byte
+// aligned) out of a caller-given region without allocating anything.
 struct Buf {
     std::vector<void*> ptrs;
+    char* region = nullptr;  // carve from here when set
+    size_t used = 0, cap = 0;
     ~Buf()
     {
         for (void* p : ptrs) (void)hipFree(p);
@@ -139,19 +144,79 @@ struct Buf {
     template <class T>
     hipError_t get(size_t count, T** out)
     {
+        const size_t bytes = sizeof(T) * (count ? count : 1);
+        if (region) {
+            const size_t need = (bytes + 255) / 256 * 256;
+            if (used + need > cap) {
+                *out = nullptr;
+                return hipErrorOutOfMemory;
+            }
+            *out = (T*)(region + used);
+            used += need;
+            return hipSuccess;
+        }
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, sizeof(T) * (count ? count : 1));
+        hipError_t e = hipMalloc(&p, bytes);
         if (e == hipSuccess) ptrs.push_back(p);
         *out = (T*)p;
         return e;
     }
 };
 
+// Bytes of work buffers a solve needs (the carve of Buf::get, in its order):
+// b, x, r, z, p, q (m doubles each), dot partials, coefficients, operator
+// input and output (m plan elements each), and the learned filter's best
+// iterate.
+size_t cg_work_bytes(int64_t m, int nsys, int64_t npart, size_t es, bool best)
+{
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t t = 6 * up(sizeof(double) * (size_t)m) + up(sizeof(double) * (size_t)npart) +
+               up(sizeof(double) * 3 * (size_t)nsys) + 2 * up(es * (size_t)m);
+    if (best) t += up(sizeof(double) * (size_t)m);
+    return t;
+}
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+// ---------------------------------------------------- allocation-free solves
+//
+// Work buffers of fkt_cg_solve_noalloc: one file-scope device array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel or a copy (there it
+// names a host-side stand-in): the address of each device's copy is looked
+// up once, with that device current, and kept per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace fkt {
 fkt_status cg_set_error(fkt_status st, const std::string& msg);
 
+// Device address of `device`'s scratch array (that device must be current).
+hipError_t cg_scratch(int device, void** ptr, size_t* bytes)
+{
+    *ptr = nullptr;
+    *bytes = kScratchBytes;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* q = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = q;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+size_t cg_work_bytes_for(int64_t n, int nrhs, int nseg, size_t es, bool best)
+{
+    const int nsys = nseg * nrhs;
+    return cg_work_bytes(n * nrhs, nsys, (int64_t)nseg * cg_dot_blocks(nseg) * nrhs, es, best);
+}
 }  // namespace fkt
 
 namespace fkt {
@@ -169,7 +234,8 @@ constexpr int kFallbackStall = 250;
 template <typename T, typename TI>
 static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, const TI* b_in, TI* x_io, int nrhs, double rtol,
                            int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
-                           fkt_plan_t P64 = nullptr, const CgPlanView* v64 = nullptr, int* replaced = nullptr)
+                           fkt_plan_t P64 = nullptr, const CgPlanView* v64 = nullptr, int* replaced = nullptr,
+                           void* region = nullptr, size_t region_bytes = 0)
 {
     const int64_t n = v.n, m = n * nrhs;
     // systems: (instance, column) pairs, each with its own CG scalars; a
@@ -178,6 +244,8 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
     const int bps = cg_dot_blocks(nseg);  // dot blocks per instance
     hipStream_t s = v.stream;
     Buf buf;
+    buf.region = (char*)region;
+    buf.cap = region_bytes;
     double *b, *x, *r, *z, *p, *q, *part, *coef, *xbest = nullptr, *q64 = nullptr;
     T *op_in, *op_out;
     hipError_t e;
@@ -352,7 +420,8 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
 
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
-                         bool io64, fkt_plan_t P64, const CgPlanView* v64, int* replaced)
+                         bool io64, fkt_plan_t P64, const CgPlanView* v64, int* replaced, void* region,
+                         size_t region_bytes)
 {
     if (precond < 0 || precond > 2 || (precond == 2 && !v.learn))
         return cg_set_error(FKT_EUNSUPPORTED, "unknown preconditioner");
@@ -374,9 +443,9 @@ fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const
                                        relres, fallback_at, P64, v64, replaced);
     if (v.prec == 1)
         return cg_typed<float, float>(P, v, sigma2, (const float*)b, (float*)x, nrhs, rtol, maxit, precond, iters,
-                                      relres, fallback_at);
+                                      relres, fallback_at, nullptr, nullptr, nullptr, region, region_bytes);
     return cg_typed<double, double>(P, v, sigma2, (const double*)b, (double*)x, nrhs, rtol, maxit, precond, iters,
-                                    relres, fallback_at);
+                                    relres, fallback_at, nullptr, nullptr, nullptr, region, region_bytes);
 }
 
 }  // namespace fkt

@@ -72,7 +72,9 @@ fkt_status cg_set_error(fkt_status st, const std::string& msg) { return fail(st,
 fkt_status cg_solve_impl(fkt_plan_t P, const CgPlanView& v, double sigma2, const void* b, void* x, int nrhs,
                          double rtol, int maxit, int precond, int* iters, double* relres, int64_t* fallback_at,
                          bool io64, fkt_plan_t P64 = nullptr, const CgPlanView* v64 = nullptr,
-                         int* replaced = nullptr);
+                         int* replaced = nullptr, void* region = nullptr, size_t region_bytes = 0);
+hipError_t cg_scratch(int device, void** ptr, size_t* bytes);
+size_t cg_work_bytes_for(int64_t n, int nrhs, int nseg, size_t es, bool best);
 }  // namespace fkt
 
 struct fkt_plan_s {
@@ -802,6 +804,46 @@ fkt_status fkt_cg_solve64(fkt_plan_t P, double sigma2, const double* b, double* 
 {
     return cg_entry(P, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, P ? &P->st.cg_fallback_iter : nullptr,
                     true);
+}
+
+fkt_status fkt_cg_solve_noalloc(fkt_plan_t P, double sigma2, const void* b, void* x, int nrhs, double rtol, int maxit,
+                                int precond, int* iters, double* relres)
+{
+    if (!P) return fail(FKT_EINVAL, "plan is NULL");
+    if (!P->on_device) return fail(FKT_EDEVICE, "host-only plan (device = -1) cannot run fkt_cg_solve_noalloc");
+    if (!b || !x) return fail(FKT_EINVAL, "b or x is NULL");
+    if (nrhs < 1 || nrhs > 64) return fail(FKT_EINVAL, "nrhs must be in [1, 64]");
+    if (!(sigma2 >= 0.0) || !std::isfinite(sigma2)) return fail(FKT_EINVAL, "sigma2 must be >= 0");
+    if (!(rtol > 0.0)) return fail(FKT_EINVAL, "rtol must be > 0");
+    if (maxit < 1) return fail(FKT_EINVAL, "maxit must be >= 1");
+    if (precond < 0 || precond > 2) return fail(FKT_EUNSUPPORTED, "unknown preconditioner");
+    // preconditioner state is built (and allocated) by fkt_cg_solve or
+    // fkt_precond_coarse, never here
+    const bool two_level = P->coarse_k > 0 && P->coarse_sigma2 == sigma2 && P->learn;
+    if (precond >= 1 && !two_level && P->bj_sigma2 != sigma2)
+        return fail(FKT_EINVAL, "block-Jacobi factors for this sigma2 are not built: call fkt_cg_solve with this "
+                                "sigma2 and precond 1 or 2 first");
+    if (precond == 2 && (!P->learn || P->learn_sigma2 != sigma2))
+        return fail(FKT_EINVAL, "the learned preconditioner has no state for this sigma2: call fkt_learn_params or "
+                                "fkt_cg_solve with precond 2 and this sigma2 first");
+    const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
+    const size_t need = fkt::cg_work_bytes_for(P->n, nrhs, P->cg_nseg, es, precond == 2);
+    DeviceScope ds(P->opt.device);
+    if (!ds.ok) return fail(FKT_EDEVICE, "cannot select HIP device");
+    void* region = nullptr;
+    size_t cap = 0;
+    const hipError_t e = fkt::cg_scratch(P->opt.device, &region, &cap);
+    if (e != hipSuccess) return hip_fail(e, "scratch array address");
+    if (need > cap)
+        return fail(FKT_EINVAL, "fkt_cg_solve_noalloc needs " + std::to_string(need) + " bytes of work space for n = " +
+                                    std::to_string(P->n) + ", nrhs = " + std::to_string(nrhs) + "; its scratch array holds " +
+                                    std::to_string(cap));
+    fkt::CgPlanView v{P->n,         (int)P->opt.prec, P->opt.device, P->stream,    P->dp.perm,   P->bj_nleaf,
+                      P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
+                      P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
+    v.coarse = two_level ? 1 : 0;
+    return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, &P->st.cg_fallback_iter,
+                              false, nullptr, nullptr, nullptr, region, cap);
 }
 
 fkt_status fkt_cg_solve_refined(fkt_plan_t P, fkt_plan_t Q, double sigma2, const double* b, double* x, int nrhs,
