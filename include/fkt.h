@@ -91,10 +91,20 @@ typedef struct {
                            high and low bf16 parts and three products per
                            tile (about 16 mantissa bits), for either value.
                            0 (default): every column on its own, FP32.      */
+    int far_mode;       /* order of the far-field evaluation (multipole to
+                           target): 1 block-major (one wave per 64-target
+                           block, its pairs packed into jobs whose node
+                           moments are staged in LDS, one sum per target);
+                           2 node-major (one wave per far node and up to 64
+                           of its targets, moments read as wave-uniform
+                           scalar operands, one atomic add per pair; plan
+                           memory 4 bytes per far pair); 0 (default) picks
+                           node-major except for FP32 plans of expansion
+                           rank above 200.                                  */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
- * overlap 1, mrhs 0. */
+ * overlap 1, mrhs 0, far_mode 0. */
 void fkt_default_options(fkt_options *opt);
 
 /*

@@ -62,7 +62,7 @@ class _Kernel(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int)]
+                ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int), ("far_mode", ctypes.c_int)]
 
 
 _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
@@ -219,7 +219,10 @@ class Plan:
             pass
 
 
-def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs):
+FAR_MODES = {"auto": 0, "block": 1, "node": 2}
+
+
+def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode="auto"):
     opt = _Options()
     _lib.fkt_default_options(ctypes.byref(opt))
     opt.theta = float(theta)
@@ -230,6 +233,7 @@ def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs):
     opt.profile = int(bool(profile))
     opt.overlap = int(bool(overlap))
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
+    opt.far_mode = FAR_MODES[far_mode]
     return opt
 
 
@@ -256,11 +260,11 @@ def _batch_points(points):
 def fkt_plan_batch(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
                    variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
                    device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-                   mrhs: str | None = None) -> Plan:
+                   mrhs: str | None = None, far_mode: str = "auto") -> Plan:
     """One plan over independent point sets: points is a list of (n_i, d)
     arrays or (X, offsets). fkt_mvm then takes the concatenated rows."""
     X, off = _batch_points(points)
-    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs)
+    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode)
     h = _P()
     _check(_lib.fkt_plan_batch(X.ctypes.data, off.ctypes.data, len(off) - 1, X.shape[1],
                                _kernel(kernel, lengthscale, alpha, variance), int(leaf_size), int(order),
@@ -320,12 +324,14 @@ def fkt_autotune_leaf(points, kernel: str, order: int, candidates, *, nrhs: int 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
              variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
              device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-             mrhs: str | None = None) -> Plan:
+             mrhs: str | None = None, far_mode: str = "auto") -> Plan:
     """Build a plan. points: (n, d) array-like (host or device; copied to host
     FP64 for the tree build). device=None builds a host-only plan. overlap
     runs the near field on a second stream beside the far field. mrhs ("f32"
     or "bf16", FP32 plans) runs the near field of groups of 32 right-hand
-    sides on the matrix cores."""
+    sides on the matrix cores. far_mode: "block" (target-block jobs, moments
+    in LDS), "node" (one far node per wave, scalar moments, atomics) or
+    "auto"."""
     if hasattr(points, "detach"):
         points = points.detach().to("cpu").double().numpy()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -348,6 +354,7 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     opt.profile = int(bool(profile))
     opt.overlap = int(bool(overlap))
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
+    opt.far_mode = FAR_MODES[far_mode]
     h = _P()
     _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
     return Plan(h, n, d, prec, device, sh)

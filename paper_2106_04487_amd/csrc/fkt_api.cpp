@@ -172,6 +172,7 @@ void fkt_default_options(fkt_options* opt)
     opt->profile = 0;
     opt->overlap = 1;
     opt->mrhs = 0;
+    opt->far_mode = 0;
 }
 
 const char* fkt_last_error(void) { return g_err.c_str(); }
@@ -242,6 +243,30 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.job_noff, a.job_noff);
     FKT_UP(L.job_nodes, a.job_nodes);
     FKT_UP(L.job_pairs, a.job_pairs);
+    {
+        // node-major far jobs (far_mode 2; far_mode 0 except FP32 plans of
+        // rank above 200, where the block-major kernel was measured faster)
+        const bool node_major = P->opt.far_mode == 2 ||
+                                (P->opt.far_mode == 0 && !(P->opt.prec == FKT_F32 && P->tab.rank > 200));
+        a.nnjobs = 0;
+        a.nj_slot = nullptr;
+        a.nj_tgt = nullptr;
+        if (node_major && !L.slot_node.empty()) {
+            std::vector<int32_t> js, jt;
+            fkt::pack_node_jobs(L, js, jt);
+            if ((int64_t)js.size() > 0x7fffffffLL / 4)
+                return fail(FKT_EUNSUPPORTED, "too many far pairs for node-major jobs; use far_mode 1");
+            for (size_t j = 0; j < js.size(); ++j) {
+                if (js[j] < 0 || js[j] >= (int32_t)L.slot_node.size() || jt[j * 64] < 0)
+                    return fail(FKT_EINVAL, "internal error: node-major job " + std::to_string(j));
+                for (int q = 0; q < 64; ++q)
+                    if (jt[j * 64 + q] >= (int32_t)P->n) return fail(FKT_EINVAL, "internal error: node-major target");
+            }
+            a.nnjobs = (int)js.size();
+            FKT_UP(js, a.nj_slot);
+            FKT_UP(jt, a.nj_tgt);
+        }
+    }
     FKT_UP(L.slot_ctr, a.slot_ctr);
     FKT_UP(L.slot_scale, a.slot_scale);
     FKT_UP(L.unit_slot, a.unit_slot);
@@ -370,6 +395,7 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
     if (opt.prec != FKT_F64 && opt.prec != FKT_F32) return fail(FKT_EINVAL, "unknown precision");
     if (opt.mrhs < 0 || opt.mrhs > 2) return fail(FKT_EINVAL, "mrhs must be 0, 1 or 2");
     if (opt.mrhs != 0 && opt.prec != FKT_F32) return fail(FKT_EUNSUPPORTED, "mrhs needs an FP32 plan");
+    if (opt.far_mode < 0 || opt.far_mode > 2) return fail(FKT_EINVAL, "far_mode must be 0, 1 or 2");
     if (opt.max_depth < 1 || opt.max_depth > 60) return fail(FKT_EINVAL, "max_depth must be in [1, 60]");
     if (opt.device < -1) return fail(FKT_EINVAL, "device must be >= -1");
     fkt_status s = check_kernel(k);

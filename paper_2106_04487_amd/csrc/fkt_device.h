@@ -28,6 +28,9 @@ struct DevPlan {
     const int* job_noff;          // [njobs + 1] into job_nodes
     const int* job_nodes;         // far-node slots of each job
     const uint16_t* job_pairs;    // [njobs][64] target lane | job node index << 6
+    int nnjobs;                   // node-major far field (0: block-major jobs above)
+    const int* nj_slot;           // [nnjobs] far-node slot of each job
+    const int* nj_tgt;            // [nnjobs][64] target tree positions (-1: empty lane)
     const double* slot_ctr;       // [nslots][d] expansion centres
     const double* slot_scale;     // [nslots] node radius (1 when zero)
     const int* unit_slot;         // s2m units: node slot

@@ -98,6 +98,9 @@ void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 // pack L's far lists (far_off / far_slot / far_mask) into jobs
 void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J);
+// node-major far jobs: for every far-node slot, its far targets (tree
+// positions, ascending) in jobs of 64 lanes (-1 pads a slot's last job)
+void pack_node_jobs(const Lists& L, std::vector<int32_t>& job_slot, std::vector<int32_t>& job_tgt);
 
 void build_tables(int d, int p, Tables& tab);
 // Bounds of every index the kernels derive from the lists (false + err).

@@ -483,6 +483,94 @@ __global__ __launch_bounds__(256) void k_s2m_reduce(int nred, int R, const int* 
 // node's moments, S_kj = sum_h Y_kh(r^) M_b[kh, j], then the radial
 // functions (FP64): z += sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj.
 //
+// Far-field value of one (target, far node) pair: the plain harmonics of
+// the unit vector towards the target contracted with the node's moments M,
+// S_kj = sum_h Y_kh(r^) M[kh, j], then the radial functions (FP64):
+// sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj. r = target - centre, scale = s.
+//
+// With UNIFORM_M the moments are the same for the whole wave (node-major
+// jobs): each harmonic's few moments are then loaded through a pointer the
+// optimiser cannot see through, so the scalar loads are issued where they
+// are used instead of all at once (which spills the scalar registers).
+template <int D, int P, int KIND, typename T, bool UNIFORM_M = false>
+__device__ __forceinline__ double far_pair(const DevPlan& a, const double (&r)[D], double scale, const T* M)
+{
+    constexpr int R = cbinom(P + D, D);
+    constexpr int NF = f_off(P, P + 1);
+    (void)R;
+    double r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) r2 = fma(r[i], r[i], r2);
+    const double ir = rsqrt_pos(r2);  // r2 > 0: a far target is never at the centre
+    const double rr = r2 * ir;
+
+    // angular part: S_kj over harmonics of r^ (|r^| = 1 at the top level)
+    T x[D], rho2[D + 1];
+    rho2[0] = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        x[i] = T(r[i] * ir);
+        rho2[i + 1] = rho2[i] + x[i] * x[i];
+    }
+    rho2[D] = T(1);
+    T Skj[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) Skj[i] = T(0);
+    int off = 0;
+    auto emit = [&](auto kc, T yv) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int nj = nj_of(P, k);
+        // constant address space: uniform loads from it go through the
+        // scalar cache (the moments are written by an earlier launch)
+        using CT = const __attribute__((address_space(4))) T;
+        CT* Mc = (CT*)(M + off);
+        if constexpr (UNIFORM_M) asm volatile("" : "+s"(Mc));
+        auto dot = [&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            if constexpr (UNIFORM_M)
+                Skj[f_off(P, k) + jj] += yv * Mc[jj];
+            else
+                Skj[f_off(P, k) + jj] += yv * M[off + jj];
+        };
+        static_for<0, nj>(dot);
+        off += nj;
+    };
+    harmonics<D, P, false, T>(x, rho2, (const T*)nullptr, emit);
+
+    // radial part (FP64): F_kj(r) r^j = [j=0] K + sum_m K^(m) r^m Tbar_kjm
+    double Dm[P + 1];
+    radial_derivs<KIND, P>(a, rr, Dm);
+    double um[P + 1];
+    um[0] = Dm[0];
+    double rp = 1.0;
+#pragma unroll
+    for (int m = 1; m <= P; ++m) { rp *= rr; um[m] = Dm[m] * rp; }
+    const double v = scale * ir;  // s / |r| < theta
+    double vp[P + 1];
+    vp[0] = 1.0;
+#pragma unroll
+    for (int jp = 1; jp <= P; ++jp) vp[jp] = vp[jp - 1] * v;
+    double acc = 0.0;
+    auto radial_k = [&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        auto radial_j = [&](auto jc) {
+            constexpr int jj = decltype(jc)::value;
+            constexpr int jv = k + 2 * jj;
+            double f = (jv == 0) ? um[0] : 0.0;
+            auto term = [&](auto mc) {
+                constexpr int m = decltype(mc)::value + 1;
+                constexpr double c = cx_tbar(D, k, jv, m);
+                f = fma(um[m], c, f);
+            };
+            static_for<0, jv>(term);
+            acc = fma(vp[jv] * f, (double)Skj[f_off(P, k) + jj], acc);
+        };
+        static_for<0, nj_of(P, k)>(radial_j);
+    };
+    static_for<0, P + 1>(radial_k);
+    return acc;
+}
+
 // One wave per 64-target block. The block's (target, far node) pairs come
 // packed in jobs of 64 lanes, one pair per lane, with at most MAXN nodes per
 // job; a job's node moments and centres are staged in LDS (two buffers: the
@@ -551,78 +639,40 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
         if (pw != 0xffffu) {
             const int ni = pw >> 6;
             const double* __restrict__ geo = sgeo[buf] + ni * G;
-            double r[D], r2 = 0.0;
+            double r[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                r[i] = txl[i] - geo[i];
-                r2 = fma(r[i], r[i], r2);
-            }
-            const double ir = rsqrt_pos(r2);  // r2 > 0: a far target is never at the centre
-            const double rr = r2 * ir;
-
-            // angular part: S_kj over harmonics of r^ (|r^| = 1 at the top level)
-            T x[D], rho2[D + 1];
-            rho2[0] = T(0);
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                x[i] = T(r[i] * ir);
-                rho2[i + 1] = rho2[i] + x[i] * x[i];
-            }
-            rho2[D] = T(1);
-            T Skj[NF];
-#pragma unroll
-            for (int i = 0; i < NF; ++i) Skj[i] = T(0);
-            const T* M = smom[buf] + ni * R;
-            int off = 0;
-            auto emit = [&](auto kc, T yv) {
-                constexpr int k = decltype(kc)::value;
-                constexpr int nj = nj_of(P, k);
-                auto dot = [&](auto jc) {
-                    constexpr int jj = decltype(jc)::value;
-                    Skj[f_off(P, k) + jj] += yv * M[off + jj];
-                };
-                static_for<0, nj>(dot);
-                off += nj;
-            };
-            harmonics<D, P, false, T>(x, rho2, (const T*)nullptr, emit);
-
-            // radial part (FP64): F_kj(r) r^j = [j=0] K + sum_m K^(m) r^m Tbar_kjm
-            double Dm[P + 1];
-            radial_derivs<KIND, P>(a, rr, Dm);
-            double um[P + 1];
-            um[0] = Dm[0];
-            double rp = 1.0;
-#pragma unroll
-            for (int m = 1; m <= P; ++m) { rp *= rr; um[m] = Dm[m] * rp; }
-            const double v = geo[D] * ir;  // s / |r| < theta
-            double vp[P + 1];
-            vp[0] = 1.0;
-#pragma unroll
-            for (int jp = 1; jp <= P; ++jp) vp[jp] = vp[jp - 1] * v;
-            double acc = 0.0;
-            auto radial_k = [&](auto kc) {
-                constexpr int k = decltype(kc)::value;
-                auto radial_j = [&](auto jc) {
-                    constexpr int jj = decltype(jc)::value;
-                    constexpr int jv = k + 2 * jj;
-                    double f = (jv == 0) ? um[0] : 0.0;
-                    auto term = [&](auto mc) {
-                        constexpr int m = decltype(mc)::value + 1;
-                        constexpr double c = cx_tbar(D, k, jv, m);
-                        f = fma(um[m], c, f);
-                    };
-                    static_for<0, jv>(term);
-                    acc = fma(vp[jv] * f, (double)Skj[f_off(P, k) + jj], acc);
-                };
-                static_for<0, nj_of(P, k)>(radial_j);
-            };
-            static_for<0, P + 1>(radial_k);
+            for (int i = 0; i < D; ++i) r[i] = txl[i] - geo[i];
+            const double acc = far_pair<D, P, KIND, T>(a, r, geo[D], smom[buf] + ni * R);
             atomicAdd(&zblk[lt], acc);
         }
         buf ^= 1;
     }
     __syncthreads();
     if (lane < cnt) unsafeAtomicAdd(zacc + tb + lane, T(zblk[lane]));
+}
+
+// Far field, node-major: every job is one far node and up to 64 of its far
+// targets (one per lane, taken from any target blocks, in tree order), so
+// the node's centre, scale and moments are the same for the whole wave and
+// are read through the scalar cache as operands of the vector FMAs: no LDS
+// staging and no per-lane moment addresses. Every pair adds its value to its
+// target's accumulator with one atomic (the near field, possibly running
+// concurrently, adds to the same accumulators). Four jobs per workgroup.
+template <int D, int P, int KIND, typename T>
+__global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zacc)
+{
+    constexpr int R = cbinom(P + D, D);
+    const int j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (j >= a.nnjobs) return;
+    const int lane = threadIdx.x & 63;
+    const int slot = a.nj_slot[j];
+    const int t = a.nj_tgt[(size_t)j * kWave + lane];
+    const int tt = t >= 0 ? t : a.nj_tgt[(size_t)j * kWave];  // lane 0 of a job always holds a target
+    double r[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) r[i] = a.pts64[(size_t)tt * D + i] - a.slot_ctr[slot * D + i];
+    const double acc = far_pair<D, P, KIND, T, true>(a, r, a.slot_scale[slot], mom + (size_t)slot * R);
+    if (t >= 0) unsafeAtomicAdd(zacc + t, T(acc));
 }
 
 // -------------------------------------------------------------- near field

@@ -262,6 +262,31 @@ void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J)
     }
 }
 
+void pack_node_jobs(const Lists& L, std::vector<int32_t>& job_slot, std::vector<int32_t>& job_tgt)
+{
+    const int64_t nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
+    std::vector<int64_t> cnt(ns + 1, 0);
+    for (int64_t q = 0; q < nb; ++q)
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) cnt[L.far_slot[e] + 1] += __builtin_popcountll(L.far_mask[e]);
+    // first job of each slot
+    std::vector<int64_t> jb(ns + 1, 0);
+    for (int64_t s2 = 0; s2 < ns; ++s2) jb[s2 + 1] = jb[s2] + (cnt[s2 + 1] + kBlock - 1) / kBlock;
+    job_slot.assign(jb[ns], 0);
+    job_tgt.assign((size_t)jb[ns] * kBlock, -1);
+    for (int64_t s2 = 0; s2 < ns; ++s2)
+        for (int64_t j = jb[s2]; j < jb[s2 + 1]; ++j) job_slot[j] = (int32_t)s2;
+    // blocks in order, so every slot's targets come out ascending
+    std::vector<int64_t> fill(ns, 0);
+    for (int64_t q = 0; q < nb; ++q)
+        for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) {
+            const int32_t s2 = L.far_slot[e];
+            for (uint64_t m = L.far_mask[e]; m; m &= m - 1) {
+                const int lane = __builtin_ctzll(m);
+                job_tgt[(size_t)jb[s2] * kBlock + fill[s2]++] = L.blk_begin[q] + lane;
+            }
+        }
+}
+
 namespace {
 struct BlockLists {
     std::vector<int32_t> near_node, far_node;

@@ -19,8 +19,12 @@ bool m2t_d(const DevPlan& a, const DevWork& wk, hipStream_t s)
         return false;
     } else {
         if (a.p == P) {
-            hipLaunchKernelGGL((k_m2t<D, P, FKT_M2T_KIND, T>), dim3(a.nblocks), dim3(kWave), 0, s, a,
-                               (const T*)wk.mom, (T*)wk.zacc);
+            if (a.nnjobs > 0)
+                hipLaunchKernelGGL((k_m2t_nodes<D, P, FKT_M2T_KIND, T>), dim3((unsigned)((a.nnjobs + 3) / 4)), dim3(256),
+                                   0, s, a, (const T*)wk.mom, (T*)wk.zacc);
+            else
+                hipLaunchKernelGGL((k_m2t<D, P, FKT_M2T_KIND, T>), dim3(a.nblocks), dim3(kWave), 0, s, a,
+                                   (const T*)wk.mom, (T*)wk.zacc);
             return true;
         }
         return m2t_d<D, T, P + 1>(a, wk, s);

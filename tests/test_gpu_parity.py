@@ -91,14 +91,17 @@ SMALL = [
 
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 def test_fp64_matches_oracle_algorithm1(F, case):
+    """Both far-field schedules (64-target blocks over their far nodes, and
+    far nodes over their targets) against the oracle."""
     name, gen, nrhs, kind, kw, leaf, p, theta = case
     X = gen()
     x = W.normal_rhs(X.shape[0], nrhs, 7)
-    z, plan = _gpu_mvm(F, X, x if nrhs > 1 else x[:, 0], kind, leaf, p, theta, **kw)
     T = oracle.Tree(X, leaf)
     okind, okw = _oracle_kind(kind, kw)
     zref = oracle.fkt_alg1(T, x, okind, theta, p, **okw)
-    _check(z, zref, 1e-10)
+    for mode in ("block", "node"):
+        z, plan = _gpu_mvm(F, X, x if nrhs > 1 else x[:, 0], kind, leaf, p, theta, far_mode=mode, **kw)
+        _check(z, zref, 1e-10)
 
 
 def test_fp64_all_near_equals_dense(F):
@@ -147,10 +150,11 @@ def test_fp32_error_against_fp64(F, kind, kw, p, theta, tol):
     X = W.uniform_cube(20000, 3, 60)
     x = W.normal_rhs(20000, 1, 61)[:, 0]
     z64, _ = _gpu_mvm(F, X, x, kind, 128, p, theta, **kw)
-    z32, _ = _gpu_mvm(F, X, x, kind, 128, p, theta, prec="f32", **kw)
-    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
-    print(f"fp32 vs fp64 {kind}: {rel:.3e}")
-    assert rel < 1e-5
+    for mode in ("block", "node"):
+        z32, _ = _gpu_mvm(F, X, x, kind, 128, p, theta, prec="f32", far_mode=mode, **kw)
+        rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+        print(f"fp32 vs fp64 {kind} ({mode}): {rel:.3e}")
+        assert rel < 1e-5
     tg = W.subsample(20000, 200, 62)
     okind, okw = _oracle_kind(kind, kw)
     T = oracle.Tree(X, 128)
@@ -197,14 +201,15 @@ def test_full_size_sampled_rows(F, full_points, full_tree, kind, kw, theta, prec
     against the oracle's rows of Algorithm 1 at the same truncation.
     FP64: the parity bar; FP32: FP32 rounding only."""
     X, x = full_points
-    z, plan = _gpu_mvm(F, X, x, kind, 256, 6, theta, prec=prec, **kw)
     tg = W.subsample(X.shape[0], 48, 4004)
     okind, okw = _oracle_kind(kind, kw)
     zr = oracle.fkt_rows(full_tree, x, okind, theta, 6, tg, **okw)[:, 0]
-    rel = np.linalg.norm(z[tg] - zr) / np.linalg.norm(zr)
-    relinf = np.abs(z[tg] - zr).max() / np.abs(zr).max()
-    print(f"full-size {kind} {prec}: rel {rel:.3e} max {relinf:.3e}")
-    assert rel <= tol and relinf <= tol
+    for mode in ("block", "node"):
+        z, plan = _gpu_mvm(F, X, x, kind, 256, 6, theta, prec=prec, far_mode=mode, **kw)
+        rel = np.linalg.norm(z[tg] - zr) / np.linalg.norm(zr)
+        relinf = np.abs(z[tg] - zr).max() / np.abs(zr).max()
+        print(f"full-size {kind} {prec} ({mode}): rel {rel:.3e} max {relinf:.3e}")
+        assert rel <= tol and relinf <= tol
 
 
 def test_pcg_block_jacobi_gp(F):
