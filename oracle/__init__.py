@@ -6,6 +6,8 @@ code with the HIP product path and never imports it.
 
 Parts:
   * ``coeffs``   -- exact-rational tables A, B, Tbar (Appendix A.2).
+  * ``radial``   -- exact ranks R_k and interpolative coefficients of the
+    compressed radial expansion for K' = q K kernels (Appendix A.4).
   * ``fkt_ref.c`` -- plain C (FP64, OpenMP): dense direct sum (eq. nbody),
     the space-partition tree (Sec. 3.1), far/near sets (eq. accparam), and
     Algorithm 1 with the compressed blocks evaluated pairwise through the
