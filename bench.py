@@ -51,13 +51,14 @@ M2T_FLOPS_PER_PAIR = {(3, 6): 418}
 NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.375e9}
 
 
-def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True):
+def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True,
+                compress=False):
     dt = torch.float32 if prec == "f32" else torch.float64
     n = X.shape[0]
-    print(f"bench: n={n} kernel={kernel} prec={prec} theta={theta} leaf={leaf} p={order} overlap={overlap}",
-          file=sys.stderr, flush=True)
+    print(f"bench: n={n} kernel={kernel} prec={prec} theta={theta} leaf={leaf} p={order} overlap={overlap} "
+          f"compress={compress}", file=sys.stderr, flush=True)
     plan = F.fkt_plan(X, kernel, leaf, order, theta=theta, prec=prec, profile=True, overlap=overlap,
-                      **KERNEL_KW[kernel])
+                      compress=compress, **KERNEL_KW[kernel])
     info = plan.info()
     x = torch.as_tensor(x64, dtype=dt, device="cuda")
     y = torch.empty_like(x)
@@ -86,7 +87,8 @@ def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmu
         rel_err = float(np.linalg.norm(z[tg] - zd) / np.linalg.norm(zd))
         print(f"bench: rel err vs dense FP64 on {len(tg)} targets: {rel_err:.3e}", file=sys.stderr, flush=True)
     plan.close()
-    return {"kernel": kernel, "prec": prec, "theta": theta, "ms_per_step": ms, "mpoints_per_s": n / ms / 1e3,
+    return {"kernel": kernel, "prec": prec, "theta": theta, "radial_compression": compress,
+            "radial_rank": info["radial_rank"], "ms_per_step": ms, "mpoints_per_s": n / ms / 1e3,
             "rel_err_vs_dense": rel_err, "stages_ms": stages, "plan": info}
 
 
@@ -115,7 +117,8 @@ def gp_solve(F, torch, n, theta, order, rank, rtol, maxit, train_steps, fp64_non
       * block_jacobi: two-level (Nystrom coarse space of `rank` landmarks,
         block-Jacobi of the residual leaf blocks), FP64 MVMs and refined;
       * learned: the same two-level form with the learned per-leaf filter
-        after train_steps Adam steps, judged by block-Jacobi on 200 CG
+        after train_steps Adam steps on the condition-number objective
+        (30 Lanczos steps per draw), judged by block-Jacobi on 200 CG
         iterations (reverted to block-Jacobi exactly if worse)."""
     spec = W.WORKLOADS["gmm4_n200k_gp"]
     X = W.gaussian_mixture(n, spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
@@ -165,10 +168,11 @@ def gp_solve(F, torch, n, theta, order, rank, rtol, maxit, train_steps, fp64_non
     timed("block_jacobi", plain("block_jacobi"))
     timed("block_jacobi_refined", refined("block_jacobi"))
     t0 = time.perf_counter()
-    l0, l1, accepted = F.fkt_learn_train(p64, sig2, steps=train_steps, batch=4, lr=3e-3, seed=1, judge_iters=200)
+    k0, k1, accepted = F.fkt_learn_train_cond(p64, sig2, train_steps, lanczos=30, lr=1e-2, seed=1, judge_iters=200)
     torch.cuda.synchronize()
-    out["learned_training"] = {"steps": train_steps, "seconds": time.perf_counter() - t0, "loss_first": l0,
-                               "loss_last": l1, "kept_after_block_jacobi_judge": accepted}
+    out["learned_training"] = {"objective": "log condition number (Lanczos)", "steps": train_steps,
+                               "seconds": time.perf_counter() - t0, "kappa_first": k0, "kappa_last": k1,
+                               "kept_after_block_jacobi_judge": accepted}
     timed("learned", plain("learned"))
     out["learned"]["fallback_to_block_jacobi_at"] = p64.info()["cg_fallback_iter"]
     F.fkt_learn_params(p32, sig2, F.fkt_learn_params(p64, sig2))
@@ -395,7 +399,7 @@ def main():
     ap.add_argument("--gp-order", type=int, default=8)
     ap.add_argument("--gp-rank", type=int, default=2048, help="landmarks of the two-level preconditioner")
     ap.add_argument("--gp-maxit", type=int, default=10000)
-    ap.add_argument("--gp-train-steps", type=int, default=30)
+    ap.add_argument("--gp-train-steps", type=int, default=10)
     ap.add_argument("--gp-fp64-none", action="store_true", help="also plain FP64 CG without a preconditioner")
     ap.add_argument("--batch-theta", type=float, default=0.3)
     ap.add_argument("--batch-leaf", type=int, default=0, help="0: the library's autotuner picks it")
@@ -459,11 +463,13 @@ def main():
 
     variants = []
     if not a.no_variants:
-        for kern, prec in (("laplace", "f64"), ("matern32", "f32"), ("laplace", "f32")):
-            if (kern, prec) == (a.kernel, a.prec):
+        # the Laplace kernel with and without radial compression (Appendix A.4)
+        for kern, prec, comp in (("laplace", "f64", False), ("laplace", "f64", True), ("matern32", "f32", False),
+                                 ("laplace", "f32", False), ("laplace", "f32", True)):
+            if (kern, prec, comp) == (a.kernel, a.prec, False):
                 continue
             v = run_variant(F, torch, X, x64, kern, prec, DEFAULT_THETA[kern], a.leaf, a.order, max(5, a.steps // 2),
-                            1, min(a.err_targets, 1000), overlap=not a.serial)
+                            1, min(a.err_targets, 1000), overlap=not a.serial, compress=comp)
             v.pop("plan")
             variants.append(v)
 

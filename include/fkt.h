@@ -101,10 +101,23 @@ typedef struct {
                            memory 4 bytes per far pair); 0 (default) picks
                            node-major except for FP32 plans of expansion
                            rank above 200.                                  */
+    int compress;       /* 1: compress the radial expansion (Appendix A.4,
+                           eq. f_g) for a kernel with K' = q K, q a Laurent
+                           polynomial (FKT_EXPONENTIAL, FKT_LAPLACE,
+                           FKT_GAUSSIAN; others: FKT_EINVAL). The exact ranks
+                           R_k are found at plan time; where compressed
+                           kernels are built (1/r and the exponential in
+                           d = 3: R_k = 1 and 2) the far field evaluates
+                           sum_k |H_k| R_k terms per node instead of
+                           C(p+d, d) (fkt_plan_stats.radial_rank), on the
+                           node-major far field (far_mode 1 and mrhs are
+                           FKT_EUNSUPPORTED). Elsewhere the plan is the
+                           uncompressed one. The result is the same
+                           truncated expansion up to rounding. 0: off.      */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
- * overlap 1, mrhs 0, far_mode 0. */
+ * overlap 1, mrhs 0, far_mode 0, compress 0. */
 void fkt_default_options(fkt_options *opt);
 
 /*
@@ -302,9 +315,34 @@ typedef struct {
     int64_t cg_fallback_iter; /* iteration at which the last fkt_cg_solve fell
                                  back from the learned filter to block-Jacobi,
                                  -1 if it did not (or no solve has run)        */
+    int64_t radial_rank;      /* far-field terms per node as evaluated: rank,
+                                 or sum_k |H_k| R_k with radial compression    */
 } fkt_plan_stats;
 
 fkt_status fkt_plan_info(fkt_plan_t p, fkt_plan_stats *s);
+
+/*
+ * fkt_radial_compression -- the exact compression of the radial expansion
+ * (Appendix A.4, eq. f_g; Table "ranks") for kernel k in d dimensions at
+ * order `order` (host only; no plan or device needed).
+ *   ranks  host, order + 1 ints (may be NULL): R_k, the rank over the
+ *          rationals of degree k's radial functions (Laurent coefficients
+ *          carried exactly modulo a 61-bit prime, as the paper's rational
+ *          rank-revealing factorisation does with exact fractions).
+ *   keep   host (may be NULL): radial rows kept per degree by the library's
+ *          compressed kernels for this kernel and d (first min(keep, nj)
+ *          rows), 0 when none are built or the rows do not qualify.
+ *   coef   host (may be NULL; written only when *keep > 0),
+ *          (order+1) * mj * mj doubles, mj = order / 2 + 1:
+ *          coef[(k * mj + jj) * mj + i] = c_{jj,i} with
+ *          L_{k+2jj}(u) = sum_i c_{jj,i} L_{k+2i}(u), i < min(keep, nj),
+ *          jj < nj = (order - k) / 2 + 1, where the radial functions of
+ *          Theorem 3.1 read F_kj(r) r^j = K(r) u^j L_j(u) in the scaled
+ *          distance u = r / l (u = r for FKT_LAPLACE).
+ * Errors: FKT_EINVAL for a kernel without K' = q K (q Laurent), d < 1, or
+ * order outside [0, 30].
+ */
+fkt_status fkt_radial_compression(const fkt_kernel *k, int d, int order, int *ranks, int *keep, double *coef);
 
 /* perm[i] = original index of the point at tree position i (host, n int64). */
 fkt_status fkt_plan_perm(fkt_plan_t p, int64_t *perm);

@@ -43,6 +43,7 @@ EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_c
             "fkt_last_error",
             "fkt_cg_solve_noalloc", "fkt_precond_coarse",
             "fkt_plan_info", "fkt_plan_perm", "fkt_plan_target_counts", "fkt_plan_lists", "fkt_plan_stage_times",
+            "fkt_radial_compression",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
             "fkt_learn_train_cond", "fkt_learn_cond_grad",
             "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
@@ -62,7 +63,8 @@ class _Kernel(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int), ("far_mode", ctypes.c_int)]
+                ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int), ("far_mode", ctypes.c_int),
+                ("compress", ctypes.c_int)]
 
 
 _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
@@ -71,7 +73,8 @@ _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes
 
 class _Stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in _STAT_FIELDS] + [("plan_seconds", ctypes.c_double),
-                                                               ("cg_fallback_iter", ctypes.c_int64)]
+                                                               ("cg_fallback_iter", ctypes.c_int64),
+                                                               ("radial_rank", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -102,6 +105,9 @@ _lib.fkt_plan_perm.restype = ctypes.c_int
 _lib.fkt_plan_perm.argtypes = [_P, _P]
 _lib.fkt_plan_target_counts.restype = ctypes.c_int
 _lib.fkt_plan_target_counts.argtypes = [_P, _P, _P, _P, _P]
+_lib.fkt_radial_compression.restype = ctypes.c_int
+_lib.fkt_radial_compression.argtypes = [ctypes.POINTER(_Kernel), ctypes.c_int, ctypes.c_int, _P,
+                                        ctypes.POINTER(ctypes.c_int), _P]
 _lib.fkt_plan_lists.restype = ctypes.c_int
 _lib.fkt_plan_lists.argtypes = [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
 _lib.fkt_plan_stage_times.restype = ctypes.c_int
@@ -175,6 +181,7 @@ class Plan:
         out = {f: int(getattr(s, f)) for f in _STAT_FIELDS}
         out["plan_seconds"] = float(s.plan_seconds)
         out["cg_fallback_iter"] = int(s.cg_fallback_iter)
+        out["radial_rank"] = int(s.radial_rank)
         return out
 
     def perm(self) -> np.ndarray:
@@ -222,7 +229,7 @@ class Plan:
 FAR_MODES = {"auto": 0, "block": 1, "node": 2}
 
 
-def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode="auto"):
+def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode="auto", compress=False):
     opt = _Options()
     _lib.fkt_default_options(ctypes.byref(opt))
     opt.theta = float(theta)
@@ -234,6 +241,7 @@ def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far
     opt.overlap = int(bool(overlap))
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
     opt.far_mode = FAR_MODES[far_mode]
+    opt.compress = int(bool(compress))
     return opt
 
 
@@ -260,11 +268,11 @@ def _batch_points(points):
 def fkt_plan_batch(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
                    variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
                    device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-                   mrhs: str | None = None, far_mode: str = "auto") -> Plan:
+                   mrhs: str | None = None, far_mode: str = "auto", compress: bool = False) -> Plan:
     """One plan over independent point sets: points is a list of (n_i, d)
     arrays or (X, offsets). fkt_mvm then takes the concatenated rows."""
     X, off = _batch_points(points)
-    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode)
+    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode, compress)
     h = _P()
     _check(_lib.fkt_plan_batch(X.ctypes.data, off.ctypes.data, len(off) - 1, X.shape[1],
                                _kernel(kernel, lengthscale, alpha, variance), int(leaf_size), int(order),
@@ -324,14 +332,15 @@ def fkt_autotune_leaf(points, kernel: str, order: int, candidates, *, nrhs: int 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
              variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
              device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-             mrhs: str | None = None, far_mode: str = "auto") -> Plan:
+             mrhs: str | None = None, far_mode: str = "auto", compress: bool = False) -> Plan:
     """Build a plan. points: (n, d) array-like (host or device; copied to host
     FP64 for the tree build). device=None builds a host-only plan. overlap
     runs the near field on a second stream beside the far field. mrhs ("f32"
     or "bf16", FP32 plans) runs the near field of groups of 32 right-hand
     sides on the matrix cores. far_mode: "block" (target-block jobs, moments
     in LDS), "node" (one far node per wave, scalar moments, atomics) or
-    "auto"."""
+    "auto". compress: radial compression (exponential, Laplace, Gaussian;
+    info()["radial_rank"] gives the terms per node evaluated)."""
     if hasattr(points, "detach"):
         points = points.detach().to("cpu").double().numpy()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -355,6 +364,7 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     opt.overlap = int(bool(overlap))
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
     opt.far_mode = FAR_MODES[far_mode]
+    opt.compress = int(bool(compress))
     h = _P()
     _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
     return Plan(h, n, d, prec, device, sh)
@@ -534,6 +544,20 @@ def fkt_learn_cond_grad(plan: Plan, sigma2: float, b, lanczos: int = 30):
     _check(_lib.fkt_learn_cond_grad(plan.handle, float(sigma2), b.data_ptr(), int(lanczos), ctypes.byref(c),
                                     g.ctypes.data))
     return c.value, g
+
+
+def fkt_radial_compression(kernel: str, d: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
+                           variance: float = 1.0):
+    """(ranks R_k, rows kept per degree by the compressed kernels (0: none),
+    interpolative coefficients [k][jj][i] or None) for the kernel."""
+    k = _kernel(kernel, lengthscale, alpha, variance)
+    mj = order // 2 + 1
+    rk = np.zeros(order + 1, dtype=np.int32)
+    keep = ctypes.c_int(0)
+    coef = np.zeros((order + 1, mj, mj), dtype=np.float64)
+    _check(_lib.fkt_radial_compression(ctypes.byref(k), int(d), int(order), rk.ctypes.data, ctypes.byref(keep),
+                                       coef.ctypes.data))
+    return rk.tolist(), keep.value, (coef if keep.value > 0 else None)
 
 
 def fkt_destroy(plan: Plan):

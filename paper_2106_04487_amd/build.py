@@ -38,6 +38,8 @@ def _jobs():
         ([*dev, "-c", os.path.join(CSRC, "cg.hip"), "-o", os.path.join(BUILD, "cg.o")]),
         (["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-c",
           os.path.join(CSRC, "learn_host.cpp"), "-o", os.path.join(BUILD, "learn_host.o")]),
+        (["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include"), "-c",
+          os.path.join(CSRC, "radial_host.cpp"), "-o", os.path.join(BUILD, "radial_host.o")]),
         ([*dev, "-c", os.path.join(CSRC, "learn.hip"), "-o", os.path.join(BUILD, "learn.o")]),
         ([*dev, "-c", os.path.join(CSRC, "mrhs.hip"), "-o", os.path.join(BUILD, "mrhs.o")]),
         ([*dev, "-c", os.path.join(CSRC, "coarse.hip"), "-o", os.path.join(BUILD, "coarse.o")]),

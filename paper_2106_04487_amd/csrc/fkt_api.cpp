@@ -115,6 +115,10 @@ struct fkt_plan_s {
     // two-level preconditioning (fkt_precond_coarse): rank and sigma2
     int coarse_k = 0;
     double coarse_sigma2 = -1.0;
+    // radial compression (opt.compress, Appendix A.4): rows kept per degree
+    // (0: off) and the interpolative coefficients
+    int comp_keep = 0;
+    std::vector<double> comp_coef;
 
     void drop_events()
     {
@@ -173,6 +177,7 @@ void fkt_default_options(fkt_options* opt)
     opt->overlap = 1;
     opt->mrhs = 0;
     opt->far_mode = 0;
+    opt->compress = 0;
 }
 
 const char* fkt_last_error(void) { return g_err.c_str(); }
@@ -246,7 +251,7 @@ static fkt_status upload_plan(fkt_plan_t P)
     {
         // node-major far jobs (far_mode 2; far_mode 0 except FP32 plans of
         // rank above 200, where the block-major kernel was measured faster)
-        const bool node_major = P->opt.far_mode == 2 ||
+        const bool node_major = P->opt.far_mode == 2 || P->comp_keep > 0 ||
                                 (P->opt.far_mode == 0 && !(P->opt.prec == FKT_F32 && P->tab.rank > 200));
         a.nnjobs = 0;
         a.nj_slot = nullptr;
@@ -277,6 +282,11 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.red_off, a.red_off);
     FKT_UP(P->tab.tbar, a.tbar);
     FKT_UP(P->tab.exp2tab, a.exp2tab);
+    a.comp_keep = P->comp_keep;
+    a.comp_rank = (int)P->st.radial_rank;
+    a.comp_invlen = P->kern.kind == FKT_LAPLACE ? 1.0 : 1.0 / P->kern.lengthscale;
+    a.comp_coef = nullptr;
+    if (P->comp_keep > 0) FKT_UP(P->comp_coef, a.comp_coef);
     {
         std::vector<double> h2(P->tab.hnorm.size());
         for (size_t i = 0; i < h2.size(); ++i) h2[i] = P->tab.hnorm[i] * P->tab.hnorm[i];
@@ -286,12 +296,25 @@ static fkt_status upload_plan(fkt_plan_t P)
     }
 #undef FKT_UP
     const size_t es = P->opt.prec == FKT_F32 ? sizeof(float) : sizeof(double);
-    if ((e = P->alloc(es * P->n * (P->d == 3 ? 4 : 6), &P->wk.src)) != hipSuccess) return hip_fail(e, "work buffer");
-    if ((e = P->alloc(es * P->n, &P->wk.zacc)) != hipSuccess) return hip_fail(e, "work buffer");
-    if ((e = P->alloc(es * L.slot_node.size() * P->tab.rank, &P->wk.mom)) != hipSuccess)
+    // multi-column passes (kMvmCols columns at a time) run on the node-major
+    // far field (or with no far field at all); their buffers hold that many
+    // columns
+    const int nc = (a.nnjobs > 0 || L.slot_node.empty()) ? fkt::kMvmCols : 1;
+    P->wk.ncmax = nc;
+    const size_t srcw = (size_t)((P->d + nc + 1) & ~1);  // packed record: coordinates + nc weights, even
+    if ((e = P->alloc(es * P->n * srcw, &P->wk.src)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * P->n * nc, &P->wk.zacc)) != hipSuccess) return hip_fail(e, "work buffer");
+    if ((e = P->alloc(es * L.slot_node.size() * P->tab.rank * nc, &P->wk.mom)) != hipSuccess)
         return hip_fail(e, "moment buffer");
-    if ((e = P->alloc(es * L.npartials * P->tab.rank, &P->wk.part)) != hipSuccess)
+    if ((e = P->alloc(es * L.npartials * P->tab.rank * nc, &P->wk.part)) != hipSuccess)
         return hip_fail(e, "partial-moment buffer");
+    P->wk.momc = nullptr;
+    if (P->comp_keep > 0 &&
+        (e = P->alloc(es * L.slot_node.size() * (size_t)P->st.radial_rank * nc, &P->wk.momc)) != hipSuccess)
+        return hip_fail(e, "compressed-moment buffer");
+    P->wk.mom_cols = L.slot_node.size() * (size_t)P->tab.rank;
+    P->wk.part_cols = (size_t)L.npartials * (size_t)P->tab.rank;
+    P->wk.momc_cols = P->comp_keep > 0 ? L.slot_node.size() * (size_t)P->st.radial_rank : 0;
     // many-RHS near field: leaves padded to multiples of 32 points, SoA
     // coordinates, target-major near lists with padded ranges
     if (P->opt.mrhs != 0) {
@@ -396,6 +419,13 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
     if (opt.mrhs < 0 || opt.mrhs > 2) return fail(FKT_EINVAL, "mrhs must be 0, 1 or 2");
     if (opt.mrhs != 0 && opt.prec != FKT_F32) return fail(FKT_EUNSUPPORTED, "mrhs needs an FP32 plan");
     if (opt.far_mode < 0 || opt.far_mode > 2) return fail(FKT_EINVAL, "far_mode must be 0, 1 or 2");
+    if (opt.compress != 0 && opt.compress != 1) return fail(FKT_EINVAL, "compress must be 0 or 1");
+    if (opt.compress && !fkt::radial_has_laurent_q((int)k.kind))
+        return fail(FKT_EINVAL, "radial compression needs K' = q K with q a Laurent polynomial "
+                                "(exponential, Laplace or Gaussian kernel)");
+    if (opt.compress && opt.mrhs != 0) return fail(FKT_EUNSUPPORTED, "radial compression with mrhs is not built");
+    if (opt.compress && opt.far_mode == 1)
+        return fail(FKT_EUNSUPPORTED, "radial compression runs the node-major far field (far_mode 0 or 2)");
     if (opt.max_depth < 1 || opt.max_depth > 60) return fail(FKT_EINVAL, "max_depth must be in [1, 60]");
     if (opt.device < -1) return fail(FKT_EINVAL, "device must be >= -1");
     fkt_status s = check_kernel(k);
@@ -430,6 +460,23 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
             return fail(FKT_EINVAL, "internal error: " + err);
         }
         fkt::build_tables(d, order, P->tab);
+        P->st.radial_rank = P->tab.rank;
+        const int keep = opt.compress ? fkt::radial_keep((int)k.kind, d) : 0;
+        if (keep > 0) {
+            // compressed kernels are built for this kernel and dimension: keep
+            // the first min(keep, nj) rows when they carry the exact rank
+            std::vector<int> rk;
+            std::string cerr;
+            bool ok = fkt::radial_ranks((int)k.kind, d, order, rk);
+            for (int kk = 0; ok && kk <= order; ++kk) ok = rk[kk] == std::min(keep, (order - kk) / 2 + 1);
+            if (ok && fkt::radial_interpolative((int)k.kind, d, order, keep, P->comp_coef, cerr)) {
+                P->comp_keep = keep;
+                int64_t rc = 0;
+                for (int kk = 0; kk <= order; ++kk)
+                    rc += (fkt::binom(kk + d - 1, d - 1) - (kk >= 2 ? fkt::binom(kk + d - 3, d - 1) : 0)) * rk[kk];
+                P->st.radial_rank = rc;
+            }
+        }
     } catch (const std::bad_alloc&) {
         delete P;
         return fail(FKT_ENOMEM, "host allocation while building the plan");
@@ -476,6 +523,16 @@ fkt_status fkt_plan_batch(const double* points, const int64_t* offsets, int nins
     return make_plan(points, offsets[ninst], d, offsets, ninst, k, leaf_size, order, opt, out);
 }
 
+// Columns of the next MVM pass when `left` columns remain: kMvmCols at a
+// time (three padded to four: the shared kernel values, harmonics and
+// radial functions outweigh one padded column) where the plan's buffers
+// allow it, else one.
+static void mvm_pass_width(const fkt_plan_s* P, int left, int& ncols, int& nc)
+{
+    nc = (P->wk.ncmax >= fkt::kMvmCols && left >= fkt::kMvmCols - 1) ? fkt::kMvmCols : 1;
+    ncols = std::min(nc, left);
+}
+
 fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
 {
     if (!P) return fail(FKT_EINVAL, "plan is NULL");
@@ -492,7 +549,9 @@ fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
         const hipError_t e = fkt::launch_mvm_mrhs(P->dp, P->wk, P->mr, (const float*)x, (float*)y, nrhs, P->stream);
         return e == hipSuccess ? FKT_OK : hip_fail(e, "fkt_mvm many-RHS launch");
     }
-    for (int c = 0; c < nrhs; ++c) {
+    for (int c = 0; c < nrhs;) {
+        int ncols, nc;
+        mvm_pass_width(P, nrhs - c, ncols, nc);
         hipEvent_t* ev = nullptr;
         if (P->opt.profile) {
             fkt_plan_s::Ev7 q{};
@@ -501,9 +560,10 @@ fkt_status fkt_mvm(fkt_plan_t P, const void* x, void* y, int nrhs)
             P->prof.push_back(q);
             ev = P->prof.back().e;
         }
-        hipError_t e = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, P->stream,
+        hipError_t e = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, ncols, nc, (int)P->opt.prec, P->stream,
                                               P->opt.overlap != 0, ev);
         if (e != hipSuccess) return hip_fail(e, "fkt_mvm launch");
+        c += ncols;
     }
     return FKT_OK;
 }
@@ -580,6 +640,32 @@ fkt_status fkt_plan_target_counts(fkt_plan_t P, int64_t* far_nodes, int64_t* far
                 if (near_points) near_points[t] += L.near_end[e] - L.near_beg[e];
             }
         }
+    }
+    return FKT_OK;
+}
+
+fkt_status fkt_radial_compression(const fkt_kernel* k, int d, int order, int* ranks, int* keep, double* coef)
+{
+    if (!k) return fail(FKT_EINVAL, "kernel is NULL");
+    fkt_status s = check_kernel(*k);
+    if (s != FKT_OK) return s;
+    if (d < 1 || order < 0 || order > 30) return fail(FKT_EINVAL, "d must be >= 1 and order in [0, 30]");
+    if (!fkt::radial_has_laurent_q((int)k->kind))
+        return fail(FKT_EINVAL, "the kernel has no K' = q K with q a Laurent polynomial");
+    try {
+        std::vector<int> rk;
+        fkt::radial_ranks((int)k->kind, d, order, rk);
+        if (ranks) std::copy(rk.begin(), rk.end(), ranks);
+        const int kp = fkt::radial_keep((int)k->kind, d);
+        bool ok = kp > 0;
+        for (int kk = 0; ok && kk <= order; ++kk) ok = rk[kk] == std::min(kp, (order - kk) / 2 + 1);
+        std::vector<double> c;
+        std::string err;
+        if (ok) ok = fkt::radial_interpolative((int)k->kind, d, order, kp, c, err);
+        if (keep) *keep = ok ? kp : 0;
+        if (coef && ok) std::copy(c.begin(), c.end(), coef);
+    } catch (const std::bad_alloc&) {
+        return fail(FKT_ENOMEM, "host allocation");
     }
     return FKT_OK;
 }
@@ -1073,9 +1159,13 @@ fkt_status fkt_graph_create(fkt_plan_t P, const void* x, void* y, int nrhs, fkt_
         if (P->opt.mrhs != 0 && nrhs % fkt::kMrCols == 0)
             le = fkt::launch_mvm_mrhs(P->dp, P->wk, P->mr, (const float*)x, (float*)y, nrhs, cap);
         else
-            for (int c = 0; c < nrhs && le == hipSuccess; ++c)
-                le = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, (int)P->opt.prec, cap, P->opt.overlap != 0,
-                                            nullptr);
+            for (int c = 0; c < nrhs && le == hipSuccess;) {
+                int ncols, nc;
+                mvm_pass_width(P, nrhs - c, ncols, nc);
+                le = fkt::launch_mvm_column(P->dp, P->wk, x, y, nrhs, c, ncols, nc, (int)P->opt.prec, cap,
+                                            P->opt.overlap != 0, nullptr);
+                c += ncols;
+            }
         e = hipStreamEndCapture(cap, &G->graph);
         if (e == hipSuccess && le != hipSuccess) e = le;
     }

@@ -43,7 +43,27 @@ struct DevPlan {
     const double* hn64;           // squared harmonic normalisation (x Z_k), FP64
     const float* hn32;            //   and FP32 copy
     const double* exp2tab;        // [256] 2^(j/256), FP64 exponential table
+    // radial compression (Appendix A.4): comp_keep > 0 keeps the first
+    // min(comp_keep, nj) radial rows of every degree; the moments are
+    // combined into them with comp_coef (see radial_keep, k_compress)
+    int comp_keep;
+    int comp_rank;                // moments per node after compression
+    double comp_invlen;           // 1 / l of the scaled distance (1 for 1/r)
+    const double* comp_coef;      // [(p+1)][p/2+1][p/2+1]
 };
+
+// Right-hand-side columns of one multi-column MVM pass: every stage runs the
+// columns together (shared kernel values, harmonics and radial functions)
+// on plans with the node-major far field; others run column by column.
+constexpr int kMvmCols = 4;
+
+// Rows kept per degree by the compressed kernels built for (kind, d), 0 for
+// none: 1/r and e^(-r/l) in d = 3 (the paper's Table "ranks": R_k = 1 and 2).
+constexpr int radial_keep(int kind, int d)
+{
+    if (d != 3) return 0;
+    return kind == FKT_LAPLACE ? 1 : (kind == FKT_EXPONENTIAL ? 2 : 0);
+}
 
 // Per-call work buffers (device) for one right-hand-side column.
 struct DevWork {
@@ -51,6 +71,11 @@ struct DevWork {
     void* zacc;   // [n] per-target sum (far field stored, near field added), tree order
     void* mom;    // [nslots][rank]
     void* part;   // [npartials][rank]
+    void* momc;   // [nslots][comp_rank] compressed moments (comp_keep > 0)
+    // src and zacc hold ncmax columns ([point][column]); mom, part and momc
+    // ncmax blocks ([column][slot or partial][entry]) of these sizes:
+    int ncmax;
+    size_t mom_cols, part_cols, momc_cols;  // elements per column block
     hipStream_t side;    // second stream: the near field runs beside the far field
     hipEvent_t fork, join;
 };
@@ -95,7 +120,10 @@ struct CgPlanView {
     int coarse = 0;          // two-level: precond 1 and 2 run through learn_apply with the coarse part
 };
 
+// Columns col .. col + ncols - 1 of y = K~ x in one pass of nc columns (1 or
+// kMvmCols, ncols <= nc; nc > 1 needs the node-major far field or no far
+// field, and work buffers sized for nc columns).
 hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,
-                             int prec, hipStream_t s, bool overlap, hipEvent_t* ev);
+                             int ncols, int nc, int prec, hipStream_t s, bool overlap, hipEvent_t* ev);
 
 }  // namespace fkt

@@ -120,6 +120,17 @@ bool build_block_jacobi(const Tree& T, const fkt_kernel& k, double sigma2, std::
                         std::vector<int32_t>& leaf_count, std::vector<int64_t>& off, std::vector<double>& inv);
 int64_t binom(int64_t a, int64_t b);
 
+// Radial compression (Appendix A.4, radial_host.cpp). Whether the kernel
+// satisfies K' = q K with q a Laurent polynomial (exponential, 1/r, Gaussian).
+bool radial_has_laurent_q(int kind);
+// Exact R_k, k = 0..p, of eq. (f_g); false for a kernel without such a q.
+bool radial_ranks(int kind, int d, int p, std::vector<int>& rank);
+// Interpolative coefficients keeping the first min(keep, nj) radial rows of
+// every degree: coef[(k * mj + jj) * mj + i] (mj = p / 2 + 1) with
+// L_{k+2jj} = sum_i coef L_{k+2i}; false (+ err) when those rows do not
+// span all rows or are dependent.
+bool radial_interpolative(int kind, int d, int p, int keep, std::vector<double>& coef, std::string& err);
+
 // Simple parallel-for over [0, n) on host threads.
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)>& fn);
 

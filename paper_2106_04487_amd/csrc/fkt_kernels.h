@@ -61,6 +61,22 @@ constexpr int f_off(int p, int k)
     for (int q = 0; q < k; ++q) o += nj_of(p, q);
     return o;
 }
+// radial rows of degree k kept by a compressed expansion (keep 0: all)
+constexpr int nk_of(int p, int k, int keep) { return keep > 0 && keep < nj_of(p, k) ? keep : nj_of(p, k); }
+constexpr int fk_off(int p, int k, int keep)
+{
+    int o = 0;
+    for (int q = 0; q < k; ++q) o += nk_of(p, q, keep);
+    return o;
+}
+// terms per node: sum_k |H_k| nk, |H_k| = C(k+d-1, d-1) - C(k+d-3, d-1)
+constexpr int crank(int d, int p, int keep)
+{
+    int o = 0;
+    for (int k = 0; k <= p; ++k)
+        o += (cbinom(k + d - 1, d - 1) - (k >= 2 ? cbinom(k + d - 3, d - 1) : 0)) * nk_of(p, k, keep);
+    return o;
+}
 
 // Hides a table pointer's value from the optimiser so that loads from fixed
 // offsets are issued where they are used (cheap scalar-cache hits) instead of
@@ -376,25 +392,29 @@ template <> __device__ __forceinline__ const float* hn_ptr<float>(const DevPlan&
 
 // ------------------------------------------------------------------ gather
 //
-// Packed source records in tree order: D coordinates then the weight of the
-// current right-hand-side column, stride src_stride(D) elements; the
-// per-target accumulator is cleared on the way.
-constexpr int src_stride(int d) { return d == 3 ? 4 : 6; }
+// Packed source records in tree order: D coordinates then the weights of
+// the NC right-hand-side columns of the pass, stride src_stride(D, NC)
+// elements (even); the per-target accumulators ([n][NC]) are cleared on the
+// way. Columns past ncols (a pass padded to NC) get weight 0.
+constexpr int src_stride(int d, int nc = 1) { return (d + nc + 1) & ~1; }
 
-template <int D, typename T>
+template <int D, typename T, int NC = 1>
 __global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict__ perm, const T* __restrict__ pts,
-                                                const T* __restrict__ x, int nrhs, int col, T* __restrict__ src,
-                                                T* __restrict__ zacc)
+                                                const T* __restrict__ x, int nrhs, int col, int ncols,
+                                                T* __restrict__ src, T* __restrict__ zacc)
 {
-    constexpr int S = src_stride(D);
+    constexpr int S = src_stride(D, NC);
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    zacc[i] = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) zacc[(size_t)i * NC + c] = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) src[(size_t)i * S + a] = pts[(size_t)i * D + a];
-    src[(size_t)i * S + D] = x[perm[i] * nrhs + col];
+    const int64_t row = perm[i] * nrhs + col;
 #pragma unroll
-    for (int a = D + 1; a < S; ++a) src[(size_t)i * S + a] = T(0);
+    for (int c = 0; c < NC; ++c) src[(size_t)i * S + D + c] = c < ncols ? x[row + c] : T(0);
+#pragma unroll
+    for (int a = D + NC; a < S; ++a) src[(size_t)i * S + a] = T(0);
 }
 
 // --------------------------------------------------------------------- s2m
@@ -404,13 +424,14 @@ __global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict
 // most kUnitPoints points of one node; each lane accumulates its points'
 // contributions to moment entries [C0, C1) in registers, then the wave sums.
 // Moments carry the harmonics' normalisation (see harmonics<NORM>).
+// The weights are column col of records of stride S (a multi-column pass
+// runs one launch per column; mom and part point at that column's block).
 template <int D, int P, typename T, int C0, int C1>
-__global__ __launch_bounds__(kWave) void k_s2m(const DevPlan a, const T* __restrict__ src, T* __restrict__ mom,
-                                               T* __restrict__ part)
+__global__ __launch_bounds__(kWave) void k_s2m(const DevPlan a, const T* __restrict__ src, int S, int col,
+                                               T* __restrict__ mom, T* __restrict__ part)
 {
     constexpr int R = cbinom(P + D, D);
     constexpr int NC = C1 - C0;
-    constexpr int S = src_stride(D);
     const int u = blockIdx.x;
     const int lane = threadIdx.x;
     const int slot = a.unit_slot[u];
@@ -435,7 +456,7 @@ __global__ __launch_bounds__(kWave) void k_s2m(const DevPlan a, const T* __restr
             rho2[i + 1] = rho2[i] + x[i] * x[i];
         }
         T q[P / 2 + 1];
-        q[0] = src[(size_t)s * S + D];
+        q[0] = src[(size_t)s * S + D + col];
 #pragma unroll
         for (int i = 1; i <= P / 2; ++i) q[i] = q[i - 1] * rho2[D];
         int off = 0;
@@ -478,26 +499,26 @@ __global__ __launch_bounds__(256) void k_s2m_reduce(int nred, int R, const int* 
 
 // --------------------------------------------------------------------- m2t
 //
-// Far field of every target: for each far node of its own walk, the plain
-// harmonics of the unit vector towards the target contracted with the
-// node's moments, S_kj = sum_h Y_kh(r^) M_b[kh, j], then the radial
-// functions (FP64): z += sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj.
-//
 // Far-field value of one (target, far node) pair: the plain harmonics of
 // the unit vector towards the target contracted with the node's moments M,
 // S_kj = sum_h Y_kh(r^) M[kh, j], then the radial functions (FP64):
 // sum_kj (s/|r|)^j (F_kj(|r|) |r|^j) S_kj. r = target - centre, scale = s.
+// With KEEP > 0 (radial compression, Appendix A.4) only the first
+// nk_of(P, k, KEEP) radial rows of each degree are evaluated, against moments
+// already combined into them (k_compress).
 //
 // With UNIFORM_M the moments are the same for the whole wave (node-major
 // jobs): each harmonic's few moments are then loaded through a pointer the
 // optimiser cannot see through, so the scalar loads are issued where they
 // are used instead of all at once (which spills the scalar registers).
-template <int D, int P, int KIND, typename T, bool UNIFORM_M = false>
-__device__ __forceinline__ double far_pair(const DevPlan& a, const double (&r)[D], double scale, const T* M)
+// With NCOL columns, column c's moments start at M + c * cs and out
+// receives one value per column; the harmonics and radial functions are
+// shared by the columns.
+template <int D, int P, int KIND, typename T, bool UNIFORM_M = false, int KEEP = 0, int NCOL = 1>
+__device__ __forceinline__ void far_pair(const DevPlan& a, const double (&r)[D], double scale, const T* M,
+                                         size_t cs, double (&out)[NCOL])
 {
-    constexpr int R = cbinom(P + D, D);
-    constexpr int NF = f_off(P, P + 1);
-    (void)R;
+    constexpr int NF = fk_off(P, P + 1, KEEP);
     double r2 = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) r2 = fma(r[i], r[i], r2);
@@ -513,24 +534,31 @@ __device__ __forceinline__ double far_pair(const DevPlan& a, const double (&r)[D
         rho2[i + 1] = rho2[i] + x[i] * x[i];
     }
     rho2[D] = T(1);
-    T Skj[NF];
+    T Skj[NF * NCOL];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) Skj[i] = T(0);
+    for (int i = 0; i < NF * NCOL; ++i) Skj[i] = T(0);
     int off = 0;
     auto emit = [&](auto kc, T yv) {
         constexpr int k = decltype(kc)::value;
-        constexpr int nj = nj_of(P, k);
+        constexpr int nj = nk_of(P, k, KEEP);
         // constant address space: uniform loads from it go through the
         // scalar cache (the moments are written by an earlier launch)
         using CT = const __attribute__((address_space(4))) T;
-        CT* Mc = (CT*)(M + off);
-        if constexpr (UNIFORM_M) asm volatile("" : "+s"(Mc));
+        CT* Mc[NCOL];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) {
+            Mc[c] = (CT*)(M + c * cs + off);
+            if constexpr (UNIFORM_M) asm volatile("" : "+s"(Mc[c]));
+        }
         auto dot = [&](auto jc) {
             constexpr int jj = decltype(jc)::value;
-            if constexpr (UNIFORM_M)
-                Skj[f_off(P, k) + jj] += yv * Mc[jj];
-            else
-                Skj[f_off(P, k) + jj] += yv * M[off + jj];
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                if constexpr (UNIFORM_M)
+                    Skj[(fk_off(P, k, KEEP) + jj) * NCOL + c] += yv * Mc[c][jj];
+                else
+                    Skj[(fk_off(P, k, KEEP) + jj) * NCOL + c] += yv * M[c * cs + off + jj];
+            }
         };
         static_for<0, nj>(dot);
         off += nj;
@@ -550,7 +578,8 @@ __device__ __forceinline__ double far_pair(const DevPlan& a, const double (&r)[D
     vp[0] = 1.0;
 #pragma unroll
     for (int jp = 1; jp <= P; ++jp) vp[jp] = vp[jp - 1] * v;
-    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) out[c] = 0.0;
     auto radial_k = [&](auto kc) {
         constexpr int k = decltype(kc)::value;
         auto radial_j = [&](auto jc) {
@@ -563,12 +592,13 @@ __device__ __forceinline__ double far_pair(const DevPlan& a, const double (&r)[D
                 f = fma(um[m], c, f);
             };
             static_for<0, jv>(term);
-            acc = fma(vp[jv] * f, (double)Skj[f_off(P, k) + jj], acc);
+            const double vf = vp[jv] * f;
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) out[c] = fma(vf, (double)Skj[(fk_off(P, k, KEEP) + jj) * NCOL + c], out[c]);
         };
-        static_for<0, nj_of(P, k)>(radial_j);
+        static_for<0, nk_of(P, k, KEEP)>(radial_j);
     };
     static_for<0, P + 1>(radial_k);
-    return acc;
 }
 
 // One wave per 64-target block. The block's (target, far node) pairs come
@@ -642,8 +672,9 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
             double r[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) r[i] = txl[i] - geo[i];
-            const double acc = far_pair<D, P, KIND, T>(a, r, geo[D], smom[buf] + ni * R);
-            atomicAdd(&zblk[lt], acc);
+            double acc[1];
+            far_pair<D, P, KIND, T>(a, r, geo[D], smom[buf] + ni * R, 0, acc);
+            atomicAdd(&zblk[lt], acc[0]);
         }
         buf ^= 1;
     }
@@ -658,10 +689,13 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
 // staging and no per-lane moment addresses. Every pair adds its value to its
 // target's accumulator with one atomic (the near field, possibly running
 // concurrently, adds to the same accumulators). Four jobs per workgroup.
-template <int D, int P, int KIND, typename T>
-__global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zacc)
+// With NCOL columns, column c's moments are the block mom + c * cs and the
+// accumulators are [n][NCOL].
+template <int D, int P, int KIND, typename T, int KEEP = 0, int NCOL = 1>
+__global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __restrict__ mom, size_t cs,
+                                                   T* __restrict__ zacc)
 {
-    constexpr int R = cbinom(P + D, D);
+    constexpr int R = crank(D, P, KEEP);
     const int j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
     if (j >= a.nnjobs) return;
     const int lane = threadIdx.x & 63;
@@ -671,8 +705,56 @@ __global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __r
     double r[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) r[i] = a.pts64[(size_t)tt * D + i] - a.slot_ctr[slot * D + i];
-    const double acc = far_pair<D, P, KIND, T, true>(a, r, a.slot_scale[slot], mom + (size_t)slot * R);
-    if (t >= 0) unsafeAtomicAdd(zacc + t, T(acc));
+    double acc[NCOL];
+    far_pair<D, P, KIND, T, true, KEEP, NCOL>(a, r, a.slot_scale[slot], mom + (size_t)slot * R, cs, acc);
+    if (t >= 0) {
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) unsafeAtomicAdd(zacc + (size_t)t * NCOL + c, T(acc[c]));
+    }
+}
+
+// Radial compression of the moments (Appendix A.4, eq. f_g): for every far
+// node and harmonic (k, h), the kept rows i < nk take the others in,
+//   M'_i = M_i + sum_{jj >= nk} c[k][jj][i] sigma^(2 (jj - i)) M_jj,
+// sigma = s / l, with the exact interpolative coefficients of the host
+// (L_{k+2jj} = sum_i c L_{k+2i}); arithmetic in FP64. One thread per node
+// walks the harmonics in the order s2m and m2t lay them out (their values
+// are not needed, only the degree of each).
+template <int D, int P, typename T, int KEEP>
+__global__ __launch_bounds__(256) void k_compress(const DevPlan a, const T* __restrict__ mom, T* __restrict__ momc)
+{
+    constexpr int R = cbinom(P + D, D);
+    constexpr int RC = crank(D, P, KEEP);
+    constexpr int MJ = P / 2 + 1;
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= a.nslots) return;
+    const double sg = a.slot_scale[slot] * a.comp_invlen;
+    const double s2 = sg * sg;
+    const T* M = mom + (size_t)slot * R;
+    T* O = momc + (size_t)slot * RC;
+    int fo = 0, co = 0;
+    T x[D], rho2[D + 1];
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = T(0);
+#pragma unroll
+    for (int i = 0; i <= D; ++i) rho2[i] = T(0);
+    auto emit = [&](auto kc, T) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int nj = nj_of(P, k), nk = nk_of(P, k, KEEP);
+        for (int i = 0; i < nk; ++i) {
+            double acc = (double)M[fo + i];
+            double w = 1.0;
+            for (int t = i; t < nk; ++t) w *= s2;  // sigma^(2 (nk - i))
+            for (int jj = nk; jj < nj; ++jj) {
+                acc = fma(a.comp_coef[(k * MJ + jj) * MJ + i] * w, (double)M[fo + jj], acc);
+                w *= s2;
+            }
+            O[co + i] = T(acc);
+        }
+        fo += nj;
+        co += nk;
+    };
+    harmonics<D, P, false, T>(x, rho2, (const T*)nullptr, emit);
 }
 
 // -------------------------------------------------------------- near field
@@ -816,11 +898,12 @@ template <> struct NearKernel<FKT_LAPLACE, float> {
 // points stream through scalar registers; each target's sum is added to its
 // accumulator with one FP64/FP32 atomic per (target, leaf), so no lane ever
 // idles on a target whose own walk does not reach l.
-template <int D, int KIND, typename T>
+// With NCOL columns each kernel value multiplies NCOL weights.
+template <int D, int KIND, typename T, int NCOL = 1>
 __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, T* __restrict__ zacc,
                                                 T c0, T c1, T scale)
 {
-    constexpr int S = src_stride(D);
+    constexpr int S = src_stride(D, NCOL);
     using NK = NearKernel<KIND, T>;
     __shared__ double tab[NK::kTable ? kExpTabLen : 1];
     const int u = blockIdx.x;
@@ -843,35 +926,61 @@ __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __rest
         T tx[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) tx[k] = src[(size_t)t * S + k];
-        auto pair = [&](const T* __restrict__ p) {
+        auto kval = [&](const T* __restrict__ p) {
             T d2 = T(NK::kBias);
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const T w = tx[k] - p[k];
                 d2 = fma(w, w, d2);
             }
-            return NK::eval(d2, c0, c1, tab) * p[D];
+            return NK::eval(d2, c0, c1, tab);
         };
-        T acc0 = T(0), acc1 = T(0);
-        int s = 0;
-        for (; s + 4 <= m; s += 4) {
-            acc0 += pair(q + (s + 0) * S);
-            acc1 += pair(q + (s + 1) * S);
-            acc0 += pair(q + (s + 2) * S);
-            acc1 += pair(q + (s + 3) * S);
+        if constexpr (NCOL == 1) {
+            auto pair = [&](const T* __restrict__ p) { return kval(p) * p[D]; };
+            T acc0 = T(0), acc1 = T(0);
+            int s = 0;
+            for (; s + 4 <= m; s += 4) {
+                acc0 += pair(q + (s + 0) * S);
+                acc1 += pair(q + (s + 1) * S);
+                acc0 += pair(q + (s + 2) * S);
+                acc1 += pair(q + (s + 3) * S);
+            }
+            for (; s < m; ++s) acc0 += pair(q + s * S);
+            if (valid) unsafeAtomicAdd(zacc + t, scale * (acc0 + acc1));
+        } else {
+            T acc[2][NCOL];
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) acc[0][c] = acc[1][c] = T(0);
+            auto pair = [&](const T* __restrict__ p, T (&ac)[NCOL]) {
+                const T kv = kval(p);
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) ac[c] = fma(kv, p[D + c], ac[c]);
+            };
+            int s = 0;
+            for (; s + 2 <= m; s += 2) {
+                pair(q + (s + 0) * S, acc[0]);
+                pair(q + (s + 1) * S, acc[1]);
+            }
+            if (s < m) pair(q + s * S, acc[0]);
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) unsafeAtomicAdd(zacc + (size_t)t * NCOL + c, scale * (acc[0][c] + acc[1][c]));
+            }
         }
-        for (; s < m; ++s) acc0 += pair(q + s * S);
-        if (valid) unsafeAtomicAdd(zacc + t, scale * (acc0 + acc1));
     }
 }
 
-// y (caller order, column col) <- zacc (tree order)
-template <typename T>
+// y (caller order, columns col .. col + ncols - 1) <- zacc (tree order, [n][NC])
+template <typename T, int NC = 1>
 __global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restrict__ perm, const T* __restrict__ zacc,
-                                                 T* __restrict__ y, int nrhs, int col)
+                                                 T* __restrict__ y, int nrhs, int col, int ncols)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) y[perm[i] * nrhs + col] = zacc[i];
+    if (i >= n) return;
+    const int64_t row = perm[i] * nrhs + col;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c < ncols) y[row + c] = zacc[(size_t)i * NC + c];
 }
 
 // ------------------------------------------------- built orders per dimension
@@ -896,8 +1005,10 @@ constexpr int s2m_chunk(int R)
 }  // namespace
 
 // Launchers implemented in the per-stage translation units.
-bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
-#define FKT_DECLARE_S2M(D, PR) bool launch_s2m_d##D##_p##PR(const DevPlan& a, const DevWork& wk, hipStream_t s);
+// nc: columns of the pass, 1 or kMvmCols (moments [column][slot][entry]).
+bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc = 1);
+#define FKT_DECLARE_S2M(D, PR) \
+    bool launch_s2m_d##D##_p##PR(const DevPlan& a, const DevWork& wk, hipStream_t s, int nc);
 FKT_DECLARE_S2M(3, 0)
 FKT_DECLARE_S2M(3, 1)
 FKT_DECLARE_S2M(4, 0)
@@ -905,8 +1016,9 @@ FKT_DECLARE_S2M(4, 1)
 FKT_DECLARE_S2M(5, 0)
 FKT_DECLARE_S2M(5, 1)
 #undef FKT_DECLARE_S2M
-bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
-#define FKT_DECLARE_M2T(K) bool launch_m2t_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s);
+bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc = 1);
+#define FKT_DECLARE_M2T(K) \
+    bool launch_m2t_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc);
 FKT_DECLARE_M2T(0)
 FKT_DECLARE_M2T(1)
 FKT_DECLARE_M2T(2)

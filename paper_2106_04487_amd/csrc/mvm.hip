@@ -1,20 +1,20 @@
-// Orchestration of one MVM column (gather, s2m, m2t, near field) and the
-// near-field launches.
+// Orchestration of one MVM pass (gather, s2m, m2t, near field, scatter) over
+// one or kMvmCols right-hand-side columns, and the near-field launches.
 #include "fkt_kernels.h"
 #include "fkt_mrhs.h"
 
 namespace fkt {
 
-bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc)
 {
     switch (kind) {
-    case 0: return launch_m2t_kind0(a, wk, prec, s);
-    case 1: return launch_m2t_kind1(a, wk, prec, s);
-    case 2: return launch_m2t_kind2(a, wk, prec, s);
-    case 3: return launch_m2t_kind3(a, wk, prec, s);
-    case 4: return launch_m2t_kind4(a, wk, prec, s);
-    case 5: return launch_m2t_kind5(a, wk, prec, s);
-    case 6: return launch_m2t_kind6(a, wk, prec, s);
+    case 0: return launch_m2t_kind0(a, wk, prec, s, nc);
+    case 1: return launch_m2t_kind1(a, wk, prec, s, nc);
+    case 2: return launch_m2t_kind2(a, wk, prec, s, nc);
+    case 3: return launch_m2t_kind3(a, wk, prec, s, nc);
+    case 4: return launch_m2t_kind4(a, wk, prec, s, nc);
+    case 5: return launch_m2t_kind5(a, wk, prec, s, nc);
+    case 6: return launch_m2t_kind6(a, wk, prec, s, nc);
     default: return false;
     }
 }
@@ -46,7 +46,7 @@ void near_consts(const DevPlan& a, T& c0, T& c1)
     c1 = (T)k1;
 }
 
-template <int D, typename T>
+template <int D, typename T, int NCOL>
 bool run_near_d(const DevPlan& a, const T* src, T* zacc, hipStream_t s)
 {
     if (a.nnear_units == 0) return true;
@@ -56,7 +56,7 @@ bool run_near_d(const DevPlan& a, const T* src, T* zacc, hipStream_t s)
     dim3 g(a.nnear_units), b(kWave);
     switch (a.kind) {
 #define FKT_NEAR_CASE(K) \
-    case K: hipLaunchKernelGGL((k_near<D, K, T>), g, b, 0, s, a, src, zacc, c0, c1, scale); return true;
+    case K: hipLaunchKernelGGL((k_near<D, K, T, NCOL>), g, b, 0, s, a, src, zacc, c0, c1, scale); return true;
         FKT_NEAR_CASE(FKT_GAUSSIAN)
         FKT_NEAR_CASE(FKT_EXPONENTIAL)
         FKT_NEAR_CASE(FKT_MATERN32)
@@ -69,16 +69,18 @@ bool run_near_d(const DevPlan& a, const T* src, T* zacc, hipStream_t s)
     }
 }
 
-// Stream layout of one column (overlap on):
+// Stream layout of one pass (overlap on):
 //   s:    gather (+ clear accumulators) -> fork -> s2m -> m2t -> wait join -> scatter
 //   side:                        wait fork -> near field -> join
 // Far and near fields both add into the accumulators, so they may run
 // concurrently. With overlap off every stage runs in order on s. Profiling
 // events (7, optional): e0 start, e1 after gather, e2 after s2m, e3 after
 // m2t, e4/e5 around the near field on its own stream, e6 after the scatter.
-template <typename T>
-hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int nrhs, int col, hipStream_t s,
-                      bool overlap, hipEvent_t* ev)
+// A pass covers columns col .. col + ncols - 1 with NC accumulators per
+// target (NC = 1 or kMvmCols; padded columns carry zero weights).
+template <typename T, int NC>
+hipError_t mvm_pass(const DevPlan& a, const DevWork& wk, const T* x, T* y, int nrhs, int col, int ncols,
+                    hipStream_t s, bool overlap, hipEvent_t* ev)
 {
     const T* pts = std::is_same<T, float>::value ? (const T*)a.pts32 : (const T*)a.pts64;
     T* src = (T*)wk.src;
@@ -88,9 +90,9 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
     auto mark = [&](int i, hipStream_t q) -> hipError_t { return ev ? hipEventRecord(ev[i], q) : hipSuccess; };
     if ((e = mark(0, s)) != hipSuccess) return e;
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, T>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
     default: return hipErrorInvalidValue;
     }
     if ((e = mark(1, s)) != hipSuccess) return e;
@@ -101,9 +103,9 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
         if ((r = mark(4, sn)) != hipSuccess) return r;
         bool ok = false;
         switch (a.d) {
-        case 3: ok = run_near_d<3, T>(a, src, zacc, sn); break;
-        case 4: ok = run_near_d<4, T>(a, src, zacc, sn); break;
-        case 5: ok = run_near_d<5, T>(a, src, zacc, sn); break;
+        case 3: ok = run_near_d<3, T, NC>(a, src, zacc, sn); break;
+        case 4: ok = run_near_d<4, T, NC>(a, src, zacc, sn); break;
+        case 5: ok = run_near_d<5, T, NC>(a, src, zacc, sn); break;
         default: break;
         }
         if (!ok) return hipErrorInvalidValue;
@@ -116,31 +118,31 @@ hipError_t mvm_column(const DevPlan& a, const DevWork& wk, const T* x, T* y, int
         if ((e = hipEventRecord(wk.join, wk.side)) != hipSuccess) return e;
     }
     const int prec = std::is_same<T, float>::value ? 1 : 0;
-    if (a.nslots > 0 && !launch_s2m(a, wk, prec, s)) return hipErrorInvalidValue;
+    if (a.nslots > 0 && !launch_s2m(a, wk, prec, s, NC)) return hipErrorInvalidValue;
     if ((e = mark(2, s)) != hipSuccess) return e;
-    if (a.nslots > 0 && !launch_m2t(a.kind, a, wk, prec, s)) return hipErrorInvalidValue;
+    if (a.nslots > 0 && !launch_m2t(a.kind, a, wk, prec, s, NC)) return hipErrorInvalidValue;
     if ((e = mark(3, s)) != hipSuccess) return e;
     if (overlap) {
         if ((e = hipStreamWaitEvent(s, wk.join, 0)) != hipSuccess) return e;
     } else if ((e = near()) != hipSuccess) {
         return e;
     }
-    hipLaunchKernelGGL((k_scatter<T>), gg, gb, 0, s, a.n, a.perm, (const T*)zacc, y, nrhs, col);
+    hipLaunchKernelGGL((k_scatter<T, NC>), gg, gb, 0, s, a.n, a.perm, (const T*)zacc, y, nrhs, col, ncols);
     if ((e = mark(6, s)) != hipSuccess) return e;
     return hipGetLastError();
 }
 
 }  // namespace
 
-bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s)
+bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc)
 {
     switch (a.d * 2 + (prec == 1 ? 1 : 0)) {
-    case 6: return launch_s2m_d3_p0(a, wk, s);
-    case 7: return launch_s2m_d3_p1(a, wk, s);
-    case 8: return launch_s2m_d4_p0(a, wk, s);
-    case 9: return launch_s2m_d4_p1(a, wk, s);
-    case 10: return launch_s2m_d5_p0(a, wk, s);
-    case 11: return launch_s2m_d5_p1(a, wk, s);
+    case 6: return launch_s2m_d3_p0(a, wk, s, nc);
+    case 7: return launch_s2m_d3_p1(a, wk, s, nc);
+    case 8: return launch_s2m_d4_p0(a, wk, s, nc);
+    case 9: return launch_s2m_d4_p1(a, wk, s, nc);
+    case 10: return launch_s2m_d5_p0(a, wk, s, nc);
+    case 11: return launch_s2m_d5_p1(a, wk, s, nc);
     default: return false;
     }
 }
@@ -156,9 +158,9 @@ hipError_t launch_s2m_column(const DevPlan& a, const DevWork& wk, const void* xv
     float* zacc = (float*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
     default: return hipErrorInvalidValue;
     }
     if (a.nslots > 0 && !launch_s2m(a, wk, 1, s)) return hipErrorInvalidValue;
@@ -174,9 +176,9 @@ hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* xv
     float* zacc = (float*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
     default: return hipErrorInvalidValue;
     }
     if (a.nslots > 0) {
@@ -198,11 +200,18 @@ int far_max_order(int d)
 
 bool far_supported(int d, int p) { return p >= 0 && p <= far_max_order(d); }
 
-hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col, int prec,
-                             hipStream_t s, bool overlap, hipEvent_t* ev)
+hipError_t launch_mvm_column(const DevPlan& a, const DevWork& wk, const void* x, void* y, int nrhs, int col,
+                             int ncols, int nc, int prec, hipStream_t s, bool overlap, hipEvent_t* ev)
 {
-    if (prec == 1) return mvm_column<float>(a, wk, (const float*)x, (float*)y, nrhs, col, s, overlap, ev);
-    return mvm_column<double>(a, wk, (const double*)x, (double*)y, nrhs, col, s, overlap, ev);
+    if (ncols < 1 || ncols > nc || nc > wk.ncmax || col < 0 || col + ncols > nrhs) return hipErrorInvalidValue;
+    if (nc == 1) {
+        if (prec == 1) return mvm_pass<float, 1>(a, wk, (const float*)x, (float*)y, nrhs, col, 1, s, overlap, ev);
+        return mvm_pass<double, 1>(a, wk, (const double*)x, (double*)y, nrhs, col, 1, s, overlap, ev);
+    }
+    if (nc != kMvmCols || (a.nslots > 0 && a.nnjobs <= 0)) return hipErrorInvalidValue;
+    if (prec == 1)
+        return mvm_pass<float, kMvmCols>(a, wk, (const float*)x, (float*)y, nrhs, col, ncols, s, overlap, ev);
+    return mvm_pass<double, kMvmCols>(a, wk, (const double*)x, (double*)y, nrhs, col, ncols, s, overlap, ev);
 }
 
 }  // namespace fkt

@@ -232,3 +232,104 @@ def test_pcg_block_jacobi_gp(F):
         xn = x.cpu().numpy()
         r = y - (oracle.fkt_alg1(T, xn, "matern52", 0.35, 6, lengthscale=0.3)[:, 0] + 1e-2 * xn)
         assert np.linalg.norm(r) / np.linalg.norm(y) < 1e-5
+
+
+COMPRESSED = [
+    # name, points, kind, kernel kwargs, leaf, p, theta, radial rank (compressed)
+    ("laplace_p6", lambda: W.uniform_cube(5000, 3, 32), "laplace", dict(), 64, 6, 0.5, 49),
+    ("laplace_p8", lambda: W.uniform_cube(4000, 3, 81), "laplace", dict(), 50, 8, 0.6, 81),
+    ("laplace_p0", lambda: W.uniform_cube(3000, 3, 82), "laplace", dict(), 64, 0, 0.4, 1),
+    ("laplace_p1_ragged", lambda: W.uniform_cube(1001, 3, 83), "laplace", dict(), 37, 1, 0.5, 4),
+    ("expo_p6", lambda: W.uniform_cube(4000, 3, 84), "exponential", dict(lengthscale=0.2), 64, 6, 0.5, 74),
+    ("expo_p8_short", lambda: W.gaussian_mixture(4000, 3, 6, 0.1, 85), "exponential", dict(lengthscale=0.05), 50, 8,
+     0.6, 130),
+]
+
+
+@pytest.mark.parametrize("case", COMPRESSED, ids=[c[0] for c in COMPRESSED])
+def test_compressed_matches_oracle_algorithm1(F, case):
+    """Radial compression (Appendix A.4) changes how the truncated expansion
+    is evaluated, not its value: the compressed FP64 MVM equals the oracle's
+    uncompressed Algorithm 1 to the FP64 bar; FP32 within FP32 rounding."""
+    name, gen, kind, kw, leaf, p, theta, rc = case
+    X = gen()
+    x = W.normal_rhs(X.shape[0], 1, 9)
+    z, plan = _gpu_mvm(F, X, x[:, 0], kind, leaf, p, theta, compress=True, **kw)
+    assert plan.info()["radial_rank"] == rc
+    T = oracle.Tree(X, leaf)
+    okind, okw = _oracle_kind(kind, kw)
+    zref = oracle.fkt_alg1(T, x, okind, theta, p, **okw)
+    _check(z, zref, 1e-10)
+    z32, _ = _gpu_mvm(F, X, x[:, 0], kind, leaf, p, theta, prec="f32", compress=True, **kw)
+    assert np.linalg.norm(z32 - z) / np.linalg.norm(z) < 2e-6
+
+
+def test_compressed_batch_plan(F):
+    """A batched plan with compression: every instance equals its own
+    uncompressed oracle MVM."""
+    sizes = [700, 1500, 64, 2300]
+    pts = [W.uniform_cube(m, 3, 90 + i) for i, m in enumerate(sizes)]
+    plan = F.fkt_plan_batch(pts, "laplace", 48, 6, theta=0.5, compress=True)
+    assert plan.info()["radial_rank"] == 49
+    x = W.normal_rhs(sum(sizes), 1, 95)[:, 0]
+    y = F.fkt_mvm(plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    o = 0
+    for X in pts:
+        m = X.shape[0]
+        zref = oracle.fkt_alg1(oracle.Tree(X, 48), x[o:o + m, None], "power", 0.5, 6, shape=1.0)
+        _check(y[o:o + m], zref, 1e-10)
+        o += m
+
+
+MULTI = [
+    # name, points, kind, kernel kwargs, leaf, p, theta, compress
+    ("matern32_d3", lambda: W.uniform_cube(4000, 3, 101), "matern32", dict(lengthscale=0.1), 64, 6, 0.5, False),
+    ("matern52_d4", lambda: W.gaussian_mixture(3000, 4, 8, 0.15, 102), "matern52", dict(lengthscale=0.3), 64, 5,
+     0.5, False),
+    ("gauss_d5", lambda: W.gaussian_mixture(2500, 5, 10, 0.1, 103), "gaussian", dict(lengthscale=0.2), 64, 4, 0.6,
+     False),
+    ("laplace_compressed", lambda: W.uniform_cube(3000, 3, 104), "laplace", dict(), 48, 6, 0.5, True),
+]
+
+
+@pytest.mark.parametrize("case", MULTI, ids=[c[0] for c in MULTI])
+def test_multi_column_passes_match_oracle(F, case):
+    """Several right-hand sides run kMvmCols = 4 columns per pass (kernel
+    values, harmonics and radial functions shared; three columns padded to
+    four, one or two column by column): every column equals the oracle's
+    Algorithm 1 for that column, for nrhs = 2, 3, 4, 5, 7 and 9."""
+    name, gen, kind, kw, leaf, p, theta, comp = case
+    X = gen()
+    T = oracle.Tree(X, leaf)
+    okind, okw = _oracle_kind(kind, kw)
+    x = W.normal_rhs(X.shape[0], 9, 105)
+    zref = oracle.fkt_alg1(T, x, okind, theta, p, **okw)
+    plan = F.fkt_plan(X, kind, leaf, p, theta=theta, compress=comp, **kw)
+    for nrhs in (2, 3, 4, 5, 7, 9):
+        xt = torch.as_tensor(np.ascontiguousarray(x[:, :nrhs]), device="cuda")
+        y = F.fkt_mvm(plan, xt).cpu().numpy().reshape(X.shape[0], nrhs)
+        for c in range(nrhs):
+            _check(y[:, c], zref[:, c], 1e-10)
+    plan.close()
+
+
+def test_multi_column_equals_single_columns(F):
+    """Eight columns in two 4-column passes equal eight one-column MVMs to
+    FP64 rounding (the passes only change the order of atomic additions),
+    in FP64 and FP32; a block-major plan (one column per pass) agrees too."""
+    X = W.uniform_cube(20000, 3, 106)
+    x = W.normal_rhs(20000, 8, 107)
+    for prec, tol in (("f64", 1e-13), ("f32", 2e-6)):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        plan = F.fkt_plan(X, "matern32", 128, 6, theta=0.4, prec=prec, lengthscale=0.05)
+        xt = torch.as_tensor(x, dtype=dt, device="cuda")
+        ym = F.fkt_mvm(plan, xt).double().cpu().numpy()
+        ys = np.stack([F.fkt_mvm(plan, xt[:, c].contiguous()).double().cpu().numpy() for c in range(8)], axis=1)
+        assert np.abs(ym - ys).max() <= tol * np.abs(ys).max()
+        if prec == "f64":
+            y64 = ym
+        plan.close()
+    plan = F.fkt_plan(X, "matern32", 128, 6, theta=0.4, lengthscale=0.05, far_mode="block")
+    yb = F.fkt_mvm(plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    assert np.abs(yb - y64).max() <= 1e-12 * np.abs(y64).max()
+    plan.close()

@@ -205,3 +205,48 @@ def test_batch_plan_rejects_bad_offsets():
         F.fkt_plan_batch((X, np.array([0, 6, 4, 10])), "gaussian", 8, 2, lengthscale=0.2, device=None)
     with pytest.raises(F.FktError):
         F.fkt_plan_batch((X, np.array([1, 10])), "gaussian", 8, 2, lengthscale=0.2, device=None)
+
+
+@pytest.mark.parametrize("kernel,kw,d", [("laplace", {}, 3), ("laplace", {}, 4), ("laplace", {}, 5),
+                                         ("exponential", dict(lengthscale=0.3), 3),
+                                         ("exponential", dict(lengthscale=0.3), 5),
+                                         ("gaussian", dict(lengthscale=0.3), 3)])
+def test_radial_compression_equals_oracle(kernel, kw, d):
+    """The library's ranks R_k (exact, modular) and interpolative
+    coefficients equal the oracle's exact-fraction ones (oracle/radial.py,
+    pinned by the paper's Table "ranks" and e^-r decomposition), p = 0..8."""
+    from oracle import radial as R
+    q = R.LAURENT_Q[{"laplace": "power1", "exponential": "exponential", "gaussian": "gaussian"}[kernel]]
+    for p in range(9):
+        rk, keep, coef = F.fkt_radial_compression(kernel, d, p, **kw)
+        assert rk == R.ranks(q, d, p), (p, rk)
+        built = {("laplace", 3): 1, ("exponential", 3): 2}.get((kernel, d), 0)
+        assert keep == built
+        if keep:
+            for k in range(p + 1):
+                n = min(keep, (p - k) // 2 + 1)
+                c = R.interpolative(q, d, k, p, n)
+                for jj, row in enumerate(c):
+                    for i, v in enumerate(row):
+                        assert coef[k, jj, i] == pytest.approx(float(v), rel=1e-15, abs=1e-300), (p, k, jj, i)
+        else:
+            assert coef is None
+
+
+def test_radial_compression_plan_rank_and_rejections():
+    X = W.uniform_cube(3000, 3, 5)
+    for kernel, kw, want in [("laplace", {}, 49), ("exponential", dict(lengthscale=0.2), 74),
+                             ("gaussian", dict(lengthscale=0.2), 84)]:
+        pl = F.fkt_plan(X, kernel, 64, 6, theta=0.5, device=None, compress=True, **kw)
+        i = pl.info()
+        assert i["rank"] == 84 and i["radial_rank"] == want, (kernel, i["radial_rank"])
+        pl.close()
+    pl = F.fkt_plan(X, "laplace", 64, 6, theta=0.5, device=None)
+    assert pl.info()["radial_rank"] == 84
+    pl.close()
+    with pytest.raises(F.FktError, match="FKT_EINVAL"):
+        F.fkt_plan(X, "matern32", 64, 6, theta=0.5, device=None, compress=True, lengthscale=0.2)
+    with pytest.raises(F.FktError, match="FKT_EUNSUPPORTED"):
+        F.fkt_plan(X, "laplace", 64, 6, theta=0.5, device=None, compress=True, far_mode="block")
+    with pytest.raises(F.FktError, match="FKT_EINVAL"):
+        F.fkt_radial_compression("matern52", 3, 6, lengthscale=0.2)
