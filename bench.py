@@ -207,7 +207,7 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
     tune = None
     if leaf <= 0:
         t0 = time.perf_counter()
-        leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [64, 128, 256, 512], nrhs=spec["nrhs"],
+        leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [128, 256, 512, 1024], nrhs=spec["nrhs"],
                                          reps=2, theta=theta, prec="f32", batch=True, **kw)
         tune_s = time.perf_counter() - t0
         print(f"bench: batch autotune {tune} -> leaf {leaf} ({tune_s:.1f} s)", file=sys.stderr, flush=True)

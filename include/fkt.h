@@ -114,10 +114,16 @@ typedef struct {
                            FKT_EUNSUPPORTED). Elsewhere the plan is the
                            uncompressed one. The result is the same
                            truncated expansion up to rounding. 0: off.      */
+    int fuse;           /* 1: the near and far field of each MVM pass run as
+                           one persistent launch over a global work queue
+                           (far jobs and near units interleaved, one atomic
+                           per item; needs the node-major far field and no
+                           compression, else FKT_EUNSUPPORTED). 0 (default):
+                           separate launches on two streams.               */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
- * overlap 1, mrhs 0, far_mode 0, compress 0. */
+ * overlap 1, mrhs 0, far_mode 0, compress 0, fuse 0. */
 void fkt_default_options(fkt_options *opt);
 
 /*

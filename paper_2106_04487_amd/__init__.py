@@ -64,7 +64,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("prec", ctypes.c_int), ("max_depth", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
                 ("overlap", ctypes.c_int), ("mrhs", ctypes.c_int), ("far_mode", ctypes.c_int),
-                ("compress", ctypes.c_int)]
+                ("compress", ctypes.c_int), ("fuse", ctypes.c_int)]
 
 
 _STAT_FIELDS = ["n", "nnodes", "nleaves", "depth", "rank", "nblocks", "far_nodes", "near_entries", "far_entries",
@@ -229,7 +229,8 @@ class Plan:
 FAR_MODES = {"auto": 0, "block": 1, "node": 2}
 
 
-def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode="auto", compress=False):
+def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode="auto", compress=False,
+             fuse=False):
     opt = _Options()
     _lib.fkt_default_options(ctypes.byref(opt))
     opt.theta = float(theta)
@@ -242,6 +243,7 @@ def _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
     opt.far_mode = FAR_MODES[far_mode]
     opt.compress = int(bool(compress))
+    opt.fuse = int(bool(fuse))
     return opt
 
 
@@ -268,11 +270,12 @@ def _batch_points(points):
 def fkt_plan_batch(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
                    variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
                    device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-                   mrhs: str | None = None, far_mode: str = "auto", compress: bool = False) -> Plan:
+                   mrhs: str | None = None, far_mode: str = "auto", compress: bool = False,
+                   fuse: bool = False) -> Plan:
     """One plan over independent point sets: points is a list of (n_i, d)
     arrays or (X, offsets). fkt_mvm then takes the concatenated rows."""
     X, off = _batch_points(points)
-    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode, compress)
+    opt = _options(theta, prec, max_depth, device, stream, profile, overlap, mrhs, far_mode, compress, fuse)
     h = _P()
     _check(_lib.fkt_plan_batch(X.ctypes.data, off.ctypes.data, len(off) - 1, X.shape[1],
                                _kernel(kernel, lengthscale, alpha, variance), int(leaf_size), int(order),
@@ -332,7 +335,8 @@ def fkt_autotune_leaf(points, kernel: str, order: int, candidates, *, nrhs: int 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,
              variance: float = 1.0, theta: float = 0.5, prec: str = "f64", max_depth: int = 48,
              device: int | None = 0, stream=None, profile: bool = False, overlap: bool = True,
-             mrhs: str | None = None, far_mode: str = "auto", compress: bool = False) -> Plan:
+             mrhs: str | None = None, far_mode: str = "auto", compress: bool = False,
+             fuse: bool = False) -> Plan:
     """Build a plan. points: (n, d) array-like (host or device; copied to host
     FP64 for the tree build). device=None builds a host-only plan. overlap
     runs the near field on a second stream beside the far field. mrhs ("f32"
@@ -340,7 +344,8 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     sides on the matrix cores. far_mode: "block" (target-block jobs, moments
     in LDS), "node" (one far node per wave, scalar moments, atomics) or
     "auto". compress: radial compression (exponential, Laplace, Gaussian;
-    info()["radial_rank"] gives the terms per node evaluated)."""
+    info()["radial_rank"] gives the terms per node evaluated). fuse: near
+    and far field in one persistent launch."""
     if hasattr(points, "detach"):
         points = points.detach().to("cpu").double().numpy()
     pts = np.ascontiguousarray(points, dtype=np.float64)
@@ -365,6 +370,7 @@ def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: fl
     opt.mrhs = {None: 0, "f32": 1, "bf16": 2}[mrhs]
     opt.far_mode = FAR_MODES[far_mode]
     opt.compress = int(bool(compress))
+    opt.fuse = int(bool(fuse))
     h = _P()
     _check(_lib.fkt_plan(pts.ctypes.data, n, d, k, int(leaf_size), int(order), ctypes.byref(opt), ctypes.byref(h)))
     return Plan(h, n, d, prec, device, sh)

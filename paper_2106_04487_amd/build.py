@@ -53,6 +53,10 @@ def _jobs():
     for kind in range(7):
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "stage_m2t.hip"),
                      "-o", os.path.join(BUILD, f"stage_m2t_{kind}.o")])
+    # persistent near + far field launches, one object per kernel kind
+    for kind in range(7):
+        jobs.append([*dev, f"-DFKT_FUSED_KIND={kind}", "-c", os.path.join(CSRC, "stage_fused.hip"),
+                     "-o", os.path.join(BUILD, f"stage_fused_{kind}.o")])
     # many-RHS source-to-multipole on the matrix cores, one object per dimension
     for d in (3, 4, 5):
         jobs.append([*dev, f"-DFKT_S2M_D={d}", "-c", os.path.join(CSRC, "s2m_mrhs.hip"),
@@ -62,7 +66,8 @@ def _jobs():
         jobs.append([*dev, f"-DFKT_M2T_KIND={kind}", "-c", os.path.join(CSRC, "m2t_mrhs.hip"),
                      "-o", os.path.join(BUILD, f"m2t_mrhs_{kind}.o")])
     # longest compiles first (the high-order d = 5 moment kernels)
-    jobs.sort(key=lambda j: 0 if ("-DFKT_S2M_D=5" in j or any("m2t_mrhs" in a for a in j)) else 1)
+    jobs.sort(key=lambda j: 0 if ("-DFKT_S2M_D=5" in j or any(("m2t" in a or "fused" in a) and a.endswith(".hip")
+                                                                for a in j)) else 1)
     return jobs
 
 

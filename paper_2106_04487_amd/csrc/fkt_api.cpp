@@ -178,6 +178,7 @@ void fkt_default_options(fkt_options* opt)
     opt->mrhs = 0;
     opt->far_mode = 0;
     opt->compress = 0;
+    opt->fuse = 0;
 }
 
 const char* fkt_last_error(void) { return g_err.c_str(); }
@@ -251,7 +252,7 @@ static fkt_status upload_plan(fkt_plan_t P)
     {
         // node-major far jobs (far_mode 2; far_mode 0 except FP32 plans of
         // rank above 200, where the block-major kernel was measured faster)
-        const bool node_major = P->opt.far_mode == 2 || P->comp_keep > 0 ||
+        const bool node_major = P->opt.far_mode == 2 || P->comp_keep > 0 || P->opt.fuse != 0 ||
                                 (P->opt.far_mode == 0 && !(P->opt.prec == FKT_F32 && P->tab.rank > 200));
         a.nnjobs = 0;
         a.nj_slot = nullptr;
@@ -312,6 +313,12 @@ static fkt_status upload_plan(fkt_plan_t P)
     if (P->comp_keep > 0 &&
         (e = P->alloc(es * L.slot_node.size() * (size_t)P->st.radial_rank * nc, &P->wk.momc)) != hipSuccess)
         return hip_fail(e, "compressed-moment buffer");
+    P->wk.qctr = nullptr;
+    a.fused = 0;
+    if (P->opt.fuse) {
+        if ((e = P->alloc(sizeof(unsigned), (void**)&P->wk.qctr)) != hipSuccess) return hip_fail(e, "queue counter");
+        a.fused = 1;
+    }
     P->wk.mom_cols = L.slot_node.size() * (size_t)P->tab.rank;
     P->wk.part_cols = (size_t)L.npartials * (size_t)P->tab.rank;
     P->wk.momc_cols = P->comp_keep > 0 ? L.slot_node.size() * (size_t)P->st.radial_rank : 0;
@@ -426,6 +433,10 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
     if (opt.compress && opt.mrhs != 0) return fail(FKT_EUNSUPPORTED, "radial compression with mrhs is not built");
     if (opt.compress && opt.far_mode == 1)
         return fail(FKT_EUNSUPPORTED, "radial compression runs the node-major far field (far_mode 0 or 2)");
+    if (opt.fuse != 0 && opt.fuse != 1) return fail(FKT_EINVAL, "fuse must be 0 or 1");
+    if (opt.fuse && (opt.compress || opt.far_mode == 1))
+        return fail(FKT_EUNSUPPORTED, "the persistent launch runs the uncompressed node-major far field "
+                                      "(compress 0, far_mode 0 or 2)");
     if (opt.max_depth < 1 || opt.max_depth > 60) return fail(FKT_EINVAL, "max_depth must be in [1, 60]");
     if (opt.device < -1) return fail(FKT_EINVAL, "device must be >= -1");
     fkt_status s = check_kernel(k);

@@ -46,6 +46,7 @@ struct DevPlan {
     // radial compression (Appendix A.4): comp_keep > 0 keeps the first
     // min(comp_keep, nj) radial rows of every degree; the moments are
     // combined into them with comp_coef (see radial_keep, k_compress)
+    int fused;                    // near and far field in one persistent launch (k_fused)
     int comp_keep;
     int comp_rank;                // moments per node after compression
     double comp_invlen;           // 1 / l of the scaled distance (1 for 1/r)
@@ -76,6 +77,7 @@ struct DevWork {
     // ncmax blocks ([column][slot or partial][entry]) of these sizes:
     int ncmax;
     size_t mom_cols, part_cols, momc_cols;  // elements per column block
+    unsigned* qctr;  // work-queue counter of the persistent launch (fused plans)
     hipStream_t side;    // second stream: the near field runs beside the far field
     hipEvent_t fork, join;
 };

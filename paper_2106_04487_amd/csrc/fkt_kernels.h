@@ -401,10 +401,12 @@ constexpr int src_stride(int d, int nc = 1) { return (d + nc + 1) & ~1; }
 template <int D, typename T, int NC = 1>
 __global__ __launch_bounds__(256) void k_gather(int n, const int64_t* __restrict__ perm, const T* __restrict__ pts,
                                                 const T* __restrict__ x, int nrhs, int col, int ncols,
-                                                T* __restrict__ src, T* __restrict__ zacc)
+                                                T* __restrict__ src, T* __restrict__ zacc,
+                                                unsigned* __restrict__ ctr = nullptr)
 {
     constexpr int S = src_stride(D, NC);
     const int i = blockIdx.x * 256 + threadIdx.x;
+    if (ctr && i == 0) *ctr = 0u;  // work-queue counter of the pass's persistent launch
     if (i >= n) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) zacc[(size_t)i * NC + c] = T(0);
@@ -691,13 +693,12 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
 // concurrently, adds to the same accumulators). Four jobs per workgroup.
 // With NCOL columns, column c's moments are the block mom + c * cs and the
 // accumulators are [n][NCOL].
-template <int D, int P, int KIND, typename T, int KEEP = 0, int NCOL = 1>
-__global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __restrict__ mom, size_t cs,
-                                                   T* __restrict__ zacc)
+// one node-major job j (wave-uniform) of 64 lanes
+template <int D, int P, int KIND, typename T, int KEEP, int NCOL>
+__device__ __forceinline__ void m2t_node_job(const DevPlan& a, int j, const T* __restrict__ mom, size_t cs,
+                                             T* __restrict__ zacc)
 {
     constexpr int R = crank(D, P, KEEP);
-    const int j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    if (j >= a.nnjobs) return;
     const int lane = threadIdx.x & 63;
     const int slot = a.nj_slot[j];
     const int t = a.nj_tgt[(size_t)j * kWave + lane];
@@ -711,6 +712,15 @@ __global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __r
 #pragma unroll
         for (int c = 0; c < NCOL; ++c) unsafeAtomicAdd(zacc + (size_t)t * NCOL + c, T(acc[c]));
     }
+}
+
+template <int D, int P, int KIND, typename T, int KEEP = 0, int NCOL = 1>
+__global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __restrict__ mom, size_t cs,
+                                                   T* __restrict__ zacc)
+{
+    const int j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (j >= a.nnjobs) return;
+    m2t_node_job<D, P, KIND, T, KEEP, NCOL>(a, j, mom, cs, zacc);
 }
 
 // Radial compression of the moments (Appendix A.4, eq. f_g): for every far
@@ -893,29 +903,17 @@ template <> struct NearKernel<FKT_LAPLACE, float> {
     }
 };
 
-// Source-major near field: one wave per work unit (a source leaf l and up to
-// kNearUnitTargets targets of N_l, 64 at a time, one per lane). The leaf's
-// points stream through scalar registers; each target's sum is added to its
-// accumulator with one FP64/FP32 atomic per (target, leaf), so no lane ever
-// idles on a target whose own walk does not reach l.
-// With NCOL columns each kernel value multiplies NCOL weights.
-template <int D, int KIND, typename T, int NCOL = 1>
-__global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, T* __restrict__ zacc,
-                                                T c0, T c1, T scale)
+// One near unit u (wave-uniform): a source leaf and up to kNearUnitTargets
+// of its targets, 64 at a time. With NCOL columns each kernel value
+// multiplies NCOL weights. tab: the exponential table in LDS (FP64 kernels
+// that use it).
+template <int D, int KIND, typename T, int NCOL>
+__device__ __forceinline__ void near_unit(const DevPlan& a, int u, const T* __restrict__ src, T* __restrict__ zacc,
+                                          T c0, T c1, T scale, const double* tab)
 {
     constexpr int S = src_stride(D, NCOL);
     using NK = NearKernel<KIND, T>;
-    __shared__ double tab[NK::kTable ? kExpTabLen : 1];
-    const int u = blockIdx.x;
-    const int lane = threadIdx.x;
-    if constexpr (NK::kTable) {
-        double tv[kExpTabLen / kWave];
-#pragma unroll
-        for (int j = 0; j < kExpTabLen / kWave; ++j) tv[j] = a.exp2tab[j * kWave + lane];
-#pragma unroll
-        for (int j = 0; j < kExpTabLen / kWave; ++j) tab[j * kWave + lane] = tv[j];
-        __syncthreads();
-    }
+    const int lane = threadIdx.x & 63;
     const int s0 = a.nu_beg[u], m = a.nu_end[u] - s0;
     const int toff = a.nu_toff[u], tcnt = a.nu_tcnt[u];
     const T* __restrict__ q = src + (size_t)s0 * S;
@@ -970,6 +968,79 @@ __global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __rest
     }
 }
 
+// Source-major near field: one wave per work unit (a source leaf l and up to
+// kNearUnitTargets targets of N_l, 64 at a time, one per lane). The leaf's
+// points stream through scalar registers; each target's sum is added to its
+// accumulator with one FP64/FP32 atomic per (target, leaf), so no lane ever
+// idles on a target whose own walk does not reach l.
+template <int D, int KIND, typename T, int NCOL = 1>
+__global__ __launch_bounds__(kWave) void k_near(const DevPlan a, const T* __restrict__ src, T* __restrict__ zacc,
+                                                T c0, T c1, T scale)
+{
+    using NK = NearKernel<KIND, T>;
+    __shared__ double tab[NK::kTable ? kExpTabLen : 1];
+    const int lane = threadIdx.x;
+    if constexpr (NK::kTable) {
+        double tv[kExpTabLen / kWave];
+#pragma unroll
+        for (int j = 0; j < kExpTabLen / kWave; ++j) tv[j] = a.exp2tab[j * kWave + lane];
+#pragma unroll
+        for (int j = 0; j < kExpTabLen / kWave; ++j) tab[j * kWave + lane] = tv[j];
+        __syncthreads();
+    }
+    near_unit<D, KIND, T, NCOL>(a, blockIdx.x, src, zacc, c0, c1, scale, tab);
+}
+
+// Near and far field in one persistent launch over a global work queue
+// (the accumulators and moments are those of the pass; the counter is
+// cleared by the gather kernel). Every wave takes the next item with one
+// atomic: items alternate between a chunk of kFusedJobs node-major far jobs
+// and one near unit while both remain, so each SIMD holds waves of both
+// kinds (the far jobs are heavy in scalar instructions, the near units in
+// vector ones, and the two issue side by side); a wave exits when the queue
+// is empty, so every wave reaches the end.
+constexpr int kFusedJobs = 8;
+
+template <int D, int P, int KIND, typename T, int NCOL>
+__global__ __launch_bounds__(256) void k_fused(const DevPlan a, const T* __restrict__ src, const T* __restrict__ mom,
+                                               size_t cs, T* __restrict__ zacc, unsigned* __restrict__ ctr, T c0,
+                                               T c1, T scale)
+{
+    using NK = NearKernel<KIND, T>;
+    __shared__ double tab[NK::kTable ? kExpTabLen : 1];
+    if constexpr (NK::kTable) {
+        for (int j = threadIdx.x; j < kExpTabLen; j += blockDim.x) tab[j] = a.exp2tab[j];
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int nm = (a.nnjobs + kFusedJobs - 1) / kFusedJobs;
+    const int nu = a.nnear_units;
+    const int both = nm < nu ? nm : nu;
+    const int total = nm + nu;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = (int)atomicAdd(ctr, 1u);
+        item = __builtin_amdgcn_readlane(item, 0);
+        if (item >= total) break;
+        bool far;
+        int idx;
+        if (item < 2 * both) {
+            far = (item & 1) == 0;
+            idx = item >> 1;
+        } else {
+            far = nm > nu;
+            idx = both + (item - 2 * both);
+        }
+        if (far) {
+            const int j1 = min(a.nnjobs, (idx + 1) * kFusedJobs);
+#pragma unroll 1
+            for (int j = idx * kFusedJobs; j < j1; ++j) m2t_node_job<D, P, KIND, T, 0, NCOL>(a, j, mom, cs, zacc);
+        } else {
+            near_unit<D, KIND, T, NCOL>(a, idx, src, zacc, c0, c1, scale, tab);
+        }
+    }
+}
+
 // y (caller order, columns col .. col + ncols - 1) <- zacc (tree order, [n][NC])
 template <typename T, int NC = 1>
 __global__ __launch_bounds__(256) void k_scatter(int n, const int64_t* __restrict__ perm, const T* __restrict__ zacc,
@@ -1017,6 +1088,21 @@ FKT_DECLARE_S2M(5, 0)
 FKT_DECLARE_S2M(5, 1)
 #undef FKT_DECLARE_S2M
 bool launch_m2t(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc = 1);
+// near and far field in one persistent launch (k_fused); c0, c1, scale: the
+// near-kernel constants in the pass's precision (as doubles)
+bool launch_fused(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc, double c0,
+                  double c1, double scale);
+#define FKT_DECLARE_FUSED(K)                                                                                      \
+    bool launch_fused_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc, double c0, \
+                              double c1, double scale);
+FKT_DECLARE_FUSED(0)
+FKT_DECLARE_FUSED(1)
+FKT_DECLARE_FUSED(2)
+FKT_DECLARE_FUSED(3)
+FKT_DECLARE_FUSED(4)
+FKT_DECLARE_FUSED(5)
+FKT_DECLARE_FUSED(6)
+#undef FKT_DECLARE_FUSED
 #define FKT_DECLARE_M2T(K) \
     bool launch_m2t_kind##K(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc);
 FKT_DECLARE_M2T(0)

@@ -85,17 +85,34 @@ hipError_t mvm_pass(const DevPlan& a, const DevWork& wk, const T* x, T* y, int n
     const T* pts = std::is_same<T, float>::value ? (const T*)a.pts32 : (const T*)a.pts64;
     T* src = (T*)wk.src;
     T* zacc = (T*)wk.zacc;
+    unsigned* ctr = a.fused ? wk.qctr : nullptr;
     const dim3 gg((a.n + 255) / 256), gb(256);
     hipError_t e;
     auto mark = [&](int i, hipStream_t q) -> hipError_t { return ev ? hipEventRecord(ev[i], q) : hipSuccess; };
     if ((e = mark(0, s)) != hipSuccess) return e;
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc, ctr); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc, ctr); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, T, NC>), gg, gb, 0, s, a.n, a.perm, pts, x, nrhs, col, ncols, src, zacc, ctr); break;
     default: return hipErrorInvalidValue;
     }
     if ((e = mark(1, s)) != hipSuccess) return e;
+    const int prec = std::is_same<T, float>::value ? 1 : 0;
+    if (a.fused) {
+        // s2m, then near and far field in one persistent launch; events e4/e5
+        // bracket the persistent launch like e2/e3
+        if (a.nslots > 0 && !launch_s2m(a, wk, prec, s, NC)) return hipErrorInvalidValue;
+        if ((e = mark(2, s)) != hipSuccess) return e;
+        if ((e = mark(4, s)) != hipSuccess) return e;
+        T c0, c1;
+        near_consts<T>(a, c0, c1);
+        if (!launch_fused(a.kind, a, wk, prec, s, NC, (double)c0, (double)c1, a.var)) return hipErrorInvalidValue;
+        if ((e = mark(3, s)) != hipSuccess) return e;
+        if ((e = mark(5, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_scatter<T, NC>), gg, gb, 0, s, a.n, a.perm, (const T*)zacc, y, nrhs, col, ncols);
+        if ((e = mark(6, s)) != hipSuccess) return e;
+        return hipGetLastError();
+    }
     overlap = overlap && wk.side != nullptr;
     const hipStream_t sn = overlap ? wk.side : s;
     auto near = [&]() -> hipError_t {
@@ -117,7 +134,6 @@ hipError_t mvm_pass(const DevPlan& a, const DevWork& wk, const T* x, T* y, int n
         if ((e = near()) != hipSuccess) return e;
         if ((e = hipEventRecord(wk.join, wk.side)) != hipSuccess) return e;
     }
-    const int prec = std::is_same<T, float>::value ? 1 : 0;
     if (a.nslots > 0 && !launch_s2m(a, wk, prec, s, NC)) return hipErrorInvalidValue;
     if ((e = mark(2, s)) != hipSuccess) return e;
     if (a.nslots > 0 && !launch_m2t(a.kind, a, wk, prec, s, NC)) return hipErrorInvalidValue;
@@ -133,6 +149,21 @@ hipError_t mvm_pass(const DevPlan& a, const DevWork& wk, const T* x, T* y, int n
 }
 
 }  // namespace
+
+bool launch_fused(int kind, const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc, double c0,
+                  double c1, double scale)
+{
+    switch (kind) {
+    case 0: return launch_fused_kind0(a, wk, prec, s, nc, c0, c1, scale);
+    case 1: return launch_fused_kind1(a, wk, prec, s, nc, c0, c1, scale);
+    case 2: return launch_fused_kind2(a, wk, prec, s, nc, c0, c1, scale);
+    case 3: return launch_fused_kind3(a, wk, prec, s, nc, c0, c1, scale);
+    case 4: return launch_fused_kind4(a, wk, prec, s, nc, c0, c1, scale);
+    case 5: return launch_fused_kind5(a, wk, prec, s, nc, c0, c1, scale);
+    case 6: return launch_fused_kind6(a, wk, prec, s, nc, c0, c1, scale);
+    default: return false;
+    }
+}
 
 bool launch_s2m(const DevPlan& a, const DevWork& wk, int prec, hipStream_t s, int nc)
 {
@@ -158,9 +189,9 @@ hipError_t launch_s2m_column(const DevPlan& a, const DevWork& wk, const void* xv
     float* zacc = (float*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
     default: return hipErrorInvalidValue;
     }
     if (a.nslots > 0 && !launch_s2m(a, wk, 1, s)) return hipErrorInvalidValue;
@@ -176,9 +207,9 @@ hipError_t launch_far_column(const DevPlan& a, const DevWork& wk, const void* xv
     float* zacc = (float*)wk.zacc;
     const dim3 gg((a.n + 255) / 256), gb(256);
     switch (a.d) {
-    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
-    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
-    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc); break;
+    case 3: hipLaunchKernelGGL((k_gather<3, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
+    case 4: hipLaunchKernelGGL((k_gather<4, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
+    case 5: hipLaunchKernelGGL((k_gather<5, float>), gg, gb, 0, s, a.n, a.perm, a.pts32, x, nrhs, col, 1, src, zacc, nullptr); break;
     default: return hipErrorInvalidValue;
     }
     if (a.nslots > 0) {

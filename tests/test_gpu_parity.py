@@ -333,3 +333,48 @@ def test_multi_column_equals_single_columns(F):
     yb = F.fkt_mvm(plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
     assert np.abs(yb - y64).max() <= 1e-12 * np.abs(y64).max()
     plan.close()
+
+
+@pytest.mark.parametrize("case", [SMALL[3], SMALL[10], SMALL[16]], ids=[SMALL[i][0] for i in (3, 10, 16)])
+def test_fused_persistent_launch_matches_oracle(F, case):
+    """fuse=True (near and far field in one persistent launch over a global
+    work queue) gives the oracle's Algorithm 1, one and several columns."""
+    name, gen, nrhs, kind, kw, leaf, p, theta = case
+    X = gen()
+    x = W.normal_rhs(X.shape[0], 5, 7)
+    T = oracle.Tree(X, leaf)
+    okind, okw = _oracle_kind(kind, kw)
+    zref = oracle.fkt_alg1(T, x, okind, theta, p, **okw)
+    plan = F.fkt_plan(X, kind, leaf, p, theta=theta, fuse=True, **kw)
+    y1 = F.fkt_mvm(plan, torch.as_tensor(x[:, 0], device="cuda")).cpu().numpy()
+    _check(y1, zref[:, 0], 1e-10)
+    y5 = F.fkt_mvm(plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    for c in range(5):
+        _check(y5[:, c], zref[:, c], 1e-10)
+    plan.close()
+
+
+def test_fused_batch_plan_graph(F):
+    """A batched plan with the persistent launch, captured in a graph and
+    replayed three times, equals its eager MVM (to FP64 rounding)."""
+    sizes = [900, 2500, 130, 1700]
+    pts = [W.uniform_cube(m, 3, 120 + i) for i, m in enumerate(sizes)]
+    plan = F.fkt_plan_batch(pts, "ratquad", 64, 6, theta=0.4, fuse=True, lengthscale=0.2, alpha=1.5)
+    x = torch.as_tensor(W.normal_rhs(sum(sizes), 4, 125), device="cuda")
+    y = torch.empty_like(x)
+    ye = F.fkt_mvm(plan, x).cpu().numpy()
+    g = F.Graph(plan, x, y)
+    for _ in range(3):
+        y.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.abs(y.cpu().numpy() - ye).max() <= 1e-12 * np.abs(ye).max()
+    g.close()
+    o = 0
+    for X in pts:
+        m = X.shape[0]
+        zref = oracle.fkt_alg1(oracle.Tree(X, 64), x.cpu().numpy()[o:o + m], "ratquad", 0.4, 6, lengthscale=0.2,
+                               shape=1.5)
+        _check(ye[o:o + m], zref, 1e-10)
+        o += m
+    plan.close()
