@@ -271,9 +271,20 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
                     out[(size_t)g * nrhs + c2] += hpart[((size_t)g * bps + k) * nrhs + c2];
         return true;
     };
-    auto apply = [&](const double* in, double* out) -> fkt_status {
+    // masked: skip the operator work of instances whose systems have all
+    // converged (their step length is 0, so their rows of the product are
+    // not used); the flags are copied to the plan's buffer first
+    std::vector<unsigned char> hact(v.active ? nseg : 0);
+    auto apply = [&](const double* in, double* out, bool masked = false) -> fkt_status {
         hipLaunchKernelGGL((k_from_f64<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, in, op_in);
-        fkt_status st = fkt_mvm(P, op_in, op_out, nrhs);
+        fkt_status st;
+        if (masked && v.active) {
+            if (hipMemcpyAsync(v.active, hact.data(), hact.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+                return cg_set_error(FKT_EDEVICE, "cg copy");
+            st = mvm_masked(P, op_in, op_out, nrhs);
+        } else {
+            st = fkt_mvm(P, op_in, op_out, nrhs);
+        }
         if (st != FKT_OK) return st;
         hipLaunchKernelGGL((k_add_shift<T>), dim3(grid_of(m)), dim3(kThreads), 0, s, m, op_out, in, sigma2, out);
         return FKT_OK;
@@ -365,7 +376,11 @@ static fkt_status cg_typed(fkt_plan_t P, const CgPlanView& v, double sigma2, con
             res_replaced = res;
             continue;
         }
-        st = apply(p, q);
+        for (int g = 0; g < (int)hact.size(); ++g) {
+            hact[g] = 0;
+            for (int c2 = 0; c2 < nrhs; ++c2) hact[g] |= relres_of(rr, g * nrhs + c2) > rtol ? 1 : 0;
+        }
+        st = apply(p, q, true);
         if (st != FKT_OK) return st;
         if (!dots(p, q, pq)) return cg_set_error(FKT_EDEVICE, "cg reduction");
         // coef = [alpha | -alpha | beta]; host slots are rewritten only after

@@ -119,6 +119,7 @@ struct fkt_plan_s {
     // (0: off) and the interpolative coefficients
     int comp_keep = 0;
     std::vector<double> comp_coef;
+    unsigned char* inst_active = nullptr;  // device [ninst] flags (batched plans)
 
     void drop_events()
     {
@@ -237,6 +238,22 @@ static fkt_status upload_plan(fkt_plan_t P)
                 std::fill(rs.begin() + T.inst_begin[i], rs.begin() + T.inst_begin[i + 1], (int32_t)i);
             FKT_UP(rs, P->cg_row_seg);
         }
+    }
+    a.slot_inst = nullptr;
+    a.nu_inst = nullptr;
+    a.inst_active = nullptr;
+    if (T.inst_begin.size() > 2) {
+        // instance of a point range's first point
+        auto inst_of = [&](int64_t pos) {
+            return (int32_t)(std::upper_bound(T.inst_begin.begin(), T.inst_begin.end(), pos) - T.inst_begin.begin() - 1);
+        };
+        std::vector<int32_t> si(L.slot_node.size()), ni(L.nu_beg.size());
+        for (size_t k = 0; k < si.size(); ++k) si[k] = inst_of(T.begin[L.slot_node[k]]);
+        for (size_t k = 0; k < ni.size(); ++k) ni[k] = inst_of(L.nu_beg[k]);
+        FKT_UP(si, a.slot_inst);
+        FKT_UP(ni, a.nu_inst);
+        if ((e = P->alloc(T.inst_begin.size() - 1, (void**)&P->inst_active)) != hipSuccess)
+            return hip_fail(e, "instance flags");
     }
     FKT_UP(L.blk_begin, a.blk_begin);
     FKT_UP(L.blk_count, a.blk_count);
@@ -912,6 +929,7 @@ static fkt_status cg_entry(fkt_plan_t P, double sigma2, const void* b, void* x, 
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
                       P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
     v.coarse = two_level ? 1 : 0;
+    v.active = P->inst_active;
     return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, fallback_at, io64, P64,
                               v64, replaced);
 }
@@ -965,6 +983,7 @@ fkt_status fkt_cg_solve_noalloc(fkt_plan_t P, double sigma2, const void* b, void
                       P->bj_maxleaf, P->bj_begin,       P->bj_count,  P->bj_off,    P->bj_inv,    P->learn,
                       P->cg_nseg,    P->cg_seg_off,     P->cg_row_seg};
     v.coarse = two_level ? 1 : 0;
+    v.active = P->inst_active;
     return fkt::cg_solve_impl(P, v, sigma2, b, x, nrhs, rtol, maxit, precond, iters, relres, &P->st.cg_fallback_iter,
                               false, nullptr, nullptr, nullptr, region, cap);
 }
@@ -1258,3 +1277,13 @@ fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int n
 }
 
 }  // extern "C"
+
+namespace fkt {
+fkt_status mvm_masked(fkt_plan_t P, const void* x, void* y, int nrhs)
+{
+    P->dp.inst_active = P->inst_active;
+    const fkt_status st = fkt_mvm(P, x, y, nrhs);
+    P->dp.inst_active = nullptr;
+    return st;
+}
+}  // namespace fkt

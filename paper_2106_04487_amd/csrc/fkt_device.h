@@ -47,6 +47,13 @@ struct DevPlan {
     // min(comp_keep, nj) radial rows of every degree; the moments are
     // combined into them with comp_coef (see radial_keep, k_compress)
     int fused;                    // near and far field in one persistent launch (k_fused)
+    // batched plans: instance of every far-node slot and near unit, and (set
+    // only for the operator applications of a solve) one flag per instance:
+    // work of an instance whose flag is 0 is skipped (its output rows are
+    // then not computed)
+    const int* slot_inst;
+    const int* nu_inst;
+    const unsigned char* inst_active;
     int comp_keep;
     int comp_rank;                // moments per node after compression
     double comp_invlen;           // 1 / l of the scaled distance (1 for 1/r)
@@ -120,7 +127,13 @@ struct CgPlanView {
     const int64_t* seg_off;  // device [nseg + 1]: instance rows [seg_off[i], seg_off[i + 1]) (user order)
     const int32_t* row_seg;  // device [n]: instance of each row (NULL when nseg = 1)
     int coarse = 0;          // two-level: precond 1 and 2 run through learn_apply with the coarse part
+    unsigned char* active = nullptr;  // device [nseg] instance flags for masked MVMs (batched plans)
 };
+
+// fkt_mvm that skips the work of instances whose flag in the plan's
+// instance-flag buffer is 0 (set by the caller on the plan's stream first);
+// without such a buffer (one instance) it is fkt_mvm.
+fkt_status mvm_masked(fkt_plan_t P, const void* x, void* y, int nrhs);
 
 // Columns col .. col + ncols - 1 of y = K~ x in one pass of nc columns (1 or
 // kMvmCols, ncols <= nc; nc > 1 needs the node-major far field or no far

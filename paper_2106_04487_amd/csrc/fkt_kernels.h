@@ -437,6 +437,7 @@ __global__ __launch_bounds__(kWave) void k_s2m(const DevPlan a, const T* __restr
     const int u = blockIdx.x;
     const int lane = threadIdx.x;
     const int slot = a.unit_slot[u];
+    if (a.inst_active && !a.inst_active[a.slot_inst[slot]]) return;  // instance not needed by this MVM
     const int beg = a.unit_begin[u], end = a.unit_end[u];
     double c[D];
 #pragma unroll
@@ -701,6 +702,7 @@ __device__ __forceinline__ void m2t_node_job(const DevPlan& a, int j, const T* _
     constexpr int R = crank(D, P, KEEP);
     const int lane = threadIdx.x & 63;
     const int slot = a.nj_slot[j];
+    if (a.inst_active && !a.inst_active[a.slot_inst[slot]]) return;
     const int t = a.nj_tgt[(size_t)j * kWave + lane];
     const int tt = t >= 0 ? t : a.nj_tgt[(size_t)j * kWave];  // lane 0 of a job always holds a target
     double r[D];
@@ -914,6 +916,7 @@ __device__ __forceinline__ void near_unit(const DevPlan& a, int u, const T* __re
     constexpr int S = src_stride(D, NCOL);
     using NK = NearKernel<KIND, T>;
     const int lane = threadIdx.x & 63;
+    if (a.inst_active && !a.inst_active[a.nu_inst[u]]) return;
     const int s0 = a.nu_beg[u], m = a.nu_end[u] - s0;
     const int toff = a.nu_toff[u], tcnt = a.nu_tcnt[u];
     const T* __restrict__ q = src + (size_t)s0 * S;
