@@ -221,6 +221,12 @@ static fkt_status upload_plan(fkt_plan_t P)
     a.ell = P->kern.lengthscale;
     a.alpha = P->kern.alpha;
     a.var = P->kern.variance;
+    if (P->kern.kind == FKT_RATQUAD && P->kern.alpha == 1.0) {
+        // (1 + r^2 / (2 l^2))^-1 is the Cauchy kernel of length scale l sqrt(2):
+        // its kernels take one reciprocal where the general shape needs a power
+        a.kind = (int)FKT_CAUCHY;
+        a.ell = P->kern.lengthscale * std::sqrt(2.0);
+    }
     FKT_UP(T.pts, a.pts64);
     if (P->opt.prec == FKT_F32) {
         std::vector<float> p32(T.pts.begin(), T.pts.end());
