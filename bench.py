@@ -48,7 +48,10 @@ M2T_FLOPS_PER_PAIR = {(3, 6): 418}
 # HBM bytes per near-field launch from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (scale factors of a plain copy) of the current near kernel, from the
 # counter profile under profiles/; empty until re-measured after a change.
-NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.375e9}
+NEAR_TRAFFIC_BYTES = {("matern32", "f64"): 2.368e9}
+# the same for the node-major far-field launch (target coordinates re-read
+# per pair, one atomic add per pair)
+M2T_TRAFFIC_BYTES = {("matern32", "f64"): 1.825e10}
 
 
 def run_variant(F, torch, X, x64, kernel, prec, theta, leaf, order, steps, warmup, err_targets, overlap=True,
@@ -179,6 +182,30 @@ def gp_solve(F, torch, n, theta, order, rank, rtol, maxit, train_steps, fp64_non
     timed("learned_refined", refined("learned"))
     p32.close()
     p64.close()
+    return out
+
+
+def gp_mvm_leg(F, torch, steps, theta=0.3, order=8):
+    """MVM time of the GP workload's operator (FP64 and FP32 plans), with
+    stage times; the solves of gp_solve spend their time here."""
+    spec = W.WORKLOADS["gmm4_n200k_gp"]
+    X = W.gaussian_mixture(spec["n"], spec["d"], spec["ncomp"], spec["std"], spec["pts_seed"])
+    out = {"workload": f"gmm{spec['d']}_n{spec['n']}_matern52_l{spec['lengthscale']}", "theta": theta, "p": order}
+    for prec in ("f64", "f32"):
+        plan = F.fkt_plan(X, spec["kernel"], spec["leaf"], order, theta=theta, prec=prec, profile=True,
+                          lengthscale=spec["lengthscale"])
+        x = torch.as_tensor(W.normal_rhs(spec["n"], 1, 7)[:, 0], dtype=torch.float32 if prec == "f32" else
+                            torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        F.fkt_mvm(plan, x, y)
+        ms = _sync_time(torch, lambda: F.fkt_mvm(plan, x, y), steps)
+        plan.stage_times(reset=True)
+        F.fkt_mvm(plan, x, y)
+        st, c = plan.stage_times()
+        out[prec] = {"ms_per_mvm": ms, "stages_ms": {k: v / c for k, v in st.items()}, "far_pairs":
+                     plan.info()["far_pairs"], "near_pairs": plan.info()["near_pairs"]}
+        print(f"bench: gp mvm {prec}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        plan.close()
     return out
 
 
@@ -406,7 +433,8 @@ def main():
     ap.add_argument("--batch-no-per-instance", action="store_true")
     ap.add_argument("--mrhs-theta", type=float, default=0.4)
     ap.add_argument("--mrhs-modes", default=",".join(MRHS_MODES))
-    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp", "nsweep", "batched_solve"],
+    ap.add_argument("--leg", default="all", choices=["all", "many_rhs", "batched", "gp", "gp_mvm", "nsweep",
+                                                     "batched_solve"],
                     help="run one secondary leg alone and print its JSON (the default runs the headline line)")
     a = ap.parse_args()
 
@@ -428,6 +456,8 @@ def main():
             out = batch_solve_leg(F, torch, 32, a.batch_theta)
         elif a.leg == "nsweep":
             out = nsweep_leg(F, torch, a.steps, a.err_targets, a.kernel, a.prec)
+        elif a.leg == "gp_mvm":
+            out = gp_mvm_leg(F, torch, a.steps, a.gp_theta, a.gp_order)
         else:
             out = gp_solve(F, torch, a.gp_n, a.gp_theta, a.gp_order, a.gp_rank, 1e-6, a.gp_maxit, a.gp_train_steps,
                            a.gp_fp64_none)
@@ -456,8 +486,10 @@ def main():
         m2t_ms = head["stages_ms"]["m2t"]
         fpairs = head["plan"]["far_pairs"]
         ach = fpairs * M2T_FLOPS_PER_PAIR[(3, a.order)] / (m2t_ms * 1e-3) / 1e12
-        m2t = {"bound": "alu", "kernel": "k_m2t", "achieved": ach, "peak": PEAK_TFLOPS[a.prec], "unit": "TFLOP/s",
-               "frac": ach / PEAK_TFLOPS[a.prec], "units": "far (target, node) expansions",
+        m2t = {"bound": "alu", "kernel": "k_m2t_nodes", "achieved": ach, "peak": PEAK_TFLOPS[a.prec],
+               "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[a.prec],
+               "traffic": M2T_TRAFFIC_BYTES.get((a.kernel, a.prec)) if a.n == 1_000_000 else None,
+               "units": "far (target, node) expansions",
                "units_per_launch": fpairs, "flops_per_unit": M2T_FLOPS_PER_PAIR[(3, a.order)],
                "avg_launch_ms": m2t_ms}
 
