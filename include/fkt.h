@@ -98,9 +98,10 @@ typedef struct {
                            2 node-major (one wave per far node and up to 64
                            of its targets, moments read as wave-uniform
                            scalar operands, one atomic add per pair; plan
-                           memory 4 bytes per far pair); 0 (default) picks
-                           node-major except for FP32 plans of expansion
-                           rank above 200.                                  */
+                           memory 4 bytes per far pair; above rank 120
+                           the moments are staged in LDS); 0 (default)
+                           picks node-major except for FP32 plans of
+                           expansion rank above 1000.                       */
     int compress;       /* 1: compress the radial expansion (Appendix A.4,
                            eq. f_g) for a kernel with K' = q K, q a Laurent
                            polynomial (FKT_EXPONENTIAL, FKT_LAPLACE,
@@ -117,9 +118,10 @@ typedef struct {
     int fuse;           /* 1: the near and far field of each MVM pass run as
                            one persistent launch over a global work queue
                            (far jobs and near units interleaved, one atomic
-                           per item; needs the node-major far field and no
-                           compression, else FKT_EUNSUPPORTED). 0 (default):
-                           separate launches on two streams.               */
+                           per item; built for d = 3, needs the node-major
+                           far field and no compression, else
+                           FKT_EUNSUPPORTED). 0 (default): separate launches
+                           on two streams.                                  */
 } fkt_options;
 
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,

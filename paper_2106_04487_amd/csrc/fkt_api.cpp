@@ -274,9 +274,9 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.job_pairs, a.job_pairs);
     {
         // node-major far jobs (far_mode 2; far_mode 0 except FP32 plans of
-        // rank above 200, where the block-major kernel was measured faster)
+        // rank above 1000, where the block-major kernel was measured faster)
         const bool node_major = P->opt.far_mode == 2 || P->comp_keep > 0 || P->opt.fuse != 0 ||
-                                (P->opt.far_mode == 0 && !(P->opt.prec == FKT_F32 && P->tab.rank > 200));
+                                (P->opt.far_mode == 0 && !(P->opt.prec == FKT_F32 && P->tab.rank > 1000));
         a.nnjobs = 0;
         a.nj_slot = nullptr;
         a.nj_tgt = nullptr;
@@ -457,6 +457,7 @@ static fkt_status make_plan(const double* points, int64_t n, int d, const int64_
     if (opt.compress && opt.far_mode == 1)
         return fail(FKT_EUNSUPPORTED, "radial compression runs the node-major far field (far_mode 0 or 2)");
     if (opt.fuse != 0 && opt.fuse != 1) return fail(FKT_EINVAL, "fuse must be 0 or 1");
+    if (opt.fuse && d != 3) return fail(FKT_EUNSUPPORTED, "the persistent launch is built for d = 3 only");
     if (opt.fuse && (opt.compress || opt.far_mode == 1))
         return fail(FKT_EUNSUPPORTED, "the persistent launch runs the uncompressed node-major far field "
                                       "(compress 0, far_mode 0 or 2)");

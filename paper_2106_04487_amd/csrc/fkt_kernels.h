@@ -694,22 +694,38 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
 // concurrently, adds to the same accumulators). Four jobs per workgroup.
 // With NCOL columns, column c's moments are the block mom + c * cs and the
 // accumulators are [n][NCOL].
-// one node-major job j (wave-uniform) of 64 lanes
-template <int D, int P, int KIND, typename T, int KEEP, int NCOL>
+// Node-major jobs whose moments are staged in LDS: at high expansion rank
+// the scalar-operand moments need more scalar registers than there are
+// (the compiler spills them into vector lanes); wave-uniform LDS reads
+// broadcast to all lanes without bank conflicts and need no scalar
+// registers. Used when the four waves' moment sets fit in 64 KB.
+template <int D, int P, typename T, int KEEP, int NCOL>
+constexpr bool m2t_nodes_lds()
+{
+    return crank(D, P, KEEP) > 120 && 4 * NCOL * crank(D, P, KEEP) * (int)sizeof(T) <= 65536;
+}
+
+// one node-major job j (wave-uniform) of 64 lanes; with MLDS the node's
+// moments are at M (LDS, column c at M + c * R), else at mom + slot * R
+// (column c at + c * cs)
+template <int D, int P, int KIND, typename T, int KEEP, int NCOL, bool MLDS = false>
 __device__ __forceinline__ void m2t_node_job(const DevPlan& a, int j, const T* __restrict__ mom, size_t cs,
-                                             T* __restrict__ zacc)
+                                             T* __restrict__ zacc, const T* M = nullptr)
 {
     constexpr int R = crank(D, P, KEEP);
     const int lane = threadIdx.x & 63;
     const int slot = a.nj_slot[j];
-    if (a.inst_active && !a.inst_active[a.slot_inst[slot]]) return;
+    if (!MLDS && a.inst_active && !a.inst_active[a.slot_inst[slot]]) return;
     const int t = a.nj_tgt[(size_t)j * kWave + lane];
     const int tt = t >= 0 ? t : a.nj_tgt[(size_t)j * kWave];  // lane 0 of a job always holds a target
     double r[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) r[i] = a.pts64[(size_t)tt * D + i] - a.slot_ctr[slot * D + i];
     double acc[NCOL];
-    far_pair<D, P, KIND, T, true, KEEP, NCOL>(a, r, a.slot_scale[slot], mom + (size_t)slot * R, cs, acc);
+    if constexpr (MLDS)
+        far_pair<D, P, KIND, T, false, KEEP, NCOL>(a, r, a.slot_scale[slot], M, (size_t)R, acc);
+    else
+        far_pair<D, P, KIND, T, true, KEEP, NCOL>(a, r, a.slot_scale[slot], mom + (size_t)slot * R, cs, acc);
     if (t >= 0) {
 #pragma unroll
         for (int c = 0; c < NCOL; ++c) unsafeAtomicAdd(zacc + (size_t)t * NCOL + c, T(acc[c]));
@@ -721,8 +737,25 @@ __global__ __launch_bounds__(256) void k_m2t_nodes(const DevPlan a, const T* __r
                                                    T* __restrict__ zacc)
 {
     const int j = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    if (j >= a.nnjobs) return;
-    m2t_node_job<D, P, KIND, T, KEEP, NCOL>(a, j, mom, cs, zacc);
+    if constexpr (m2t_nodes_lds<D, P, T, KEEP, NCOL>()) {
+        constexpr int R = crank(D, P, KEEP);
+        __shared__ T smom[4 * NCOL * R];
+        T* my = smom + (threadIdx.x >> 6) * NCOL * R;
+        const int lane = threadIdx.x & 63;
+        bool run = j < a.nnjobs;
+        if (run) {
+            const int slot = a.nj_slot[j];
+            run = !(a.inst_active && !a.inst_active[a.slot_inst[slot]]);
+            if (run)
+                for (int c = 0; c < NCOL; ++c)
+                    for (int i = lane; i < R; i += kWave) my[c * R + i] = mom[c * cs + (size_t)slot * R + i];
+        }
+        __syncthreads();  // every wave of the block reaches it
+        if (run) m2t_node_job<D, P, KIND, T, KEEP, NCOL, true>(a, j, mom, cs, zacc, my);
+    } else {
+        if (j >= a.nnjobs) return;
+        m2t_node_job<D, P, KIND, T, KEEP, NCOL>(a, j, mom, cs, zacc);
+    }
 }
 
 // Radial compression of the moments (Appendix A.4, eq. f_g): for every far

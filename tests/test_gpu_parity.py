@@ -335,10 +335,11 @@ def test_multi_column_equals_single_columns(F):
     plan.close()
 
 
-@pytest.mark.parametrize("case", [SMALL[3], SMALL[10], SMALL[16]], ids=[SMALL[i][0] for i in (3, 10, 16)])
+@pytest.mark.parametrize("case", [SMALL[3], SMALL[4], SMALL[16]], ids=[SMALL[i][0] for i in (3, 4, 16)])
 def test_fused_persistent_launch_matches_oracle(F, case):
     """fuse=True (near and far field in one persistent launch over a global
-    work queue) gives the oracle's Algorithm 1, one and several columns."""
+    work queue) gives the oracle's Algorithm 1, one and several columns
+    (built for d = 3; d = 4 is refused)."""
     name, gen, nrhs, kind, kw, leaf, p, theta = case
     X = gen()
     x = W.normal_rhs(X.shape[0], 5, 7)
@@ -352,6 +353,8 @@ def test_fused_persistent_launch_matches_oracle(F, case):
     for c in range(5):
         _check(y5[:, c], zref[:, c], 1e-10)
     plan.close()
+    with pytest.raises(F.FktError, match="FKT_EUNSUPPORTED"):
+        F.fkt_plan(W.uniform_cube(500, 4, 3), kind, leaf, p, theta=theta, fuse=True, **kw)
 
 
 def test_fused_batch_plan_graph(F):

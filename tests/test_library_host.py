@@ -250,3 +250,14 @@ def test_radial_compression_plan_rank_and_rejections():
         F.fkt_plan(X, "laplace", 64, 6, theta=0.5, device=None, compress=True, far_mode="block")
     with pytest.raises(F.FktError, match="FKT_EINVAL"):
         F.fkt_radial_compression("matern52", 3, 6, lengthscale=0.2)
+
+
+def test_fuse_option_validation():
+    """The persistent launch is refused where it is not built (d = 4, 5) or
+    cannot run (block-major far field, radial compression)."""
+    X3, X4 = W.uniform_cube(2000, 3, 8), W.uniform_cube(2000, 4, 9)
+    pl = F.fkt_plan(X3, "gaussian", 64, 4, theta=0.5, device=None, fuse=True, lengthscale=0.2)
+    pl.close()
+    for X, kw in ((X4, {}), (X3, dict(far_mode="block")), (X3, dict(compress=True))):
+        with pytest.raises(F.FktError, match="FKT_EUNSUPPORTED"):
+            F.fkt_plan(X, "gaussian", 64, 4, theta=0.5, device=None, fuse=True, lengthscale=0.2, **kw)
