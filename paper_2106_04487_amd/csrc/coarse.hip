@@ -286,18 +286,30 @@ bool chol_lower(int k, double* a)
     return true;
 }
 
-// x <- L^-1 (lower triangular, row-major, zeros above) for the lower factor in a
+// x <- L^-1 (lower triangular, row-major, zeros above) for the lower factor
+// in a. Row i of X = L^-1 is (e_i - sum_{q<i} L_iq X_q) / L_ii: each row an
+// axpy combination of earlier rows (unit stride); threads take blocks of 32
+// columns.
 static void lower_inverse(int k, const double* a, std::vector<double>& x)
 {
     x.assign((size_t)k * k, 0.0);
-    // column c of L^-1 by forward substitution; columns are independent
-    parallel_for(k, 8, [&](int64_t c0, int64_t c1) {
-        for (int64_t c = c0; c < c1; ++c) {
-            for (int64_t i = c; i < k; ++i) {
-                double s = (i == c) ? 1.0 : 0.0;
+    constexpr int64_t cb = 32;
+    parallel_for((k + cb - 1) / cb, 1, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t c0 = b * cb, c1 = std::min<int64_t>(k, c0 + cb);
+            for (int64_t i = c0; i < k; ++i) {
+                double* xi = x.data() + (size_t)i * k;
                 const double* ai = a + (size_t)i * k;
-                for (int64_t q = c; q < i; ++q) s -= ai[q] * x[(size_t)q * k + c];
-                x[(size_t)i * k + c] = s / ai[i];
+                const int64_t ce = std::min<int64_t>(c1, i + 1);
+                for (int64_t c = c0; c < ce; ++c) xi[c] = (i == c) ? 1.0 : 0.0;
+                for (int64_t q = c0; q < i; ++q) {  // X_qc = 0 for c > q
+                    const double f = ai[q];
+                    const double* xq = x.data() + (size_t)q * k;
+                    const int64_t qe = std::min<int64_t>(ce, q + 1);
+                    for (int64_t c = c0; c < qe; ++c) xi[c] -= f * xq[c];
+                }
+                const double inv = 1.0 / ai[i];
+                for (int64_t c = c0; c < ce; ++c) xi[c] *= inv;
             }
         }
     });
@@ -308,14 +320,22 @@ bool spd_inverse(int k, double* a)
     if (!chol_lower(k, a)) return false;
     std::vector<double> x;
     lower_inverse(k, a, x);
-    // a^-1 = L^-T L^-1: entry (i, j) = sum_{q >= max(i, j)} x[q][i] x[q][j]
-    parallel_for(k, 8, [&](int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i)
-            for (int64_t j = 0; j < k; ++j) {
-                double s = 0.0;
-                for (int64_t q = std::max(i, j); q < k; ++q) s += x[(size_t)q * k + i] * x[(size_t)q * k + j];
-                a[(size_t)i * k + j] = s;
+    // a^-1 = X^T X = sum_q (row q of X)^T (row q of X): every thread owns 8
+    // output rows and adds the rank-one terms row by row (unit stride)
+    std::fill(a, a + (size_t)k * k, 0.0);
+    constexpr int64_t rb = 8;
+    parallel_for((k + rb - 1) / rb, 1, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t i0 = b * rb, i1 = std::min<int64_t>(k, i0 + rb);
+            for (int64_t q = i0; q < k; ++q) {
+                const double* xq = x.data() + (size_t)q * k;
+                for (int64_t i = i0; i < std::min<int64_t>(i1, q + 1); ++i) {
+                    const double f = xq[i];
+                    double* ar = a + (size_t)i * k;
+                    for (int64_t j = 0; j <= q; ++j) ar[j] += f * xq[j];
+                }
             }
+        }
     });
     return true;
 }

@@ -47,7 +47,9 @@ def test_noalloc_matches_allocating_solve_twice(F):
         b = torch.as_tensor(bh if nrhs > 1 else bh[:, 0], device="cuda").contiguous()
         xr, itr, rrr, x, it, rr = _solve_both(F, plan, sig2, b, pc)
         assert rr <= 1e-10 and rrr <= 1e-10
-        assert abs(it - itr) <= 2, (it, itr)
+        # the MVM's atomic sums round differently from run to run; at rtol
+        # 1e-10 a solve of ~1,200 iterations has shifted by up to 8
+        assert abs(it - itr) <= max(2, 0.01 * itr), (it, itr)
         # both are solutions of the same system to 1e-10; their difference is
         # bounded by the condition number times that
         err = float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr))
