@@ -12,6 +12,7 @@ import os
 import re
 import subprocess
 import sys
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -122,7 +123,10 @@ def build(jobs: int = 8, verbose: bool = False, incremental: bool = False) -> st
             print(" ".join(cmd), flush=True)
         out = cmd[cmd.index("-o") + 1]
         fp = _fingerprint(cmd) if out.endswith(".o") else None  # inputs as compiled
+        t0 = time.perf_counter()
         r = subprocess.run(cmd, capture_output=True, text=True)
+        if verbose:
+            print(f"{time.perf_counter() - t0:7.1f} s  {out}", flush=True)
         if r.returncode != 0:
             raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + r.stdout + r.stderr)
         if fp:
