@@ -235,16 +235,20 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
     kw = dict(lengthscale=spec["lengthscale"], alpha=spec["alpha"])
     p = spec["order"]
     tune = None
+    far_mode = "auto"
     if leaf <= 0:
+        # leaf size and far-field schedule from the library's autotuner
         t0 = time.perf_counter()
-        leaf, tune = F.fkt_autotune_leaf((X, off), spec["kernel"], p, [128, 256, 512, 1024], nrhs=spec["nrhs"],
-                                         reps=2, theta=theta, prec="f32", batch=True, **kw)
+        (leaf, far_mode), table = F.fkt_autotune((X, off), spec["kernel"], p, [256, 512, 1024], ("block", "node"),
+                                                 nrhs=spec["nrhs"], reps=2, theta=theta, prec="f32", batch=True, **kw)
+        tune = {f"{lf}/{m}": v for (lf, m), v in table.items()}
         tune_s = time.perf_counter() - t0
-        print(f"bench: batch autotune {tune} -> leaf {leaf} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+        print(f"bench: batch autotune {tune} -> leaf {leaf}, {far_mode} ({tune_s:.1f} s)", file=sys.stderr,
+              flush=True)
     x = torch.as_tensor(x64, dtype=torch.float32, device="cuda").contiguous()
     y = torch.empty_like(x)
     t0 = time.perf_counter()
-    plan = F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
+    plan = F.fkt_plan_batch((X, off), spec["kernel"], leaf, p, theta=theta, prec="f32", far_mode=far_mode, **kw)
     plan_s = time.perf_counter() - t0
     F.fkt_mvm(plan, x, y)
     eager_ms = _sync_time(torch, lambda: F.fkt_mvm(plan, x, y), reps)
@@ -258,8 +262,8 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
     per_ms = plans_s = None
     if per_instance:
         t0 = time.perf_counter()
-        plans = [F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, prec="f32", **kw)
-                 for i in range(len(sizes))]
+        plans = [F.fkt_plan(X[off[i]:off[i + 1]], spec["kernel"], leaf, p, theta=theta, prec="f32",
+                            far_mode=far_mode, **kw) for i in range(len(sizes))]
         plans_s = time.perf_counter() - t0
         xs = [x[off[i]:off[i + 1]] for i in range(len(sizes))]
         ys = [y[off[i]:off[i + 1]] for i in range(len(sizes))]
@@ -281,7 +285,8 @@ def batch_leg(F, torch, reps, theta, err_per_inst, leaf=0, per_instance=True):
         errs.append(float(np.linalg.norm(yb[a:b][tg] - zd) / np.linalg.norm(zd)))
     out = {"workload": f"batch{len(sizes)}_rq_d3_n{n}", "instances": len(sizes), "n_total": int(n),
            "size_min": int(sizes.min()), "size_max": int(sizes.max()), "nrhs": spec["nrhs"], "dtype": "f32",
-           "theta": theta, "p": p, "leaf": leaf, "autotune_ms": tune, "batched_graph_ms": graph_ms,
+           "theta": theta, "p": p, "leaf": leaf, "far_mode": far_mode, "autotune_ms": tune,
+           "batched_graph_ms": graph_ms,
            "batched_eager_ms": eager_ms, "per_instance_ms": per_ms,
            "batched_graph_mpoints_per_s": n / graph_ms / 1e3,
            "speedup_graph_vs_per_instance": per_ms / graph_ms if per_ms else None,

@@ -124,6 +124,11 @@ typedef struct {
                            on two streams.                                  */
 } fkt_options;
 
+/* Test hook: with the environment variable FKT_FAIL_ALLOC_AT=k set, the k-th
+ * device allocation while a plan is built reports out of memory (fkt_plan
+ * then returns FKT_ENOMEM and frees what it had allocated). Unset: no
+ * effect. */
+
 /* Defaults: theta 0.5, FKT_F64, max_depth 48, device 0, stream NULL, profile 0,
  * overlap 1, mrhs 0, far_mode 0, compress 0, fuse 0. */
 void fkt_default_options(fkt_options *opt);
@@ -427,6 +432,20 @@ void fkt_graph_destroy(fkt_graph_t g);
 fkt_status fkt_autotune_leaf(const double *points, const int64_t *offsets, int ninst, int64_t n, int d, fkt_kernel k,
                              int order, const fkt_options *opt, const int *candidates, int ncand, int nrhs, int reps,
                              int *best, double *ms);
+
+/*
+ * Autotuner over leaf sizes and far-field schedules: as fkt_autotune_leaf
+ * for every pair (leaves[i], far_modes[m]) (far_mode values of
+ * fkt_options: 0 automatic, 1 block-major, 2 node-major; the two schedules
+ * tile the far field differently: 64-target blocks over LDS-staged node
+ * moments, or one far node over 64 targets). *best_leaf and *best_mode
+ * (may be NULL) receive the fastest pair; ms (host, nleaf * nmodes doubles,
+ * row i = leaf i, may be NULL) each pair's time per MVM. Errors: as
+ * fkt_autotune_leaf, FKT_EINVAL for a far_mode outside 0..2.
+ */
+fkt_status fkt_autotune(const double *points, const int64_t *offsets, int ninst, int64_t n, int d, fkt_kernel k,
+                        int order, const fkt_options *opt, const int *leaves, int nleaf, const int *far_modes,
+                        int nmodes, int nrhs, int reps, int *best_leaf, int *best_mode, double *ms);
 
 /*
  * Learned per-leaf preconditioner (not part of the paper's method; used by

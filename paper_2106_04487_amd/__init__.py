@@ -46,7 +46,8 @@ EXPORTED = ["fkt_default_options", "fkt_plan", "fkt_mvm", "fkt_cg_solve", "fkt_c
             "fkt_radial_compression",
             "fkt_learn_nparams", "fkt_learn_params", "fkt_learn_loss_grad", "fkt_learn_train",
             "fkt_learn_train_cond", "fkt_learn_cond_grad",
-            "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf"]
+            "fkt_plan_batch", "fkt_graph_create", "fkt_graph_launch", "fkt_graph_destroy", "fkt_autotune_leaf",
+            "fkt_autotune"]
 
 
 class FktError(RuntimeError):
@@ -124,6 +125,10 @@ _lib.fkt_autotune_leaf.restype = ctypes.c_int
 _lib.fkt_autotune_leaf.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _Kernel, ctypes.c_int,
                                    ctypes.POINTER(_Options), _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.POINTER(ctypes.c_int), _P]
+_lib.fkt_autotune.restype = ctypes.c_int
+_lib.fkt_autotune.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _Kernel, ctypes.c_int,
+                              ctypes.POINTER(_Options), _P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _P]
 _lib.fkt_learn_nparams.restype = ctypes.c_int64
 _lib.fkt_learn_nparams.argtypes = []
 _lib.fkt_learn_params.restype = ctypes.c_int
@@ -330,6 +335,31 @@ def fkt_autotune_leaf(points, kernel: str, order: int, candidates, *, nrhs: int 
                                   cand.ctypes.data, len(cand), int(nrhs), int(reps), ctypes.byref(best),
                                   ms.ctypes.data))
     return best.value, dict(zip(cand.tolist(), ms.tolist()))
+
+
+def fkt_autotune(points, kernel: str, order: int, leaves, far_modes=("block", "node"), *, nrhs: int = 1,
+                 reps: int = 3, lengthscale: float = 1.0, alpha: float = 1.0, variance: float = 1.0,
+                 theta: float = 0.5, prec: str = "f64", batch: bool = False, device: int = 0):
+    """((best leaf, best far_mode name), {(leaf, far_mode): ms per MVM}) from
+    the library's autotuner over leaf sizes and far-field schedules."""
+    if batch:
+        X, off = _batch_points(points)
+        offp, ninst = off.ctypes.data, len(off) - 1
+    else:
+        X = np.ascontiguousarray(points, dtype=np.float64)
+        off, offp, ninst = None, None, 1
+    lv = np.ascontiguousarray(leaves, dtype=np.int32)
+    fm = np.ascontiguousarray([FAR_MODES[m] for m in far_modes], dtype=np.int32)
+    ms = np.zeros((len(lv), len(fm)))
+    bl, bm = ctypes.c_int(-1), ctypes.c_int(-1)
+    opt = _options(theta, prec, 48, device, None, False, True, None)
+    _check(_lib.fkt_autotune(X.ctypes.data, offp, ninst, X.shape[0], X.shape[1],
+                             _kernel(kernel, lengthscale, alpha, variance), int(order), ctypes.byref(opt),
+                             lv.ctypes.data, len(lv), fm.ctypes.data, len(fm), int(nrhs), int(reps), ctypes.byref(bl),
+                             ctypes.byref(bm), ms.ctypes.data))
+    names = {v: k for k, v in FAR_MODES.items()}
+    table = {(int(l), m): float(ms[i, j]) for i, l in enumerate(lv) for j, m in enumerate(far_modes)}
+    return (bl.value, names[bm.value]), table
 
 
 def fkt_plan(points, kernel: str, leaf_size: int, order: int, *, lengthscale: float = 1.0, alpha: float = 1.0,

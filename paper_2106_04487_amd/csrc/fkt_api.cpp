@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -89,6 +90,7 @@ struct fkt_plan_s {
     bool on_device = false;
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
+    int64_t nalloc = 0;  // device allocations of the plan so far (fault-injection hook)
     fkt::DevPlan dp{};
     fkt::DevWork wk{};
     fkt::DevMrhs mr{};   // many-RHS layout (opt.mrhs != 0)
@@ -147,6 +149,11 @@ struct fkt_plan_s {
     {
         *out = nullptr;
         if (bytes == 0) bytes = 256;
+        // test hook: FKT_FAIL_ALLOC_AT=k makes the plan's k-th device
+        // allocation report out-of-memory (error paths without a full device)
+        ++nalloc;
+        if (const char* f = std::getenv("FKT_FAIL_ALLOC_AT"))
+            if (std::atoll(f) == nalloc) return hipErrorOutOfMemory;
         hipError_t e = hipMalloc(out, bytes);
         if (e == hipSuccess) allocs.push_back(*out);
         return e;
@@ -1227,12 +1234,15 @@ fkt_status fkt_graph_launch(fkt_graph_t G)
 
 void fkt_graph_destroy(fkt_graph_t G) { delete G; }
 
-fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int ninst, int64_t n, int d, fkt_kernel k,
-                             int order, const fkt_options* opt, const int* candidates, int ncand, int nrhs, int reps,
-                             int* best, double* ms)
+fkt_status fkt_autotune(const double* points, const int64_t* offsets, int ninst, int64_t n, int d, fkt_kernel k,
+                        int order, const fkt_options* opt, const int* leaves, int nleaf, const int* far_modes,
+                        int nmodes, int nrhs, int reps, int* best_leaf, int* best_mode, double* ms)
 {
-    if (!candidates || ncand < 1 || !best) return fail(FKT_EINVAL, "candidates, ncand or best invalid");
+    if (!leaves || nleaf < 1 || !far_modes || nmodes < 1 || !best_leaf)
+        return fail(FKT_EINVAL, "candidates, counts or best_leaf invalid");
     if (nrhs < 1 || nrhs > 64 || reps < 1) return fail(FKT_EINVAL, "nrhs must be in [1, 64] and reps >= 1");
+    for (int m = 0; m < nmodes; ++m)
+        if (far_modes[m] < 0 || far_modes[m] > 2) return fail(FKT_EINVAL, "far_modes entries must be 0, 1 or 2");
     fkt_options o;
     fkt_default_options(&o);
     if (opt) o = *opt;
@@ -1253,27 +1263,32 @@ fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int n
     }
     fkt_status st = FKT_OK;
     double best_ms = 0.0;
-    *best = -1;
-    for (int c = 0; c < ncand && st == FKT_OK; ++c) {
-        fkt_plan_t P = nullptr;
-        st = offsets ? fkt_plan_batch(points, offsets, ninst, d, k, candidates[c], order, &o, &P)
-                     : fkt_plan(points, n, d, k, candidates[c], order, &o, &P);
-        if (st != FKT_OK) break;
-        // one untimed pass, then reps timed passes bracketed by events
-        st = fkt_mvm(P, x, y, nrhs);
-        if (st == FKT_OK && hipEventRecord(e0, P->stream) != hipSuccess) st = fail(FKT_EDEVICE, "event record");
-        for (int r = 0; r < reps && st == FKT_OK; ++r) st = fkt_mvm(P, x, y, nrhs);
-        float t = 0.f;
-        if (st == FKT_OK && (hipEventRecord(e1, P->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&t, e0, e1) != hipSuccess))
-            st = fail(FKT_EDEVICE, "autotune timing");
-        fkt_destroy(P);
-        if (st != FKT_OK) break;
-        const double per = (double)t / reps;
-        if (ms) ms[c] = per;
-        if (*best < 0 || per < best_ms) {
-            best_ms = per;
-            *best = candidates[c];
+    *best_leaf = -1;
+    if (best_mode) *best_mode = -1;
+    for (int c = 0; c < nleaf && st == FKT_OK; ++c) {
+        for (int m = 0; m < nmodes && st == FKT_OK; ++m) {
+            o.far_mode = far_modes[m];
+            fkt_plan_t P = nullptr;
+            st = offsets ? fkt_plan_batch(points, offsets, ninst, d, k, leaves[c], order, &o, &P)
+                         : fkt_plan(points, n, d, k, leaves[c], order, &o, &P);
+            if (st != FKT_OK) break;
+            // one untimed pass, then reps timed passes bracketed by events
+            st = fkt_mvm(P, x, y, nrhs);
+            if (st == FKT_OK && hipEventRecord(e0, P->stream) != hipSuccess) st = fail(FKT_EDEVICE, "event record");
+            for (int r = 0; r < reps && st == FKT_OK; ++r) st = fkt_mvm(P, x, y, nrhs);
+            float t = 0.f;
+            if (st == FKT_OK && (hipEventRecord(e1, P->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                st = fail(FKT_EDEVICE, "autotune timing");
+            fkt_destroy(P);
+            if (st != FKT_OK) break;
+            const double per = (double)t / reps;
+            if (ms) ms[(size_t)c * nmodes + m] = per;
+            if (*best_leaf < 0 || per < best_ms) {
+                best_ms = per;
+                *best_leaf = leaves[c];
+                if (best_mode) *best_mode = far_modes[m];
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1281,6 +1296,18 @@ fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int n
     (void)hipFree(x);
     (void)hipFree(y);
     return st;
+}
+
+fkt_status fkt_autotune_leaf(const double* points, const int64_t* offsets, int ninst, int64_t n, int d, fkt_kernel k,
+                             int order, const fkt_options* opt, const int* candidates, int ncand, int nrhs, int reps,
+                             int* best, double* ms)
+{
+    fkt_options o;
+    fkt_default_options(&o);
+    if (opt) o = *opt;
+    const int mode = o.far_mode;
+    return fkt_autotune(points, offsets, ninst, n, d, k, order, &o, candidates, ncand, &mode, 1, nrhs, reps, best,
+                        nullptr, ms);
 }
 
 }  // extern "C"

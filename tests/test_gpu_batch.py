@@ -156,3 +156,21 @@ def test_autotuner_picks_a_candidate(F):
     print("autotune ms per MVM:", ms, "best", best)
     assert best in ms and all(v > 0.0 for v in ms.values())
     assert ms[best] == min(ms.values())
+
+
+def test_autotune_over_leaf_and_far_schedule(F):
+    """fkt_autotune times every (leaf, far-field schedule) pair and returns
+    the fastest; the pair it returns builds a plan whose MVM matches the
+    oracle on every instance."""
+    X, off = W.batched_instances(W.instance_sizes(6, 500, 4000, 140), 3, 141)
+    (leaf, mode), table = F.fkt_autotune((X, off), "ratquad", 4, [32, 64, 128], ("block", "node"), nrhs=2, reps=1,
+                                         theta=0.5, batch=True, **KW)
+    assert len(table) == 6 and all(v > 0 for v in table.values())
+    assert table[(leaf, mode)] == min(table.values())
+    plan = F.fkt_plan_batch((X, off), "ratquad", leaf, 4, theta=0.5, far_mode=mode, **KW)
+    x = W.normal_rhs(X.shape[0], 2, 142)
+    import torch
+    y = F.fkt_mvm(plan, torch.as_tensor(x, device="cuda")).cpu().numpy()
+    ref = _oracle_batch(X, off, x, leaf, 4, 0.5)
+    assert np.linalg.norm(y - ref) <= 1e-10 * np.linalg.norm(ref)
+    plan.close()

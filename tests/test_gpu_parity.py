@@ -381,3 +381,25 @@ def test_fused_batch_plan_graph(F):
         _check(ye[o:o + m], zref, 1e-10)
         o += m
     plan.close()
+
+
+def test_plan_allocation_failures_are_reported(F, monkeypatch):
+    """Fault injection (FKT_FAIL_ALLOC_AT=k: the plan's k-th device
+    allocation fails): every failure point gives FKT_ENOMEM and releases the
+    partial plan, and a plan built afterwards still computes the oracle's
+    MVM."""
+    X = W.uniform_cube(3000, 3, 130)
+    x = W.normal_rhs(3000, 1, 131)
+    kw = dict(lengthscale=0.1)
+    for k in (1, 2, 5, 10, 20, 30):
+        monkeypatch.setenv("FKT_FAIL_ALLOC_AT", str(k))
+        try:
+            plan = F.fkt_plan(X, "matern32", 64, 4, theta=0.5, **kw)
+        except F.FktError as e:
+            assert e.status == 2, e  # FKT_ENOMEM
+        else:
+            plan.close()  # fewer than k allocations: the plan is complete
+    monkeypatch.delenv("FKT_FAIL_ALLOC_AT")
+    z, plan = _gpu_mvm(F, X, x[:, 0], "matern32", 64, 4, 0.5, **kw)
+    zref = oracle.fkt_alg1(oracle.Tree(X, 64), x, "matern32", 0.5, 4, **kw)
+    _check(z, zref, 1e-10)
