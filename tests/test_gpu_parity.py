@@ -403,3 +403,21 @@ def test_plan_allocation_failures_are_reported(F, monkeypatch):
     z, plan = _gpu_mvm(F, X, x[:, 0], "matern32", 64, 4, 0.5, **kw)
     zref = oracle.fkt_alg1(oracle.Tree(X, 64), x, "matern32", 0.5, 4, **kw)
     _check(z, zref, 1e-10)
+
+
+@pytest.mark.parametrize("d,p,kind,kw", [(4, 8, "matern52", dict(lengthscale=0.3)), (3, 8, "exponential",
+                                                                                       dict(lengthscale=0.2))])
+def test_high_rank_fp32_far_field_schedules(F, d, p, kind, kw):
+    """At ranks above 120 the node-major far field stages moments in LDS; in
+    FP32 both schedules stay within FP32 rounding of the FP64 plan (whose
+    own parity with the oracle is tested above), and agree with each other."""
+    X = W.gaussian_mixture(6000, d, 8, 0.15, 150 + d)
+    x = W.normal_rhs(6000, 1, 151)[:, 0]
+    z64, _ = _gpu_mvm(F, X, x, kind, 128, p, 0.4, **kw)
+    zs = {}
+    for mode in ("node", "block"):
+        zs[mode], _ = _gpu_mvm(F, X, x, kind, 128, p, 0.4, prec="f32", far_mode=mode, **kw)
+        rel = np.linalg.norm(zs[mode] - z64) / np.linalg.norm(z64)
+        print(f"d{d} p{p} {kind} FP32 {mode}: {rel:.2e} vs FP64")
+        assert rel < 1e-5
+    assert np.linalg.norm(zs["node"] - zs["block"]) / np.linalg.norm(z64) < 2e-6
