@@ -164,7 +164,11 @@ fkt_status fkt_plan(const double *points, int64_t n, int d, fkt_kernel k, int le
  * expansion about each far node's centre.
  *   x, y      device, n x nrhs row-major, element type double (FKT_F64) or
  *             float (FKT_F32). Must not overlap. y is fully overwritten.
- *   nrhs      number of right-hand sides, 1 <= nrhs <= 64.
+ *   nrhs      number of right-hand sides, 1 <= nrhs <= 64. Plans with the
+ *             node-major far field run the columns in passes of four (three
+ *             padded to four; one or two column by column), sharing every
+ *             kernel value, harmonic and radial function within a pass;
+ *             mrhs plans run groups of 32 columns on the matrix cores.
  * Enqueued on the plan's stream; returns before the result is ready.
  * Allocates nothing: the plan's work buffers are allocated by fkt_plan.
  * Errors: FKT_EINVAL (NULL/overlapping pointers, nrhs), FKT_EDEVICE (host-only
@@ -185,7 +189,9 @@ fkt_status fkt_mvm(fkt_plan_t p, const void *x, void *y, int nrhs);
  *             (fkt_plan_batch) the operator is block diagonal, so every
  *             instance and column runs its own CG recurrences (its own step
  *             lengths and stopping test, norms over the instance's rows);
- *             a system that has converged is frozen while the others go on.
+ *             a system that has converged is frozen while the others go on,
+ *             and the operator work of an instance whose systems have all
+ *             converged is skipped in the following iterations.
  *   maxit     iteration cap, >= 1.
  *   precond   0 none, 1 block-Jacobi (per-leaf dense Cholesky of
  *             K_ll + sigma2 I), 2 the learned per-leaf spectral filter

@@ -6,11 +6,16 @@ fallback: if ``libfkt.so`` is missing the import of this module fails.
 
 Entry points mirror the C ABI (include/fkt.h):
     fkt_plan(points, kernel, leaf_size, order, ...) -> Plan
+    fkt_plan_batch((points, offsets), kernel, leaf_size, order, ...) -> Plan
     fkt_mvm(plan, x, y=None) -> y
     fkt_cg_solve(plan, sigma2, b, x0=None, ...) -> (x, iters, relres)
     fkt_cg_solve64(plan, sigma2, b, x0=None, ...) -> (x, iters, relres), FP64 b and x
     fkt_cg_solve_refined(plan64, plan32, sigma2, b, x0=None, ...) -> (x, iters, outer, relres)
-    fkt_destroy(plan)
+    fkt_cg_solve_noalloc(plan, sigma2, b, x, ...) -> (iters, relres)
+    fkt_precond_coarse(plan, sigma2, landmarks)
+    fkt_learn_train_cond / fkt_learn_train / fkt_learn_params / ... (learned filter)
+    Graph(plan, x, y).launch(), fkt_autotune / fkt_autotune_leaf,
+    fkt_radial_compression(kernel, d, order), fkt_destroy(plan)
 """
 from __future__ import annotations
 
