@@ -18,9 +18,11 @@
  *   - Device work is enqueued on the plan's stream and is asynchronous: the
  *     caller synchronises the stream before reading results.
  *   - The caller owns every array it passes; the plan copies what it keeps.
- *   - A plan is immutable after fkt_plan. Calls on one plan from several
- *     host threads must use the same stream or be serialised by the caller
- *     (the plan owns one set of work buffers).
+ *   - A plan's tree, lists and tables are fixed by fkt_plan; preconditioner
+ *     state (fkt_precond_coarse, fkt_learn_*) is added by later calls. Calls
+ *     on one plan must be serialised by the caller: the plan owns one set of
+ *     work buffers, and a solve sets plan state (the instance flags of its
+ *     masked operator applications) while it runs.
  */
 #ifndef FKT_H
 #define FKT_H
