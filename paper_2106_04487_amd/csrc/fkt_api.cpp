@@ -411,6 +411,13 @@ static fkt_status upload_plan(fkt_plan_t P)
             FKT_UP3(J.job_nodes, P->mr.job_nodes);
             FKT_UP3(J.job_pairs, P->mr.job_pairs);
 #undef FKT_UP3
+            int64_t maxj = 0;
+            for (size_t b = 0; b + 1 < J.job_off.size(); ++b)
+                maxj = std::max<int64_t>(maxj, (int64_t)J.job_off[b + 1] - J.job_off[b]);
+            int64_t seg = fkt::kMrSegJobs;
+            if ((maxj + seg - 1) / seg > 65535) seg = (maxj + 65534) / 65535;  // grid y limit
+            P->mr.job_seg = (int)seg;
+            P->mr.job_nseg = (int)std::max<int64_t>(1, (maxj + seg - 1) / seg);
         }
         if (ns > 0) {
             if ((e = P->alloc(sizeof(float) * (size_t)fkt::kMrCols * ns * R, &P->mr.mom)) != hipSuccess)

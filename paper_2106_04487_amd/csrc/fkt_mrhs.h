@@ -13,6 +13,7 @@ namespace fkt {
 
 constexpr int kMrCols = 32;      // columns per group
 constexpr int kMrJobNodes = 4;   // far nodes per 64-lane job of the matrix-core far field
+constexpr int kMrSegJobs = 64;   // far jobs per work unit of the matrix-core far field
 
 struct DevMrhs {
     int npad = 0;                     // leaves padded to multiples of 32 points
@@ -37,6 +38,11 @@ struct DevMrhs {
     const int* job_noff = nullptr;
     const int* job_nodes = nullptr;
     const uint16_t* job_pairs = nullptr;
+    // the far jobs of a block are cut into units of job_seg consecutive jobs,
+    // one wave each (grid nblocks x job_nseg), so the waves of heavy blocks
+    // spread over the machine; units add their sums into zf atomically
+    int job_seg = kMrSegJobs;
+    int job_nseg = 1;
 };
 
 // far field of one column (gather clearing wk.zacc, s2m, m2t into wk.zacc)

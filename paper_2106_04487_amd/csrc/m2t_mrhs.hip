@@ -13,7 +13,11 @@
 // once per group) with v_mfma_f32_16x16x32_bf16, three products per tile
 // (hi*hi + hi*lo + lo*hi: about 16 bits of mantissa), rows of other nodes
 // masked to zero. Pair rows are then added into the block's per-target LDS
-// sums, which are written once per (target, column).
+// sums. The jobs of a block are cut into units of a fixed number of jobs,
+// one wave each, so that blocks with many far nodes do not leave a long tail
+// of single waves at the end of the launch; each unit adds its per-target
+// sums into the far-field buffer (cleared beforehand) with one atomic add per
+// (target, column).
 #include <hip/hip_runtime.h>
 
 #include "fkt_kernels.h"
@@ -45,14 +49,16 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
     __shared__ bf8 Alo[4][kKS][kWave];
     __shared__ float Zb[kWave][kMrCols + 1];
     const int blk = blockIdx.x, lane = threadIdx.x, r16 = lane & 15;
+    const int jb = mr.job_off[blk] + (int)blockIdx.y * mr.job_seg, je = mr.job_off[blk + 1];
+    if (jb >= je) return;  // whole-wave exit: this unit has no jobs
     const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
     for (int c = 0; c <= kMrCols; ++c) Zb[lane][c] = 0.f;
     double tx[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
 
-    const int j0 = mr.job_off[blk], j1 = mr.job_off[blk + 1];
-    for (int j = j0; j < j1; ++j) {
+    const int j1 = min(je, jb + mr.job_seg);
+    for (int j = jb; j < j1; ++j) {
         const int n0 = mr.job_noff[j], nn = mr.job_noff[j + 1] - n0;
         const unsigned pw = mr.job_pairs[(size_t)j * kWave + lane];
         const bool valid = pw != 0xffffu;
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
     }
     __syncthreads();
     if (lane < cnt)
-        for (int c = 0; c < kMrCols; ++c) zf[(size_t)c * a.n + tb + lane] = Zb[lane][c];
+        for (int c = 0; c < kMrCols; ++c) unsafeAtomicAdd(zf + (size_t)c * a.n + tb + lane, Zb[lane][c]);
 }
 
 template <int D, int P = 0>
@@ -210,7 +216,7 @@ bool launch_d(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
         return false;
     } else {
         if (a.p == P) {
-            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks), dim3(kWave), 0, s, a, mr,
+            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks, mr.job_nseg), dim3(kWave), 0, s, a, mr,
                                (const bf8*)mr.bhi, (const bf8*)mr.blo, mr.ks, (float*)mr.zf);
             return true;
         }

@@ -19,6 +19,8 @@
 // coordinates of the leaf's first point), so every step loads aligned runs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fkt_kernels.h"
 #include "fkt_mrhs.h"
 
@@ -40,6 +42,12 @@ __global__ __launch_bounds__(256) void k_mr_gather(int npad, const int* __restri
     const float* xr = s >= 0 ? x + perm[s] * nrhs + col0 : nullptr;
 #pragma unroll 8
     for (int c = 0; c < kMrCols; ++c) XT[(size_t)c * npad + p] = (TC)(xr ? xr[c] : 0.f);
+}
+
+// p[0, n) = 0 (a kernel, not a memset node, so the MVM stays capturable)
+__global__ __launch_bounds__(256) void k_mr_zero(int64_t n, float* __restrict__ p)
+{
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256) p[g] = 0.f;
 }
 
 // X32[i][c] = x[perm[i]][col0 + c]: the group's weights in tree order
@@ -253,6 +261,10 @@ hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, co
             const int64_t nf = (int64_t)a.nslots * mr.ks * 2 * kWave;
             hipLaunchKernelGGL(k_mom_frag, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s, a.nslots, a.rank,
                                mr.ks, (const float*)mr.mom, (bf8*)mr.bhi, (bf8*)mr.blo);
+            // the far-field units add into zf
+            const int64_t nz = (int64_t)a.n * kMrCols;
+            hipLaunchKernelGGL(k_mr_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((nz + 255) / 256, 8192))), dim3(256), 0, s,
+                               nz, zf);
             if (!launch_m2t_mrhs(a, mr, s)) return hipErrorInvalidValue;
         } else {
             // far field of each column into zf[c] (the gather clears it)
