@@ -400,10 +400,12 @@ static fkt_status upload_plan(fkt_plan_t P)
         P->mr.ks = (int)((R + 63) / 64 * 2);
         {
             fkt::JobSet J;
-            fkt::pack_far_jobs(L, fkt::kMrJobNodes, J);
+            fkt::pack_far_jobs_grouped(L, fkt::kMrJobNodes, fkt::kMrGroupBlocks, J);
             std::string err;
-            if (!fkt::check_jobs(L, J.job_off, J.job_noff, J.job_nodes, J.job_pairs, J.max_nodes, err))
+            if (!fkt::check_jobs_grouped(L, J, fkt::kMrGroupBlocks, err))
                 return fail(FKT_EINVAL, "internal error: " + err);
+            P->mr.job_group = fkt::kMrGroupBlocks;
+            P->mr.ngroups = (int)(J.job_off.size() - 1);
 #define FKT_UP3(vec, dst) \
     if ((e = P->upload(vec, &dst)) != hipSuccess) return hip_fail(e, "many-RHS job upload")
             FKT_UP3(J.job_off, P->mr.job_off);

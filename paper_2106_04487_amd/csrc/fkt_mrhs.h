@@ -14,6 +14,7 @@ namespace fkt {
 constexpr int kMrCols = 32;      // columns per group
 constexpr int kMrJobNodes = 4;   // far nodes per 64-lane job of the matrix-core far field
 constexpr int kMrSegJobs = 64;   // far jobs per work unit of the matrix-core far field
+constexpr int kMrGroupBlocks = 16;  // target blocks whose far pairs are packed together
 
 struct DevMrhs {
     int npad = 0;                     // leaves padded to multiples of 32 points
@@ -24,7 +25,7 @@ struct DevMrhs {
     const int* near_pcnt = nullptr;   //   padded point count (multiple of 32)
     const uint64_t* near_mask = nullptr;  // targets of the block that have the leaf in their near set
     void* xt = nullptr;               // [32][npad] weights of the group (bf16 or FP32)
-    void* zf = nullptr;               // [32][n] far field of the group, FP32, tree order
+    void* zf = nullptr;               // [n][32] far field of the group, FP32, tree order
     bool bf16 = false;
     // far field of the group on the matrix cores
     void* mom = nullptr;              // [32][nslots][rank] FP32 moments
@@ -34,13 +35,15 @@ struct DevMrhs {
     void* bhi = nullptr;              // [nslots][ks][2][64] bf16 x 8 MFMA B fragments, high part
     void* blo = nullptr;              //   and low part (m - hi)
     int ks = 0;                       // 32-entry k-steps per node (rank padded to a multiple of 64)
-    const int* job_off = nullptr;     // far jobs per block with up to kMrJobNodes nodes (see Lists)
+    const int* job_off = nullptr;     // far jobs per group of job_group blocks, up to kMrJobNodes nodes each
     const int* job_noff = nullptr;
     const int* job_nodes = nullptr;
     const uint16_t* job_pairs = nullptr;
-    // the far jobs of a block are cut into units of job_seg consecutive jobs,
-    // one wave each (grid nblocks x job_nseg), so the waves of heavy blocks
-    // spread over the machine; units add their sums into zf atomically
+    int job_group = 1;                // blocks per group (pair word: lane | block in group << 6 | node << 10)
+    int ngroups = 0;
+    // the far jobs of a group are cut into units of job_seg consecutive jobs,
+    // one wave each (grid ngroups x job_nseg), so the waves of heavy groups
+    // spread over the machine; every job adds its rows into zf atomically
     int job_seg = kMrSegJobs;
     int job_nseg = 1;
 };

@@ -4,20 +4,21 @@
 // For a (target, far node) pair the multipole-to-target step is a dot
 // product of the pair's basis vector b (entries Y_kh(r^) (s/|r|)^j F_kj(|r|),
 // the same factors as the one-column kernel) with the node's moments, so
-// for 32 columns it is a (pairs x rank) by (rank x 32) product. One wave owns
-// a 64-target block and walks its far jobs (64 pairs of up to kMrJobNodes
-// nodes, lanes grouped by node): each lane generates its pair's basis entries in
-// emission order and writes them, split into bf16 high and low parts, into
-// an LDS chunk laid out as MFMA A fragments; every 32 entries the chunk is
-// multiplied by each job node's moments (bf16 high/low B fragments prepared
-// once per group) with v_mfma_f32_16x16x32_bf16, three products per tile
-// (hi*hi + hi*lo + lo*hi: about 16 bits of mantissa), rows of other nodes
-// masked to zero. Pair rows are then added into the block's per-target LDS
-// sums. The jobs of a block are cut into units of a fixed number of jobs,
-// one wave each, so that blocks with many far nodes do not leave a long tail
-// of single waves at the end of the launch; each unit adds its per-target
-// sums into the far-field buffer (cleared beforehand) with one atomic add per
-// (target, column).
+// for 32 columns it is a (pairs x rank) by (rank x 32) product. The far
+// pairs of a group of consecutive 64-target blocks are packed by node into
+// jobs of 64 pairs of up to kMrJobNodes nodes (lanes grouped by node), so a
+// node's moment fragments, which dominate the memory traffic, serve as many
+// rows as possible. One wave walks a unit of a group's jobs: each lane
+// generates its pair's basis entries in emission order and writes them,
+// split into bf16 high and low parts, into an LDS chunk laid out as MFMA A
+// fragments; every 32 entries the chunk is multiplied by each job node's
+// moments (bf16 high/low B fragments prepared once per group of columns)
+// with v_mfma_f32_16x16x32_bf16, three products per tile (hi*hi + hi*lo +
+// lo*hi: about 16 bits of mantissa), rows of other nodes masked to zero.
+// Each job's rows are then added into the far-field buffer (target-major,
+// cleared beforehand) by atomic adds, 16 consecutive columns per row and
+// instruction. Units hold a fixed number of jobs, so heavy groups spread
+// over the machine instead of leaving a tail at the end of the launch.
 #include <hip/hip_runtime.h>
 
 #include "fkt_kernels.h"
@@ -47,28 +48,24 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
     constexpr int NF = f_off(P, P + 1);
     __shared__ bf8 Ahi[4][kKS][kWave];  // [row tile][k-step in chunk][fragment lane]
     __shared__ bf8 Alo[4][kKS][kWave];
-    __shared__ float Zb[kWave][kMrCols + 1];
-    const int blk = blockIdx.x, lane = threadIdx.x, r16 = lane & 15;
-    const int jb = mr.job_off[blk] + (int)blockIdx.y * mr.job_seg, je = mr.job_off[blk + 1];
+    const int grp = blockIdx.x, lane = threadIdx.x, r16 = lane & 15;
+    const int jb = mr.job_off[grp] + (int)blockIdx.y * mr.job_seg, je = mr.job_off[grp + 1];
     if (jb >= je) return;  // whole-wave exit: this unit has no jobs
-    const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
-    for (int c = 0; c <= kMrCols; ++c) Zb[lane][c] = 0.f;
-    double tx[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
+    const int q0 = grp * mr.job_group;
 
     const int j1 = min(je, jb + mr.job_seg);
     for (int j = jb; j < j1; ++j) {
         const int n0 = mr.job_noff[j], nn = mr.job_noff[j + 1] - n0;
         const unsigned pw = mr.job_pairs[(size_t)j * kWave + lane];
         const bool valid = pw != 0xffffu;
-        const int lt = pw & 63, ni = valid ? (int)(pw >> 6) : 0;
+        const int ni = valid ? (int)(pw >> 10) : 0;
+        const int tgt = valid ? a.blk_begin[q0 + ((pw >> 6) & 15)] + (int)(pw & 63) : -1;
         // lane k < nn holds the slot of job node k, read back with readlane
         const int jslot = mr.job_nodes[n0 + min(lane, nn - 1)];
         const int slot = __shfl(jslot, ni, kWave);
         double txl[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) txl[i] = __shfl(tx[i], lt, kWave);
+        for (int i = 0; i < D; ++i) txl[i] = valid ? a.pts64[(size_t)tgt * D + i] : 0.0;
 
         // geometry and radial factors of this lane's pair (FP64), as in k_m2t
         double r[D], r2 = 0.0;
@@ -192,21 +189,20 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
         };
         static_for<0, RP - R>(pad);
 
-        // pair rows into the block's per-target sums
+        // pair rows into the far field: C layout of a 16 x 16 tile, lane l,
+        // entry q -> row 4 (l / 16) + q, column l % 16
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * rt + 4 * (lane >> 4) + q;
+                const int trow = __shfl(tgt, row, kWave);
+                if (trow >= 0)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = 16 * rt + 4 * (lane >> 4) + q;
-                    const unsigned prow = (unsigned)__shfl((int)pw, row, kWave);
-                    if (prow != 0xffffu) atomicAdd(&Zb[prow & 63][16 * ct + r16], acc[rt][ct][q]);
-                }
+                    for (int ct = 0; ct < 2; ++ct)
+                        unsafeAtomicAdd(zf + (size_t)trow * kMrCols + 16 * ct + r16, acc[rt][ct][q]);
+            }
     }
-    __syncthreads();
-    if (lane < cnt)
-        for (int c = 0; c < kMrCols; ++c) unsafeAtomicAdd(zf + (size_t)c * a.n + tb + lane, Zb[lane][c]);
 }
 
 template <int D, int P = 0>
@@ -216,7 +212,7 @@ bool launch_d(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
         return false;
     } else {
         if (a.p == P) {
-            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(a.nblocks, mr.job_nseg), dim3(kWave), 0, s, a, mr,
+            hipLaunchKernelGGL((k_m2t_mrhs<D, P, FKT_M2T_KIND>), dim3(mr.ngroups, mr.job_nseg), dim3(kWave), 0, s, a, mr,
                                (const bf8*)mr.bhi, (const bf8*)mr.blo, mr.ks, (float*)mr.zf);
             return true;
         }

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevM
                 const int row = rt * 16 + 4 * g + r, col = ct * 16 + r16;
                 if (row < cnt) {
                     const int t = tb + row;
-                    y[a.perm[t] * nrhs + col0 + col] = scale * acc[rt][ct][r] + zf[(size_t)col * a.n + t];
+                    y[a.perm[t] * nrhs + col0 + col] = scale * acc[rt][ct][r] + zf[(size_t)t * kMrCols + col];
                 }
             }
 }
@@ -267,13 +267,10 @@ hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, co
                                nz, zf);
             if (!launch_m2t_mrhs(a, mr, s)) return hipErrorInvalidValue;
         } else {
-            // far field of each column into zf[c] (the gather clears it)
-            for (int c = 0; c < kMrCols; ++c) {
-                DevWork w = wk;
-                w.zacc = zf + (size_t)c * a.n;
-                hipError_t e = launch_far_column(a, w, x, nrhs, col0 + c, 1, s);
-                if (e != hipSuccess) return e;
-            }
+            // no far-node slots: no target has a far field
+            const int64_t nz = (int64_t)a.n * kMrCols;
+            hipLaunchKernelGGL(k_mr_zero, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>((nz + 255) / 256, 8192))),
+                               dim3(256), 0, s, nz, zf);
         }
         hipLaunchKernelGGL((k_mr_gather<TC>), dim3((mr.npad + 255) / 256), dim3(256), 0, s, mr.npad, mr.src, a.perm, x,
                            nrhs, col0, XT);

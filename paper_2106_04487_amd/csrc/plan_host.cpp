@@ -262,6 +262,52 @@ void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J)
     }
 }
 
+void pack_far_jobs_grouped(const Lists& L, int max_nodes, int group, JobSet& J)
+{
+    const int64_t nb = (int64_t)L.blk_begin.size(), ng = (nb + group - 1) / group;
+    J = JobSet();
+    J.max_nodes = max_nodes;
+    J.job_off.assign(ng + 1, 0);
+    J.job_noff.assign(1, 0);
+    struct Ent {
+        int32_t slot, bg, e;
+    };
+    std::vector<Ent> ent;
+    for (int64_t g = 0; g < ng; ++g) {
+        ent.clear();
+        const int64_t q0 = g * group, q1 = std::min<int64_t>(nb, q0 + group);
+        for (int64_t q = q0; q < q1; ++q)
+            for (int e = L.far_off[q]; e < L.far_off[q + 1]; ++e) ent.push_back({L.far_slot[e], (int32_t)(q - q0), e});
+        std::stable_sort(ent.begin(), ent.end(), [](const Ent& u, const Ent& v) { return u.slot < v.slot; });
+        int in_job = kBlock, nodes_in_job = max_nodes;  // forces a new job
+        int32_t open_slot = -1;                          // node whose lanes the current job is filling
+        for (const Ent& en : ent) {
+            uint64_t m = L.far_mask[en.e];
+            while (m) {
+                if (in_job == kBlock || (open_slot != en.slot && nodes_in_job == max_nodes)) {
+                    J.job_pairs.resize(J.job_pairs.size() + kBlock, (uint16_t)0xffff);
+                    J.job_noff.push_back(J.job_noff.back());
+                    in_job = 0;
+                    nodes_in_job = 0;
+                    open_slot = -1;
+                }
+                if (open_slot != en.slot) {
+                    J.job_nodes.push_back(en.slot);
+                    J.job_noff.back() += 1;
+                    ++nodes_in_job;
+                    open_slot = en.slot;
+                }
+                const int lane = __builtin_ctzll(m);
+                m &= m - 1;
+                J.job_pairs[J.job_pairs.size() - kBlock + in_job] =
+                    (uint16_t)(lane | (en.bg << 6) | ((nodes_in_job - 1) << 10));
+                ++in_job;
+            }
+        }
+        J.job_off[g + 1] = (int32_t)(J.job_noff.size() - 1);
+    }
+}
+
 void pack_node_jobs(const Lists& L, std::vector<int32_t>& job_slot, std::vector<int32_t>& job_tgt)
 {
     const int64_t nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
@@ -677,6 +723,44 @@ bool check_lists(const Tree& T, const Lists& L, std::string& err)
     if (L.red_off.size() != L.red_slot.size() + 1 || L.red_off.back() != L.npartials) return bad("partial lists", 0);
     for (size_t r = 0; r < L.red_slot.size(); ++r)
         if (L.red_slot[r] < 0 || L.red_slot[r] >= ns || L.red_off[r + 1] < L.red_off[r]) return bad("partial list", (int64_t)r);
+    return true;
+}
+
+bool check_jobs_grouped(const Lists& L, const JobSet& J, int group, std::string& err)
+{
+    const int64_t nb = (int64_t)L.blk_begin.size(), ns = (int64_t)L.slot_node.size();
+    const int64_t ng = (nb + group - 1) / group, njobs = (int64_t)J.job_noff.size() - 1;
+    auto bad = [&](const std::string& what, int64_t i) {
+        err = "plan check: " + what + " at " + std::to_string(i);
+        return false;
+    };
+    if (group < 1 || group > 16 || J.max_nodes < 1 || J.max_nodes > 4) return bad("job grouping", group);
+    if ((int64_t)J.job_off.size() != ng + 1 || J.job_off[0] != 0 || J.job_off[ng] != njobs)
+        return bad("grouped job offsets", 0);
+    if (J.job_noff[0] != 0 || J.job_noff[njobs] != (int64_t)J.job_nodes.size() ||
+        (int64_t)J.job_pairs.size() != njobs * kBlock)
+        return bad("grouped job arrays", 0);
+    for (int64_t g = 0; g < ng; ++g) {
+        if (J.job_off[g + 1] < J.job_off[g]) return bad("grouped job offsets", g);
+        for (int64_t j = J.job_off[g]; j < J.job_off[g + 1]; ++j) {
+            const int nn = J.job_noff[j + 1] - J.job_noff[j];
+            if (nn < 1 || nn > J.max_nodes) return bad("grouped job node count", j);
+            for (int k = 0; k < nn; ++k) {
+                const int32_t sl = J.job_nodes[J.job_noff[j] + k];
+                if (sl < 0 || sl >= ns) return bad("grouped job node slot", j);
+            }
+            int prev = 0;
+            for (int lane = 0; lane < kBlock; ++lane) {
+                const uint16_t pw = J.job_pairs[(size_t)j * kBlock + lane];
+                if (pw == 0xffffu) continue;
+                const int64_t q = g * group + ((pw >> 6) & 15);
+                const int node = pw >> 10;
+                if (((pw >> 6) & 15) >= group || q >= nb || (pw & 63) >= L.blk_count[q] || node >= nn || node < prev)
+                    return bad("grouped job pair", j);
+                prev = node;  // lanes grouped by node, in node order
+            }
+        }
+    }
     return true;
 }
 
