@@ -98,11 +98,11 @@ void build_forest(const double* X, const int64_t* offsets, int ninst, int d, int
 void build_lists(const Tree& T, double theta, int max_job_nodes, Lists& L, fkt_plan_stats& st);
 // pack L's far lists (far_off / far_slot / far_mask) into jobs
 void pack_far_jobs(const Lists& L, int max_nodes, JobSet& J);
-// far jobs over groups of `group` consecutive blocks (group <= 16): a far
+// far jobs over groups of `group` consecutive blocks (group <= 64): a far
 // node's pairs from all blocks of a group are packed together, so a job's
 // moment fragments serve more rows. job_off has one entry per group; a pair
-// word is lane | (block - first block of the group) << 6 | node index << 10
-// (0xffff: empty lane).
+// word is lane | (block - first block of the group) << 6 | node index << 12
+// (0xffff: empty lane; max_nodes <= 4).
 void pack_far_jobs_grouped(const Lists& L, int max_nodes, int group, JobSet& J);
 bool check_jobs_grouped(const Lists& L, const JobSet& J, int group, std::string& err);
 // node-major far jobs: for every far-node slot, its far targets (tree

@@ -14,7 +14,7 @@ namespace fkt {
 constexpr int kMrCols = 32;      // columns per group
 constexpr int kMrJobNodes = 4;   // far nodes per 64-lane job of the matrix-core far field
 constexpr int kMrSegJobs = 64;   // far jobs per work unit of the matrix-core far field
-constexpr int kMrGroupBlocks = 16;  // target blocks whose far pairs are packed together
+constexpr int kMrGroupBlocks = 64;  // target blocks whose far pairs are packed together (at most 64)
 
 struct DevMrhs {
     int npad = 0;                     // leaves padded to multiples of 32 points
@@ -39,7 +39,7 @@ struct DevMrhs {
     const int* job_noff = nullptr;
     const int* job_nodes = nullptr;
     const uint16_t* job_pairs = nullptr;
-    int job_group = 1;                // blocks per group (pair word: lane | block in group << 6 | node << 10)
+    int job_group = 1;                // blocks per group (pair word: lane | block in group << 6 | node << 12)
     int ngroups = 0;
     // the far jobs of a group are cut into units of job_seg consecutive jobs,
     // one wave each (grid ngroups x job_nseg), so the waves of heavy groups

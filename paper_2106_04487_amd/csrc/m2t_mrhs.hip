@@ -58,8 +58,8 @@ __global__ __launch_bounds__(kWave) void k_m2t_mrhs(const DevPlan a, const DevMr
         const int n0 = mr.job_noff[j], nn = mr.job_noff[j + 1] - n0;
         const unsigned pw = mr.job_pairs[(size_t)j * kWave + lane];
         const bool valid = pw != 0xffffu;
-        const int ni = valid ? (int)(pw >> 10) : 0;
-        const int tgt = valid ? a.blk_begin[q0 + ((pw >> 6) & 15)] + (int)(pw & 63) : -1;
+        const int ni = valid ? (int)(pw >> 12) : 0;
+        const int tgt = valid ? a.blk_begin[q0 + ((pw >> 6) & 63)] + (int)(pw & 63) : -1;
         // lane k < nn holds the slot of job node k, read back with readlane
         const int jslot = mr.job_nodes[n0 + min(lane, nn - 1)];
         const int slot = __shfl(jslot, ni, kWave);

@@ -300,7 +300,7 @@ void pack_far_jobs_grouped(const Lists& L, int max_nodes, int group, JobSet& J)
                 const int lane = __builtin_ctzll(m);
                 m &= m - 1;
                 J.job_pairs[J.job_pairs.size() - kBlock + in_job] =
-                    (uint16_t)(lane | (en.bg << 6) | ((nodes_in_job - 1) << 10));
+                    (uint16_t)(lane | (en.bg << 6) | ((nodes_in_job - 1) << 12));
                 ++in_job;
             }
         }
@@ -734,7 +734,7 @@ bool check_jobs_grouped(const Lists& L, const JobSet& J, int group, std::string&
         err = "plan check: " + what + " at " + std::to_string(i);
         return false;
     };
-    if (group < 1 || group > 16 || J.max_nodes < 1 || J.max_nodes > 4) return bad("job grouping", group);
+    if (group < 1 || group > 64 || J.max_nodes < 1 || J.max_nodes > 4) return bad("job grouping", group);
     if ((int64_t)J.job_off.size() != ng + 1 || J.job_off[0] != 0 || J.job_off[ng] != njobs)
         return bad("grouped job offsets", 0);
     if (J.job_noff[0] != 0 || J.job_noff[njobs] != (int64_t)J.job_nodes.size() ||
@@ -753,9 +753,9 @@ bool check_jobs_grouped(const Lists& L, const JobSet& J, int group, std::string&
             for (int lane = 0; lane < kBlock; ++lane) {
                 const uint16_t pw = J.job_pairs[(size_t)j * kBlock + lane];
                 if (pw == 0xffffu) continue;
-                const int64_t q = g * group + ((pw >> 6) & 15);
-                const int node = pw >> 10;
-                if (((pw >> 6) & 15) >= group || q >= nb || (pw & 63) >= L.blk_count[q] || node >= nn || node < prev)
+                const int bg = (pw >> 6) & 63, node = pw >> 12;
+                const int64_t q = g * group + bg;
+                if (bg >= group || q >= nb || (pw & 63) >= L.blk_count[q] || node >= nn || node < prev)
                     return bad("grouped job pair", j);
                 prev = node;  // lanes grouped by node, in node order
             }
