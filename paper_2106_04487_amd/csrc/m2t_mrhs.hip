@@ -160,16 +160,31 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3, 3))) v
         };
         // entry idx of this lane's row goes to fragment lane (lane % 16) + 16 g,
         // element q, of row tile lane / 16, with g = (idx % 32) / 8, q = idx % 8;
-        // eight consecutive entries are collected and stored as one vector
-        bf8 hv, lv;
+        // eight consecutive entries are collected and stored as one vector.
+        // Entries are converted two at a time: the high parts of a pair by one
+        // packed conversion (round to nearest even), unpacked to FP32 by a
+        // shift and a mask, then the low parts (value minus high part) by a
+        // second packed conversion.
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        u4 hw, lw;
+        float ev = 0.f;
         auto put = [&](int idx, float bv) {
             const int c = idx % kKC, ks = c / 32, g = (c % 32) / 8, q = c % 8;
-            const __bf16 h = (__bf16)bv;
-            hv[q] = h;
-            lv[q] = (__bf16)(bv - (float)h);
+            if (q % 2 == 0) {
+                ev = bv;
+            } else {
+                const bf2 hp = __builtin_convertvector(f2{ev, bv}, bf2);
+                const unsigned hu = __builtin_bit_cast(unsigned, hp);
+                const float h0 = __builtin_bit_cast(float, hu << 16), h1 = __builtin_bit_cast(float, hu & 0xffff0000u);
+                const bf2 lp = __builtin_convertvector(f2{ev - h0, bv - h1}, bf2);
+                hw[q / 2] = hu;
+                lw[q / 2] = __builtin_bit_cast(unsigned, lp);
+            }
             if (q == 7) {
-                Ahi[lane >> 4][ks][r16 + 16 * g] = hv;
-                Alo[lane >> 4][ks][r16 + 16 * g] = lv;
+                Ahi[lane >> 4][ks][r16 + 16 * g] = __builtin_bit_cast(bf8, hw);
+                Alo[lane >> 4][ks][r16 + 16 * g] = __builtin_bit_cast(bf8, lw);
             }
             if (c == kKC - 1) flush(idx - (kKC - 1));
         };
