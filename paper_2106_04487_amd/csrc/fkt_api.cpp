@@ -386,6 +386,15 @@ static fkt_status upload_plan(fkt_plan_t P)
         FKT_UP2(pts, P->mr.pts);
         FKT_UP2(src, P->mr.src);
         FKT_UP2(L.near_off, P->mr.near_off);
+        {
+            int64_t maxe = 0;
+            for (size_t b = 0; b + 1 < L.near_off.size(); ++b)
+                maxe = std::max<int64_t>(maxe, (int64_t)L.near_off[b + 1] - L.near_off[b]);
+            int64_t seg = fkt::kMrSegNear;
+            if ((maxe + seg - 1) / seg > 65535) seg = (maxe + 65534) / 65535;  // grid y limit
+            P->mr.near_seg = (int)seg;
+            P->mr.near_nseg = (int)std::max<int64_t>(1, (maxe + seg - 1) / seg);
+        }
         FKT_UP2(pb, P->mr.near_pbeg);
         FKT_UP2(pc, P->mr.near_pcnt);
         FKT_UP2(L.near_mask, P->mr.near_mask);

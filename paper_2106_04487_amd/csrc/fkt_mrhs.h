@@ -14,6 +14,7 @@ namespace fkt {
 constexpr int kMrCols = 32;      // columns per group
 constexpr int kMrJobNodes = 4;   // far nodes per 64-lane job of the matrix-core far field
 constexpr int kMrSegJobs = 64;   // far jobs per work unit of the matrix-core far field
+constexpr int kMrSegNear = 32;   // near leaves per work unit of the matrix-core near field
 constexpr int kMrGroupBlocks = 64;  // target blocks whose far pairs are packed together (at most 64)
 
 struct DevMrhs {
@@ -24,6 +25,11 @@ struct DevMrhs {
     const int* near_pbeg = nullptr;   //   padded first point of the leaf (multiple of 32)
     const int* near_pcnt = nullptr;   //   padded point count (multiple of 32)
     const uint64_t* near_mask = nullptr;  // targets of the block that have the leaf in their near set
+    // a block's near leaves are cut into units of near_seg leaves, one wave
+    // each (grid nblocks x near_nseg); units add into zf, which is then
+    // written to the output
+    int near_seg = kMrSegNear;
+    int near_nseg = 1;
     void* xt = nullptr;               // [32][npad] weights of the group (bf16 or FP32)
     void* zf = nullptr;               // [n][32] far field of the group, FP32, tree order
     bool bf16 = false;

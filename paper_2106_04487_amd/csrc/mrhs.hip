@@ -2,8 +2,10 @@
 // the matrix cores (this file); the moments (s2m_mrhs.hip) and the far-field
 // evaluation (m2t_mrhs.hip) of the 32 columns on the matrix cores too.
 //
-// Near field (Algorithm 1, near_mat, for 32 columns at once): one wave owns
-// a 64-target block and walks the union of its targets' near leaves. For
+// Near field (Algorithm 1, near_mat, for 32 columns at once): one wave takes
+// a 64-target block and up to 32 leaves of the union of its targets' near
+// leaves (a block's leaves are cut into such units so that heavy blocks do
+// not leave a tail at the end of the launch). For
 // every 32 points of a leaf each lane evaluates 32 kernel values (4 row
 // tiles of 16 targets x 8 points; rows whose target does not have the leaf
 // in its own near set get 0), and the 64 x 32 block of K times the 32 x 32
@@ -12,8 +14,9 @@
 // v_mfma_f32_16x16x4f32 (FP32 throughout). Lane l of a 16 x 16 tile holds
 // row l % 16 and points 8 (l / 16) .. + 7 of the 32, for both variants (the
 // points are a reduction index, so the order within a step is free). The
-// block's 64 x 32 result is final: the epilogue adds the far field and
-// writes y in the caller's order, once per (target, column); no atomics.
+// unit's 64 x 32 result is added atomically into the group's far-field
+// buffer (target-major, 16 consecutive columns per row and instruction),
+// which a last kernel writes to y in the caller's order.
 //
 // Leaves are laid out padded to multiples of 32 points (pad weight 0,
 // coordinates of the leaf's first point), so every step loads aligned runs.
@@ -105,13 +108,16 @@ bool launch_m2t_mrhs(const DevPlan& a, const DevMrhs& mr, hipStream_t s)
 
 template <int D, int KIND, typename TC>
 __global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevMrhs mr, const TC* __restrict__ XT,
-                                                     const float* __restrict__ zf, float* __restrict__ y, int nrhs,
-                                                     int col0, float c0, float c1, float scale)
+                                                     float* __restrict__ zf, float c0, float c1, float scale)
 {
     using NK = NearKernel<KIND, float>;
     constexpr bool kBf16 = std::is_same<TC, __bf16>::value;
     const int blk = blockIdx.x, lane = threadIdx.x;
     const int r16 = lane & 15, g = lane >> 4;
+    // this unit's near leaves of the block
+    const int e0 = mr.near_off[blk] + (int)blockIdx.y * mr.near_seg;
+    const int e1 = min(mr.near_off[blk + 1], e0 + mr.near_seg);
+    if (e0 >= e1) return;  // whole-wave exit
     const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
     float tx[4][D];
 #pragma unroll
@@ -127,7 +133,6 @@ __global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevM
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const int e0 = mr.near_off[blk], e1 = mr.near_off[blk + 1];
     for (int e = e0; e < e1; ++e) {
         const uint64_t mask = mr.near_mask[e];
         float flag[4];
@@ -206,24 +211,32 @@ __global__ __launch_bounds__(kWave) void k_near_mrhs(const DevPlan a, const DevM
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rt * 16 + 4 * g + r, col = ct * 16 + r16;
-                if (row < cnt) {
-                    const int t = tb + row;
-                    y[a.perm[t] * nrhs + col0 + col] = scale * acc[rt][ct][r] + zf[(size_t)t * kMrCols + col];
-                }
+                if (row < cnt) unsafeAtomicAdd(zf + (size_t)(tb + row) * kMrCols + col, scale * acc[rt][ct][r]);
             }
 }
 
+// y[perm[t]][col0 + c] = zf[t][c]: near plus far field of the group, to the
+// caller's order
+__global__ __launch_bounds__(256) void k_mr_out(int n, const int64_t* __restrict__ perm, const float* __restrict__ zf,
+                                                float* __restrict__ y, int nrhs, int col0)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)n * kMrCols) return;
+    const int64_t t = g / kMrCols;
+    const int c = (int)(g % kMrCols);
+    y[perm[t] * nrhs + col0 + c] = zf[g];
+}
+
 template <int D, typename TC>
-bool launch_near_mrhs_d(const DevPlan& a, const DevMrhs& mr, const TC* XT, const float* zf, float* y, int nrhs,
-                        int col0, hipStream_t s)
+bool launch_near_mrhs_d(const DevPlan& a, const DevMrhs& mr, const TC* XT, float* zf, hipStream_t s)
 {
     float c0, c1;
     near_consts_f32(a, c0, c1);
     const float scale = (float)a.var;
     switch (a.kind) {
 #define FKT_MR_CASE(K) \
-    case K: hipLaunchKernelGGL((k_near_mrhs<D, K, TC>), dim3(a.nblocks), dim3(kWave), 0, s, a, mr, XT, zf, y, nrhs, \
-                               col0, c0, c1, scale); return true;
+    case K: hipLaunchKernelGGL((k_near_mrhs<D, K, TC>), dim3(a.nblocks, mr.near_nseg), dim3(kWave), 0, s, a, mr, XT, \
+                               zf, c0, c1, scale); return true;
         FKT_MR_CASE(FKT_GAUSSIAN)
         FKT_MR_CASE(FKT_EXPONENTIAL)
         FKT_MR_CASE(FKT_MATERN32)
@@ -276,12 +289,14 @@ hipError_t mvm_mrhs_t(const DevPlan& a, const DevWork& wk, const DevMrhs& mr, co
                            nrhs, col0, XT);
         bool ok = false;
         switch (a.d) {
-        case 3: ok = launch_near_mrhs_d<3, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
-        case 4: ok = launch_near_mrhs_d<4, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
-        case 5: ok = launch_near_mrhs_d<5, TC>(a, mr, XT, zf, y, nrhs, col0, s); break;
+        case 3: ok = launch_near_mrhs_d<3, TC>(a, mr, XT, zf, s); break;
+        case 4: ok = launch_near_mrhs_d<4, TC>(a, mr, XT, zf, s); break;
+        case 5: ok = launch_near_mrhs_d<5, TC>(a, mr, XT, zf, s); break;
         default: break;
         }
         if (!ok) return hipErrorInvalidValue;
+        const int64_t ny = (int64_t)a.n * kMrCols;
+        hipLaunchKernelGGL(k_mr_out, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s, a.n, a.perm, zf, y, nrhs, col0);
     }
     return hipGetLastError();
 }
