@@ -148,10 +148,32 @@ __global__ __launch_bounds__(kT) void k_gemv_t_part(int64_t n, int k, int64_t ro
 {
     const int64_t i0 = (int64_t)blockIdx.x * rows, i1 = min(n, i0 + rows);
     for (int j = threadIdx.x; j < k; j += kT) {
-        double acc = 0.0;
-        for (int64_t i = i0; i < i1; ++i) acc = fma(G[i * k + j], h[i] * sv[i], acc);
-        part[(int64_t)blockIdx.x * k + j] = acc;
+        // four independent accumulators keep four row loads in flight
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t i = i0;
+        for (; i + 3 < i1; i += 4) {
+            a0 = fma(G[i * k + j], h[i] * sv[i], a0);
+            a1 = fma(G[(i + 1) * k + j], h[i + 1] * sv[i + 1], a1);
+            a2 = fma(G[(i + 2) * k + j], h[i + 2] * sv[i + 2], a2);
+            a3 = fma(G[(i + 3) * k + j], h[i + 3] * sv[i + 3], a3);
+        }
+        for (; i < i1; ++i) a0 = fma(G[i * k + j], h[i] * sv[i], a0);
+        part[(int64_t)j * gridDim.x + blockIdx.x] = (a0 + a1) + (a2 + a3);
     }
+}
+
+// u[j] = sum_z part[j][z]: one wave per j, lanes over the chunks
+__global__ __launch_bounds__(kT) void k_sum_chunks(int nz, int k, const double* __restrict__ part,
+                                                   double* __restrict__ u)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+    if (j >= k) return;
+    double s = 0.0;
+    for (int z = lane; z < nz; z += 64) s += part[(int64_t)j * nz + z];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) u[j] = s;
 }
 
 // out[i] = sum_z part[z][i] (+1 on the diagonal of a k x k matrix when eye_k > 0)
@@ -235,7 +257,7 @@ hipError_t gemv_t_weighted(int64_t n, int k, const double* G, const double* h, c
 {
     const int64_t rows = (n + nchunk - 1) / nchunk;
     hipLaunchKernelGGL(k_gemv_t_part, dim3((unsigned)nchunk), dim3(kT), 0, s, n, k, rows, G, h, sv, part);
-    hipLaunchKernelGGL(k_sum_part64, dim3(grid_of(k)), dim3(kT), 0, s, nchunk, (int64_t)k, part, u, 0);
+    hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((k + 3) / 4)), dim3(kT), 0, s, nchunk, k, part, u);
     return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ hipError_t gemm64_batched(bool ta, bool tb, const Gemm64* desc, int nbatch, int 
 hipError_t kernel_columns(const DevPlan& a, const int* cols, int k, double* out, hipStream_t s);
 
 // u = G^T (h .* s) for G [n][k] row-major: per-chunk partial sums of
-// nchunk row chunks, then their sum (part: nchunk x k doubles).
+// nchunk row chunks (part: k x nchunk doubles, column-major by chunk), then
+// their sum, one wave per entry of u.
 hipError_t gemv_t_weighted(int64_t n, int k, const double* G, const double* h, const double* sv, double* part,
                            int nchunk, double* u, hipStream_t s);
 // w = Cinv u (k x k, row-major)
@@ -41,7 +42,7 @@ hipError_t gemv_sub(int64_t n, int k, const double* G, const double* w, const do
 // out[z][i] summed over z < nz into C, plus the identity when add_eye (k x k)
 hipError_t sum_partials64(int nz, int64_t len, const double* part, double* out, int add_eye_k, hipStream_t s);
 
-constexpr int kCoarseChunks = 256;  // row chunks of gemv_t_weighted
+constexpr int kCoarseChunks = 1024;  // row chunks of gemv_t_weighted (4 waves each)
 constexpr int kCoarseMaxRank = 4096;
 
 // Host dense SPD helpers (row-major k x k, threads over rows/columns).
