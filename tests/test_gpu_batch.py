@@ -46,6 +46,29 @@ def test_batch_mvm_matches_oracle_per_instance(F, prec, tol):
     plan.close()
 
 
+def test_batch_many_rhs_matches_oracle_per_instance(F):
+    """32 columns on the matrix cores over a forest: the far pairs of groups
+    of consecutive target blocks are packed together and the near and far
+    units add into one buffer, so groups and units span instance borders;
+    every instance must still match the oracle run on it alone (FP32 MFMA
+    near field, bf16 x3 far field: the FP32 bar)."""
+    import torch
+    sizes = [1500, 1, 64, 3000, 0, 777, 2500]
+    X, off = W.batched_instances(sizes, 3, 902)
+    x = W.normal_rhs(X.shape[0], 32, 903)
+    leaf, p, theta = 32, 5, 0.5
+    plan = F.fkt_plan_batch((X, off), "ratquad", leaf, p, theta=theta, prec="f32", mrhs="f32", **KW)
+    y = F.fkt_mvm(plan, torch.as_tensor(x, dtype=torch.float32, device="cuda")).double().cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    zref = _oracle_batch(X, off, x, leaf, p, theta)
+    for i in range(len(sizes)):
+        a, b = off[i], off[i + 1]
+        if b > a:
+            e = np.linalg.norm(y[a:b] - zref[a:b]) / np.linalg.norm(zref[a:b])
+            assert e <= 1e-5, (i, sizes[i], e)
+
+
 @pytest.mark.parametrize("prec,mrhs,nrhs", [("f64", None, 4), ("f32", None, 4), ("f32", "bf16", 32)])
 def test_graph_replays_match_eager(F, prec, mrhs, nrhs):
     import torch
