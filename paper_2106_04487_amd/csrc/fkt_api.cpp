@@ -280,6 +280,17 @@ static fkt_status upload_plan(fkt_plan_t P)
     FKT_UP(L.job_nodes, a.job_nodes);
     FKT_UP(L.job_pairs, a.job_pairs);
     {
+        // block-major jobs in units of kFarSegJobs, one wave each, so that
+        // blocks with many far jobs spread over the machine
+        int64_t maxj = 0;
+        for (size_t b = 0; b + 1 < L.job_off.size(); ++b)
+            maxj = std::max<int64_t>(maxj, (int64_t)L.job_off[b + 1] - L.job_off[b]);
+        int64_t seg = fkt::kFarSegJobs;
+        if ((maxj + seg - 1) / seg > 65535) seg = (maxj + 65534) / 65535;  // grid y limit
+        a.job_seg = (int)seg;
+        a.job_nseg = (int)std::max<int64_t>(1, (maxj + seg - 1) / seg);
+    }
+    {
         // node-major far jobs (far_mode 2; far_mode 0 except FP32 plans of
         // rank above 1000, where the block-major kernel was measured faster)
         const bool node_major = P->opt.far_mode == 2 || P->comp_keep > 0 || P->opt.fuse != 0 ||

@@ -28,6 +28,7 @@ struct DevPlan {
     const int* job_noff;          // [njobs + 1] into job_nodes
     const int* job_nodes;         // far-node slots of each job
     const uint16_t* job_pairs;    // [njobs][64] target lane | job node index << 6
+    int job_seg, job_nseg;        // block-major jobs per work unit, units per block (grid nblocks x job_nseg)
     int nnjobs;                   // node-major far field (0: block-major jobs above)
     const int* nj_slot;           // [nnjobs] far-node slot of each job
     const int* nj_tgt;            // [nnjobs][64] target tree positions (-1: empty lane)
@@ -64,6 +65,7 @@ struct DevPlan {
 // columns together (shared kernel values, harmonics and radial functions)
 // on plans with the node-major far field; others run column by column.
 constexpr int kMvmCols = 4;
+constexpr int kFarSegJobs = 32;  // block-major far jobs per work unit
 
 // Rows kept per degree by the compressed kernels built for (kind, d), 0 for
 // none: 1/r and e^(-r/l) in d = 3 (the paper's Table "ranks": R_k = 1 and 2).

@@ -604,13 +604,15 @@ __device__ __forceinline__ void far_pair(const DevPlan& a, const double (&r)[D],
     static_for<0, P + 1>(radial_k);
 }
 
-// One wave per 64-target block. The block's (target, far node) pairs come
-// packed in jobs of 64 lanes, one pair per lane, with at most MAXN nodes per
-// job; a job's node moments and centres are staged in LDS (two buffers: the
-// next job is fetched into registers while the current one computes), and
-// each lane adds its pair's value to its target's LDS accumulator. The block
-// then adds its 64 sums to zacc (the near field, possibly running
-// concurrently, adds to the same accumulators).
+// One wave per 64-target block and unit of up to job_seg of its jobs (units
+// spread the heavy blocks over the machine). The block's (target, far node)
+// pairs come packed in jobs of 64 lanes, one pair per lane, with at most
+// MAXN nodes per job; a job's node moments and centres are staged in LDS
+// (two buffers: the next job is fetched into registers while the current
+// one computes), and each lane adds its pair's value to its target's LDS
+// accumulator. The unit then adds its 64 sums to zacc (other units of the
+// block and the near field, possibly running concurrently, add to the same
+// accumulators).
 template <int D, int P, int KIND, typename T>
 __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restrict__ mom, T* __restrict__ zacc)
 {
@@ -625,6 +627,10 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
     __shared__ double zblk[kWave];
     const int blk = blockIdx.x;
     const int lane = threadIdx.x;
+    // this unit's jobs of the block
+    const int j0 = a.job_off[blk] + (int)blockIdx.y * a.job_seg;
+    const int j1 = min(a.job_off[blk + 1], j0 + a.job_seg);
+    if (j0 >= j1) return;  // whole-wave exit
     const int tb = a.blk_begin[blk], cnt = a.blk_count[blk];
     zblk[lane] = 0.0;
     // each lane holds its own target; pairs fetch it by cross-lane shuffle
@@ -632,7 +638,6 @@ __global__ __launch_bounds__(kWave) void k_m2t(const DevPlan a, const T* __restr
 #pragma unroll
     for (int i = 0; i < D; ++i) tx[i] = a.pts64[(size_t)(tb + (lane < cnt ? lane : 0)) * D + i];
 
-    const int j0 = a.job_off[blk], j1 = a.job_off[blk + 1];
     T pre[PF];
     double pgeo = 0.0;
     // Fetch job j's node moments and centres into registers: lane i of row q

@@ -36,7 +36,7 @@ bool m2t_dpn(const DevPlan& a, const DevWork& wk, hipStream_t s)
         return true;
     }
     if constexpr (NCOL == 1) {
-        hipLaunchKernelGGL((k_m2t<D, P, FKT_M2T_KIND, T>), dim3(a.nblocks), dim3(kWave), 0, s, a, (const T*)wk.mom,
+        hipLaunchKernelGGL((k_m2t<D, P, FKT_M2T_KIND, T>), dim3(a.nblocks, a.job_nseg), dim3(kWave), 0, s, a, (const T*)wk.mom,
                            (T*)wk.zacc);
         return true;
     }
